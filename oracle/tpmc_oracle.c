@@ -1,0 +1,464 @@
+/*
+ * tpmc_oracle.c -- FP64 CPU oracle of the TPMC drag hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY (see tpmc_oracle.h).  Plain, slow and written for a
+ * reader checking it against the paper: every inverse CDF is solved by pure
+ * bisection, every ray is tested against every triangle, every sum is a
+ * Neumaier-compensated FP64 sum.  Nothing here is shared with the GPU path.
+ *
+ * Paper: J. B. Parham and L. A. Barba, "Finding the Force -- Consistent
+ * Particle Seeding for Satellite Aerodynamics", AIAA.
+ */
+#include "tpmc_oracle.h"
+
+#include <math.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_SQRTPI 1.77245385090551602730
+
+/* ------------------------------------------------------------------------- */
+/* Philox4x32-10, from its published definition (Salmon et al., SC'11):       */
+/* ten rounds of two 32x32->64 multiplies, the key bumped by the Weyl         */
+/* constants between rounds.                                                  */
+/* ------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Four words of the stream of particle pid at step `step`.
+ * Counter = (pid lo, pid hi, step, 0), key = (seed lo, seed hi). */
+static void orc_stream(uint64_t seed, uint64_t pid, uint32_t step, uint32_t out[4]) {
+  uint32_t ctr[4] = {(uint32_t)pid, (uint32_t)(pid >> 32), step, 0u};
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  orc_philox4x32_10(ctr, key, out);
+}
+
+/* Uniform variates in (0, 1), exact in their type.
+ * Seeding (FP64 path): u = (k + 1/2) 2^-32.  Reflection (FP32 path):
+ * u = (floor(k / 2^9) + 1/2) 2^-23. */
+static double u64_of(uint32_t k) { return ((double)k + 0.5) * 0x1p-32; }
+static double u32_of(uint32_t k) { return ((double)(k >> 9) + 0.5) * 0x1p-23; }
+
+/* ------------------------------------------------------------------------- */
+/* Compensated summation (Neumaier's improvement of Kahan summation).         */
+/* ------------------------------------------------------------------------- */
+static void nsum(double* s, double* c, double x) {
+  double t = *s + x;
+  if (fabs(*s) >= fabs(x)) *c += (*s - t) + x;
+  else *c += (x - t) + *s;
+  *s = t;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Seeding model, Sec. III.A.1-2.                                              */
+/* ------------------------------------------------------------------------- */
+
+/* chi(s) = e^{-s^2} + sqrt(pi) s (1 + erf s): the bracket of the per-area
+ * inward number flux (eq. integration) and the normaliser of eq. vel_dist1.
+ * 1 + erf s is written erfc(-s) so that it stays accurate for s < 0. */
+double orc_chi(double s) { return exp(-s * s) + ORC_SQRTPI * s * erfc(-s); }
+
+/* Z(S) = e^{-S^2} + sqrt(pi)(S + 1/(2S)) erf S: the denominator of g(phi|S)
+ * (Sec. III.A.1).  Its S -> 0 limit is 2. */
+double orc_Z(double S) {
+  if (S < 1e-8) return 2.0;
+  return exp(-S * S) + ORC_SQRTPI * (S + 0.5 / S) * erf(S);
+}
+
+/* Gamma / (n c_mp) = [sqrt(pi) e^{-S^2} + (pi/(2S) + pi S) erf S] r^2, the
+ * number flux into a sphere of radius r (Sec. III.A.1, final Gamma result).
+ * It equals sqrt(pi) r^2 Z(S); at S = 0 it is 2 sqrt(pi) r^2. */
+double orc_gamma_hat(double S, double r) {
+  if (S < 1e-8) return 2.0 * ORC_SQRTPI * r * r;
+  return (ORC_SQRTPI * exp(-S * S) + (ORC_PI / (2.0 * S) + ORC_PI * S) * erf(S)) * r * r;
+}
+
+/* Unnormalised CDF of mu = sin(phi) under g(phi|S) (Sec. III.A.1):
+ * with d(mu) = cos(phi) d(phi), the density of mu on [-1, 1] is chi(S mu) / Z(S),
+ * so G(t) = integral_{-1}^{t} chi(S mu) d(mu) and G(1) = Z(S).  Antiderivative:
+ *   H(t) = sqrt(pi)/(4S) erf(St) + sqrt(pi) S t^2 (1 + erf St) / 2 + t e^{-S^2 t^2} / 2,
+ * evaluated as G(t) = H(t) - H(-1) term by term so that no term cancels. */
+static double orc_G_mu(double t, double S) {
+  double St = S * t;
+  double e_diff; /* erf(S t) - erf(-S) */
+  if (t < 0.0 && -St > 1.0) e_diff = erfc(-St) - erfc(S);
+  else e_diff = erf(St) + erf(S);
+  double term1 = ORC_SQRTPI / (4.0 * S) * e_diff;
+  double term2 = 0.5 * ORC_SQRTPI * S * (t * t * erfc(-St) - erfc(S));
+  double term3 = 0.5 * (t * exp(-St * St) + exp(-S * S));
+  return term1 + term2 + term3;
+}
+
+double orc_F_mu(double t, double S) {
+  if (t <= -1.0) return 0.0;
+  if (t >= 1.0) return 1.0;
+  if (S < 1e-8) return 0.5 * (t + 1.0); /* S -> 0: g -> cos(phi)/2, mu uniform */
+  return orc_G_mu(t, S) / orc_Z(S);
+}
+
+/* Inverse of F_mu by bisection on [-1, 1] until the bracket stops shrinking. */
+double orc_inv_F_mu(double u, double S) {
+  if (S < 1e-8) return 2.0 * u - 1.0;
+  double target = u * orc_Z(S);
+  double lo = -1.0, hi = 1.0;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (orc_G_mu(mid, S) < target) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* CDF of the inward normal speed x = v_n / c_mp >= 0 of eq. vel_dist1, read as
+ * p(x | s) = 2 x e^{-(x - s)^2} / chi(s) (the printed "2 v_i" taken as 2x in
+ * units of c_mp, the only reading that integrates to 1):
+ *   F_n(x|s) = [e^{-s^2} - e^{-(x-s)^2} + sqrt(pi) s (erf(x-s) + erf s)] / chi(s),
+ * with erf(x-s) + erf(s) written as a difference of two small erfc values
+ * wherever the plain sum would cancel. */
+static double orc_Fn_num(double x, double s) {
+  double a = x - s;
+  double e_sum; /* erf(x - s) + erf(s) */
+  if (s < 0.0) e_sum = erfc(-s) - erfc(a);
+  else if (a < 0.0) e_sum = erfc(-a) - erfc(s);
+  else e_sum = erf(a) + erf(s);
+  return exp(-s * s) - exp(-a * a) + ORC_SQRTPI * s * e_sum;
+}
+
+double orc_F_n(double x, double s) {
+  if (x <= 0.0) return 0.0;
+  return orc_Fn_num(x, s) / orc_chi(s);
+}
+
+double orc_inv_F_n(double u, double s) {
+  double target = u * orc_chi(s);
+  double lo = 0.0, hi = (s > 0.0 ? s : 0.0) + 7.0;
+  while (orc_Fn_num(hi, s) < target) hi *= 2.0;
+  for (int it = 0; it < 400; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (orc_Fn_num(mid, s) < target) lo = mid;
+    else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Query constants.                                                            */
+/* ------------------------------------------------------------------------- */
+int orc_setup(const orc_query* q, const double* V, uint64_t nv, orc_consts* c) {
+  memset(c, 0, sizeof(*c));
+  double w = q->q_wxyz[0], x = q->q_wxyz[1], y = q->q_wxyz[2], z = q->q_wxyz[3];
+  double n = sqrt(w * w + x * x + y * y + z * z);
+  if (!(n > 0.0)) return 1;
+  w /= n; x /= n; y /= n; z /= n;
+  /* R(q) maps body to wind axes; its rows are the wind axes in the body frame:
+   * U = R^T x_hat, e1 = R^T y_hat, e2 = R^T z_hat.  This frame replaces the
+   * Rodrigues rotation of Sec. III.A.3 (same distribution, no degenerate axis). */
+  c->U[0] = 1.0 - 2.0 * (y * y + z * z);
+  c->U[1] = 2.0 * (x * y - w * z);
+  c->U[2] = 2.0 * (x * z + w * y);
+  c->e1[0] = 2.0 * (x * y + w * z);
+  c->e1[1] = 1.0 - 2.0 * (x * x + z * z);
+  c->e1[2] = 2.0 * (y * z - w * x);
+  c->e2[0] = 2.0 * (x * z - w * y);
+  c->e2[1] = 2.0 * (y * z + w * x);
+  c->e2[2] = 1.0 - 2.0 * (x * x + y * y);
+
+  c->S = q->S;
+  c->s_zero = q->S < 1e-8;
+  c->tau = sqrt(q->T_w / q->T_inf);
+  c->alpha = q->alpha;
+  c->N = q->n_particles;
+  c->seed = q->seed;
+  c->rmax = q->max_reflections;
+  c->round_fp32 = q->round_fp32;
+
+  if (q->cv_radius > 0.0) {
+    for (int k = 0; k < 3; ++k) c->c0[k] = q->cv_center[k];
+    c->r = q->cv_radius;
+  } else {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (uint64_t i = 0; i < nv; ++i)
+      for (int k = 0; k < 3; ++k) {
+        if (V[3 * i + k] < lo[k]) lo[k] = V[3 * i + k];
+        if (V[3 * i + k] > hi[k]) hi[k] = V[3 * i + k];
+      }
+    for (int k = 0; k < 3; ++k) c->c0[k] = 0.5 * (lo[k] + hi[k]);
+    double rr = 0.0;
+    for (uint64_t i = 0; i < nv; ++i) {
+      double d0 = V[3 * i] - c->c0[0], d1 = V[3 * i + 1] - c->c0[1], d2 = V[3 * i + 2] - c->c0[2];
+      double d = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      if (d > rr) rr = d;
+    }
+    c->r = rr * (1.0 + 1e-3);
+  }
+  c->Z = orc_Z(c->S);
+  c->Gamma_hat = orc_gamma_hat(c->S, c->r);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Seeding one particle, Sec. III.A.1-3.                                       */
+/* ------------------------------------------------------------------------- */
+static void orc_seed_one(const orc_consts* c, uint64_t pid, double x[3], double wv[3], double* mu_out) {
+  uint32_t r0[4], r1[4];
+  orc_stream(c->seed, pid, 0u, r0);
+  orc_stream(c->seed, pid, 1u, r1);
+  double u0 = u64_of(r0[0]), u1 = u64_of(r0[1]), u2 = u64_of(r0[2]), u3 = u64_of(r0[3]);
+  double u4 = u64_of(r1[0]);
+
+  /* Position: latitude from g(phi|S) via mu = sin(phi), longitude uniform. */
+  double mu = c->s_zero ? 2.0 * u0 - 1.0 : orc_inv_F_mu(u0, c->S);
+  double a = sqrt(fmax(0.0, 1.0 - mu * mu)); /* cos(phi) */
+  double th = 2.0 * ORC_PI * u1;
+  double ct = cos(th), st = sin(th);
+  double cvec[3], dvec[3], nhat[3], t1[3], t2[3];
+  for (int k = 0; k < 3; ++k) {
+    cvec[k] = ct * c->e1[k] + st * c->e2[k];
+    dvec[k] = -st * c->e1[k] + ct * c->e2[k];
+  }
+  /* Inward normal n = mu U - cos(phi) c, so that U.n = mu = sin(phi): the point
+   * x = c0 - r n lies upstream for mu > 0.  t1 is the unit tangent along the
+   * tangential part of U, t1 = (U - mu n)/cos(phi) = cos(phi) U + mu c, and
+   * t2 = t1 x n = -(U x c) = -d. */
+  for (int k = 0; k < 3; ++k) {
+    nhat[k] = mu * c->U[k] - a * cvec[k];
+    t1[k] = a * c->U[k] + mu * cvec[k];
+    t2[k] = -dvec[k];
+    x[k] = c->c0[k] - c->r * nhat[k];
+  }
+
+  /* Velocity, eqs. vel_dist1-3: the inward normal component from the
+   * flux-weighted drifting distribution with S_n = S sin(phi), the tangential
+   * components Gaussian (variance 1/2 in units of c_mp^2) about S_t1 = S cos(phi)
+   * and S_t2 = 0. */
+  double s_n = c->S * mu;
+  double wn = orc_inv_F_n(u2, s_n);
+  double rad = sqrt(-2.0 * log(u3));
+  double g1 = rad * cos(2.0 * ORC_PI * u4);
+  double g2 = rad * sin(2.0 * ORC_PI * u4);
+  double wt1 = c->S * a + g1 / sqrt(2.0);
+  double wt2 = g2 / sqrt(2.0);
+  /* Back to body axes by the transpose of the local frame matrix (Sec. III.A.3). */
+  for (int k = 0; k < 3; ++k) wv[k] = wn * nhat[k] + wt1 * t1[k] + wt2 * t2[k];
+
+  if (c->round_fp32) {
+    for (int k = 0; k < 3; ++k) {
+      x[k] = (double)(float)x[k];
+      wv[k] = (double)(float)wv[k];
+    }
+  }
+  if (mu_out) *mu_out = mu;
+}
+
+void orc_seed_range(const orc_consts* c, uint64_t p0, uint64_t p1, double* x, double* w, double* mu) {
+  for (uint64_t p = p0; p < p1; ++p) {
+    uint64_t i = p - p0;
+    orc_seed_one(c, p, x + 3 * i, w + 3 * i, mu ? mu + i : 0);
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Gas-surface interaction (Sec. II.A): Maxwell model, diffuse with            */
+/* probability alpha, else specular.                                           */
+/* ------------------------------------------------------------------------- */
+void orc_reflect(const orc_consts* c, uint64_t pid, uint32_t b, const double w_in[3],
+                 const double n_g[3], double w_out[3]) {
+  uint32_t r[4];
+  orc_stream(c->seed, pid, 2u + b, r);
+  double ua = u32_of(r[0]), ub = u32_of(r[1]), uc = u32_of(r[2]), ud = u32_of(r[3]);
+  double wn = w_in[0] * n_g[0] + w_in[1] * n_g[1] + w_in[2] * n_g[2];
+  if (ua < c->alpha) {
+    /* Diffuse: the particle leaves from the side it arrived on, with the
+     * flux-weighted half-range Maxwellian of the wall temperature: normal
+     * speed tau sqrt(-ln u) (eq. vel_dist1 with S_n = 0, c_mp -> c_w) and
+     * Gaussian tangential components of variance tau^2 / 2. */
+    double ns[3];
+    double sg = wn < 0.0 ? 1.0 : -1.0;
+    for (int k = 0; k < 3; ++k) ns[k] = sg * n_g[k];
+    /* Orthonormal tangents of ns (Duff et al., JCGT 2017). */
+    double sign = ns[2] >= 0.0 ? 1.0 : -1.0;
+    double aa = -1.0 / (sign + ns[2]);
+    double bb = ns[0] * ns[1] * aa;
+    double b1[3] = {1.0 + sign * ns[0] * ns[0] * aa, sign * bb, -sign * ns[0]};
+    double b2[3] = {bb, sign + ns[1] * ns[1] * aa, -ns[1]};
+    double vn = c->tau * sqrt(-log(ub));
+    double rad = sqrt(-2.0 * log(uc));
+    double g1 = rad * cos(2.0 * ORC_PI * ud), g2 = rad * sin(2.0 * ORC_PI * ud);
+    double v1 = c->tau * g1 / sqrt(2.0), v2 = c->tau * g2 / sqrt(2.0);
+    for (int k = 0; k < 3; ++k) w_out[k] = vn * ns[k] + v1 * b1[k] + v2 * b2[k];
+  } else {
+    /* Specular: mirror the normal component. */
+    for (int k = 0; k < 3; ++k) w_out[k] = w_in[k] - 2.0 * wn * n_g[k];
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Ray-triangle test (Sec. II.A: closest intersection on a triangulation).     */
+/* Watertight formulation of Woop, Benthin & Wald (JCGT 2013), two-sided.      */
+/* ------------------------------------------------------------------------- */
+int orc_intersect(const double o[3], const double d[3], const double v0[3], const double v1[3],
+                  const double v2[3], double* t_out, double b[3]) {
+  int kz = 0;
+  if (fabs(d[1]) > fabs(d[kz])) kz = 1;
+  if (fabs(d[2]) > fabs(d[kz])) kz = 2;
+  if (d[kz] == 0.0) return 0;
+  int kx = (kz + 1) % 3, ky = (kx + 1) % 3;
+  if (d[kz] < 0.0) { int tmp = kx; kx = ky; ky = tmp; }
+  double Sx = d[kx] / d[kz], Sy = d[ky] / d[kz], Sz = 1.0 / d[kz];
+  double A[3], B[3], C[3];
+  for (int k = 0; k < 3; ++k) { A[k] = v0[k] - o[k]; B[k] = v1[k] - o[k]; C[k] = v2[k] - o[k]; }
+  double Ax = A[kx] - Sx * A[kz], Ay = A[ky] - Sy * A[kz];
+  double Bx = B[kx] - Sx * B[kz], By = B[ky] - Sy * B[kz];
+  double Cx = C[kx] - Sx * C[kz], Cy = C[ky] - Sy * C[kz];
+  double U = Cx * By - Cy * Bx;
+  double Vv = Ax * Cy - Ay * Cx;
+  double W = Bx * Ay - By * Ax;
+  if ((U < 0.0 || Vv < 0.0 || W < 0.0) && (U > 0.0 || Vv > 0.0 || W > 0.0)) return 0;
+  double det = U + Vv + W;
+  if (det == 0.0) return 0;
+  double T = U * (Sz * A[kz]) + Vv * (Sz * B[kz]) + W * (Sz * C[kz]);
+  double t = T / det;
+  if (!(t > 0.0)) return 0;
+  *t_out = t;
+  b[0] = U / det; b[1] = Vv / det; b[2] = W / det;
+  return 1;
+}
+
+static void tri_verts(const double* V, const uint32_t* T, uint64_t k, double v0[3], double v1[3], double v2[3]) {
+  for (int j = 0; j < 3; ++j) {
+    v0[j] = V[3 * (uint64_t)T[3 * k + 0] + j];
+    v1[j] = V[3 * (uint64_t)T[3 * k + 1] + j];
+    v2[j] = V[3 * (uint64_t)T[3 * k + 2] + j];
+  }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Trace, interact and tally (Sec. II.A; multiple reflections, Sec. I).        */
+/* ------------------------------------------------------------------------- */
+int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt,
+                    const orc_consts* c, uint64_t p0, uint64_t p1,
+                    double* tri_sum, double* tri_comp, orc_scalars* sc,
+                    int32_t* first_tri, int32_t* nhits, double* Dp) {
+  (void)nv;
+  for (uint64_t pid = p0; pid < p1; ++pid) {
+    double o[3], w[3];
+    orc_seed_one(c, pid, o, w, 0);
+    int64_t prev = -1;
+    uint32_t hits = 0;
+    double D = 0.0;
+    int32_t first = -1;
+    sc->rays += 1;
+    for (;;) {
+      sc->segments += 1;
+      /* Closest hit over every triangle except the one just left; ties in t
+       * keep the lower index because only a strictly smaller t replaces it. */
+      int64_t best = -1;
+      double best_t = INFINITY, best_b[3] = {0, 0, 0};
+      for (uint64_t k = 0; k < nt; ++k) {
+        if ((int64_t)k == prev) continue;
+        double v0[3], v1[3], v2[3], t, b[3];
+        tri_verts(V, T, k, v0, v1, v2);
+        if (orc_intersect(o, w, v0, v1, v2, &t, b) && t < best_t) {
+          best_t = t; best = (int64_t)k;
+          best_b[0] = b[0]; best_b[1] = b[1]; best_b[2] = b[2];
+        }
+      }
+      if (best < 0) {
+        if (hits == 0) sc->missed += 1;
+        else sc->escaped += 1;
+        break;
+      }
+      double v0[3], v1[3], v2[3], p[3], e1[3], e2[3], ng[3];
+      tri_verts(V, T, (uint64_t)best, v0, v1, v2);
+      for (int k = 0; k < 3; ++k) {
+        p[k] = best_b[0] * v0[k] + best_b[1] * v1[k] + best_b[2] * v2[k];
+        e1[k] = v1[k] - v0[k];
+        e2[k] = v2[k] - v0[k];
+      }
+      ng[0] = e1[1] * e2[2] - e1[2] * e2[1];
+      ng[1] = e1[2] * e2[0] - e1[0] * e2[2];
+      ng[2] = e1[0] * e2[1] - e1[1] * e2[0];
+      double nl = sqrt(ng[0] * ng[0] + ng[1] * ng[1] + ng[2] * ng[2]);
+      for (int k = 0; k < 3; ++k) ng[k] /= nl;
+
+      double wout[3];
+      orc_reflect(c, pid, hits, w, ng, wout);
+      /* Momentum given to the body by this hit (Sec. II.A): w - w', and its
+       * moment about the body origin, p x (w - w'). */
+      double dw[3] = {w[0] - wout[0], w[1] - wout[1], w[2] - wout[2]};
+      double L[3] = {p[1] * dw[2] - p[2] * dw[1], p[2] * dw[0] - p[0] * dw[2], p[0] * dw[1] - p[1] * dw[0]};
+      double* s = tri_sum + 7 * (uint64_t)best;
+      double* cc = tri_comp + 7 * (uint64_t)best;
+      for (int k = 0; k < 3; ++k) { nsum(s + k, cc + k, dw[k]); nsum(s + 3 + k, cc + 3 + k, L[k]); }
+      s[6] += 1.0;
+      D += dw[0] * c->U[0] + dw[1] * c->U[1] + dw[2] * c->U[2];
+      if (hits == 0) first = (int32_t)best;
+      hits += 1;
+      sc->hits += 1;
+      for (int k = 0; k < 3; ++k) { o[k] = p[k]; w[k] = wout[k]; }
+      prev = best;
+      if (hits >= c->rmax) { sc->capped += 1; break; }
+    }
+    nsum(&sc->D, &sc->D_c, D);
+    nsum(&sc->D2, &sc->D2_c, D * D);
+    uint64_t i = pid - p0;
+    if (first_tri) first_tri[i] = first;
+    if (nhits) nhits[i] = (int32_t)hits;
+    if (Dp) Dp[i] = D;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Force, moment and drag coefficient (eq. drag; Sec. II.A effective mass).    */
+/* Each particle carries the rate Gamma / N, so the force is                   */
+/*   F = rho c_mp^2 (Gamma_hat / N) sum (w - w'),  q = rho S^2 c_mp^2 / 2,      */
+/*   F / q = K sum (w - w') with K = 2 Gamma_hat / (N S^2).                     */
+/* ------------------------------------------------------------------------- */
+void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt, const orc_scalars* sc,
+                  const double x_ref[3], double A_ref, orc_result* out) {
+  memset(out, 0, sizeof(*out));
+  double F[3] = {0, 0, 0}, Fc[3] = {0, 0, 0}, L[3] = {0, 0, 0}, Lc[3] = {0, 0, 0};
+  for (uint64_t k = 0; k < nt; ++k)
+    for (int j = 0; j < 3; ++j) {
+      nsum(&F[j], &Fc[j], tri_total[7 * k + j]);
+      nsum(&L[j], &Lc[j], tri_total[7 * k + 3 + j]);
+    }
+  for (int j = 0; j < 3; ++j) { F[j] += Fc[j]; L[j] += Lc[j]; }
+  double N = (double)c->N;
+  double K = c->s_zero ? NAN : 2.0 * c->Gamma_hat / (N * c->S * c->S);
+  double M[3] = {L[0] - (x_ref[1] * F[2] - x_ref[2] * F[1]),
+                 L[1] - (x_ref[2] * F[0] - x_ref[0] * F[2]),
+                 L[2] - (x_ref[0] * F[1] - x_ref[1] * F[0])};
+  for (int j = 0; j < 3; ++j) {
+    out->F_over_q[j] = K * F[j];
+    out->M_over_q[j] = K * M[j];
+    out->Fhat[j] = c->Gamma_hat / N * F[j];
+  }
+  out->CD = (out->F_over_q[0] * c->U[0] + out->F_over_q[1] * c->U[1] + out->F_over_q[2] * c->U[2]) / A_ref;
+  double meanD = (sc->D + sc->D_c) / N;
+  double varD = (sc->D2 + sc->D2_c) / N - meanD * meanD;
+  if (varD < 0.0) varD = 0.0;
+  out->CD_sigma = c->s_zero ? NAN : 2.0 * c->Gamma_hat / (c->S * c->S * A_ref) * sqrt(varD / N);
+  out->Gamma_hat = c->Gamma_hat;
+  out->rays = sc->rays; out->hits = sc->hits; out->segments = sc->segments;
+  out->missed = sc->missed; out->escaped = sc->escaped; out->capped = sc->capped;
+}

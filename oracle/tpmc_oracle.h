@@ -1,0 +1,109 @@
+/*
+ * tpmc_oracle.h -- FP64 CPU oracle of the test-particle Monte Carlo (TPMC)
+ * drag hot path of Parham & Barba, "Finding the Force -- Consistent Particle
+ * Seeding for Satellite Aerodynamics".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, plain reference that the
+ * GPU path is checked against.  Only tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or helper
+ * with the HIP library under paper_1312_3691_amd/csrc.
+ *
+ * Units: velocities are dimensionless, w = v / c_mp (c_mp = most probable
+ * thermal speed of the free stream, Nomenclature).  Lengths are metres in the
+ * body frame.
+ */
+#ifndef TPMC_ORACLE_H
+#define TPMC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One drag query (paper Sec. II.A problem statement, Sec. III.A seeding). */
+typedef struct {
+  double q_wxyz[4];          /* unit quaternion body->wind; free stream along +x_wind */
+  double S;                  /* speed ratio U / c_mp (Nomenclature), >= 0 */
+  double T_inf, T_w;         /* free-stream and wall temperature, K */
+  double alpha;              /* Maxwell accommodation: probability of diffuse re-emission */
+  uint64_t n_particles;      /* N */
+  uint64_t seed;             /* Philox key */
+  uint32_t max_reflections;  /* hit cap per particle */
+  int32_t round_fp32;        /* 1: round seeded x, w to FP32 before tracing */
+  double cv_center[3];       /* control-volume centre (used when cv_radius > 0) */
+  double cv_radius;          /* <= 0: bounding sphere of the vertices times (1 + 1e-3) */
+} orc_query;
+
+/* Per-query constants derived in FP64 (Sec. III.A.1, III.A.3). */
+typedef struct {
+  double U[3], e1[3], e2[3]; /* free-stream direction and seeding tangents, body frame */
+  double S, tau, alpha;      /* tau = sqrt(T_w / T_inf) = c_w / c_mp */
+  double Z;                  /* normaliser of the incidence-latitude density */
+  double Gamma_hat;          /* Gamma / (n c_mp), number flux into the CV */
+  double c0[3], r;           /* control volume */
+  uint64_t N, seed;
+  uint32_t rmax;
+  int32_t round_fp32;
+  int32_t s_zero;            /* 1 when S is treated as exactly zero */
+} orc_consts;
+
+/* Running sums over a particle range.  D is the per-particle momentum given to
+ * the body along U (sum over that particle's hits of (w - w').U). */
+typedef struct {
+  double D, D_c, D2, D2_c;   /* Neumaier sums of D and D^2 */
+  uint64_t rays, hits, segments, missed, escaped, capped;
+} orc_scalars;
+
+typedef struct {
+  double F_over_q[3], M_over_q[3], Fhat[3];
+  double CD, CD_sigma, Gamma_hat;
+  uint64_t rays, hits, segments, missed, escaped, capped;
+} orc_result;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Closed-form pieces of the seeding model. */
+double orc_chi(double s);                 /* e^{-s^2} + sqrt(pi) s (1 + erf s) */
+double orc_Z(double S);                   /* normaliser of g(phi|S) */
+double orc_gamma_hat(double S, double r); /* Gamma / (n c_mp) */
+double orc_F_mu(double t, double S);      /* CDF of mu = sin(phi) */
+double orc_inv_F_mu(double u, double S);
+double orc_F_n(double x, double s);       /* CDF of the inward normal speed */
+double orc_inv_F_n(double u, double s);
+
+int orc_setup(const orc_query* q, const double* V, uint64_t nv, orc_consts* out);
+
+/* Seed particles [p0, p1): x, w are [n][3]; mu may be NULL. */
+void orc_seed_range(const orc_consts* c, uint64_t p0, uint64_t p1,
+                    double* x, double* w, double* mu);
+
+/* Re-emission of one particle: hit number b (0-based) of particle pid, incoming
+ * w_in at a triangle with unit geometric normal n_g. */
+void orc_reflect(const orc_consts* c, uint64_t pid, uint32_t b,
+                 const double w_in[3], const double n_g[3], double w_out[3]);
+
+/* Closest-hit test of one ray against one triangle (two-sided, t > 0).
+ * Returns 1 on hit with t and barycentrics b[3] (weights of v0, v1, v2). */
+int orc_intersect(const double o[3], const double d[3], const double v0[3],
+                  const double v1[3], const double v2[3], double* t, double b[3]);
+
+/* Trace particles [p0, p1) through the mesh, accumulating per-triangle sums
+ * tri_sum/tri_comp ([nt][7]: dw_x, dw_y, dw_z, (p x dw)_x.._z, count; Neumaier
+ * pairs) and the scalar sums.  Optional per-particle outputs (length p1 - p0):
+ * first_tri (-1 when missed), nhits, Dp. */
+int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt,
+                    const orc_consts* c, uint64_t p0, uint64_t p1,
+                    double* tri_sum, double* tri_comp, orc_scalars* sc,
+                    int32_t* first_tri, int32_t* nhits, double* Dp);
+
+/* Convert merged sums to force, moment and drag coefficient. */
+void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt,
+                  const orc_scalars* sc, const double x_ref[3], double A_ref,
+                  orc_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
