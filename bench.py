@@ -1,0 +1,263 @@
+"""Benchmark: particle-surface hits per second on one MI355X.
+
+Workload (one step): the flat-plate and capped-cylinder verification sweep --
+a 1 x 1 m double-sided plate (2 triangles) and a 64-segment capped cylinder
+(256 triangles), each at 10 incidence angles 0..90 deg, S in {1, 3, 8},
+specular and diffuse (alpha = 1), T_inf = 1000 K, T_w = 300 K, 1e7 particles
+per case: 120 drag queries, 1.2e9 particles.  Each mesh's 60 queries run as one
+persistent, graph-replayed batched launch; inputs (meshes, BVHs, query tables)
+are resident on the GPU before the timed region.
+
+Also reported: the same 120 queries through the plain one-query-per-launch
+path (seed -> trace -> forces, host sync per query) with p50 / p99 query
+latency; C_D error of every case against the per-facet closed form; the
+roofline of the dominant kernel; and the CPU oracle on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-surface hits/sec on 1 MI355X at C_D error ≤1e-3; p50/p99 query ms"
+T_INF, T_W = 1000.0, 300.0
+N_PER_CASE = 10_000_000
+ALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (one VALU op per lane per clock)
+# Algorithmic lane-operations per unit of work ("Roofline").
+OPS_SEED = 950.0   # per particle: 2 Philox blocks + FP64 inverse-CDF seeding + frame
+OPS_NODE = 40.0    # per BVH node visit: two slab tests + stack
+OPS_TRI = 45.0     # per watertight triangle test
+OPS_HIT = 225.0    # per hit: Philox block + re-emission + tally
+KERNEL_SOURCES = ["tpmc_device.hpp", "tpmc_kernels.hip", "tpmc_internal.h"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cases(n=N_PER_CASE):
+    from paper_1312_3691_amd import inputs as I
+    out = []
+    for kind, gen in (("plate", I.plate_cases), ("cylinder", I.cylinder_cases)):
+        for i, c in enumerate(gen(n=n)):
+            q = I.query(q=c["q"], S=c["S"], T_inf=T_INF, T_w=T_W, alpha=c["alpha"], n=n,
+                        seed=len(out), max_reflections=16)
+            out.append(dict(kind=kind, angle=c["angle"], query=q))
+    return out
+
+
+def meshes():
+    from paper_1312_3691_amd import inputs as I
+    return {"plate": I.plate(), "cylinder": I.capped_cylinder()}
+
+
+def exact_cd(kind, V, T, q):
+    from oracle import closed_forms as CF
+    from paper_1312_3691_amd import inputs as I
+    U = I.flow_dir(q["q"])
+    F, _, _ = CF.mesh_force(V, T, U, q["S"], math.sqrt(T_W / T_INF), q["alpha"], two_sided=(kind == "plate"))
+    return float(F @ U)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1312_3691_amd", "csrc", s), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str, workload: str):
+    """HBM traffic per launch measured with rocprofv3 counters (profiles/traffic.json),
+    used only while the kernel sources are unchanged since the measurement."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(kernel, {}).get(workload)
+        if e and e.get("kernel_hash") == kernel_hash():
+            return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(case_list, mesh_map, budget_s=15.0):
+    """The FP64 oracle, as it stands, on the first particles of every case."""
+    from oracle import oracle as O
+    threads = min(os.cpu_count() or 1, 16)
+    # calibrate on one plate and one cylinder case
+    t0 = time.perf_counter()
+    probe = 2000
+    for c in (case_list[0], case_list[-1]):
+        V, T = mesh_map[c["kind"]]
+        O.run(V, T, c["query"], p_range=(0, probe), threads=threads)
+    per_particle = (time.perf_counter() - t0) / (2 * probe)
+    m = int(max(1000, min(200_000, budget_s / (per_particle * len(case_list)))))
+    hits = 0
+    t0 = time.perf_counter()
+    for c in case_list:
+        V, T = mesh_map[c["kind"]]
+        r = O.run(V, T, c["query"], p_range=(0, m), threads=threads)
+        hits += int(r["hits"])
+    dt = time.perf_counter() - t0
+    return {"value": hits / dt, "unit": "hits/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {m} particles of each of the {len(case_list)} cases "
+                      f"({m * len(case_list)} particles, {hits} hits, {dt:.1f} s wall)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--particles", type=int, default=N_PER_CASE, help="particles per case (default 1e7)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the drag path shards by particle range, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1312_3691_amd import tpmc
+
+    ctx = tpmc.Context(0)
+    mm = meshes()
+    cl = cases(args.particles)
+    dev_mesh = {k: ctx.build_mesh(*v) for k, v in mm.items()}
+    batches = {}
+    for kind in ("plate", "cylinder"):
+        qs = [c["query"] for c in cl if c["kind"] == kind]
+        batches[kind] = tpmc.Batch(dev_mesh[kind], qs)
+    torch.cuda.synchronize()
+
+    def step(use_graph=True):
+        out = []
+        for kind in ("plate", "cylinder"):
+            b = batches[kind]
+            b.launch(use_graph=use_graph)
+            out += b.results(A_ref=1.0)
+        return out
+
+    log("warmup")
+    res = step(use_graph=False)
+    for _ in range(args.warmup):
+        res = step()
+    torch.cuda.synchronize()
+    log("timed steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    hits = sum(r["hits"] for r in res)
+    particles = sum(r["rays"] for r in res)
+    segments = sum(r["segments"] for r in res)
+
+    # dominant kernel: the persistent batched kernel, timed with events on its stream
+    stream = ctx.stream
+    kern_ms = {}
+    for kind in ("plate", "cylinder"):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(max(2, args.steps)):
+            e0.record(stream)
+            batches[kind].launch(use_graph=True)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        kern_ms[kind] = float(np.mean(ts))
+
+    # traversal work per segment from the counting kernel (untimed, 1e6-particle subsets)
+    log("work counters")
+    nodes = tests = segs_c = 0
+    for c in cl[::6]:
+        q = dict(c["query"], n=min(1_000_000, c["query"]["n"]))
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        pr = tpmc.PlainRun(dev_mesh[c["kind"]], [q]).seed().trace(counters=cnt)
+        r = pr.forces()[0]
+        nodes += int(cnt[0])
+        tests += int(cnt[1])
+        segs_c += r["segments"]
+        pr.close()
+    V_seg, T_seg = nodes / segs_c, tests / segs_c
+    ops = particles * OPS_SEED + segments * (V_seg * OPS_NODE + T_seg * OPS_TRI) + hits * OPS_HIT
+    launch_s = sum(kern_ms.values()) / 1e3
+    achieved = ops / launch_s
+    workload = "plate+cylinder sweep, 120 cases x 1e7 particles"
+    traffic = stored_traffic("batch_kernel", workload)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s",
+                "frac": achieved / ALU_PEAK, "traffic": traffic,
+                "kernel": "batch_kernel (seed + trace + tally fused)", "kernel_ms_per_step": launch_s * 1e3,
+                "work_per_step": {"particles": particles, "segments": segments, "hits": hits,
+                                  "node_visits_per_segment": V_seg, "triangle_tests_per_segment": T_seg,
+                                  "alg_lane_ops": ops}}
+
+    # accuracy of every case against the per-facet closed form
+    errs, within = [], 0
+    for c, r in zip([c for k in ("plate", "cylinder") for c in cl if c["kind"] == k], res):
+        V, T = mm[c["kind"]]
+        e = abs(r["CD"] - exact_cd(c["kind"], V, T, c["query"]))
+        errs.append(e)
+        within += e <= 1e-3
+    accuracy = {"max_abs_cd_err": float(max(errs)), "median_abs_cd_err": float(np.median(errs)),
+                "cases_within_1e-3": int(within), "cases": len(errs),
+                "max_cd_sigma": float(max(r["CD_sigma"] for r in res if not math.isnan(r["CD_sigma"])))}
+
+    # plain path: one query per launch, host sync per query
+    plain = None
+    if not args.no_plain:
+        log("plain path")
+        lat = []
+        p_hits = 0
+        for c in cl[:2]:
+            tpmc.run(dev_mesh[c["kind"]], [c["query"]])[1].close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in cl:
+            t1 = time.perf_counter()
+            r, pr = tpmc.run(dev_mesh[c["kind"]], [c["query"]])
+            lat.append((time.perf_counter() - t1) * 1e3)
+            p_hits += r[0]["hits"]
+            pr.close()
+        pdt = time.perf_counter() - t0
+        plain = {"hits_per_s": p_hits / pdt, "s_per_step": pdt,
+                 "query_ms_p50": float(np.percentile(lat, 50)), "query_ms_p99": float(np.percentile(lat, 99))}
+
+    cpu = None
+    if not args.no_cpu:
+        log("cpu baseline")
+        cpu = cpu_baseline(cl, mm)
+
+    line = {"metric": METRIC, "value": hits / dt, "unit": "hits/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": workload + (" (1.2e9 particles)" if args.particles == N_PER_CASE else
+                                               f" ({args.particles} particles per case)"),
+                       "meshes": "plate 2 tris, capped cylinder 256 tris", "S": [1, 3, 8],
+                       "accommodation": [0.0, 1.0], "angles_deg": list(range(0, 91, 10)),
+                       "T_inf_K": T_INF, "T_w_K": T_W, "particles_per_case": args.particles,
+                       "path": "batched persistent launch per mesh, HIP graph replay"},
+            "query_ms_p50": plain["query_ms_p50"] if plain else None,
+            "query_ms_p99": plain["query_ms_p99"] if plain else None,
+            "segments_per_s": segments / dt, "particles_per_s": particles / dt,
+            "accuracy": accuracy, "plain_path": plain, "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * tpmc.h -- C ABI of the MI355X test-particle Monte Carlo (TPMC) drag library.
+ *
+ * Method: J. B. Parham and L. A. Barba, "Finding the Force -- Consistent
+ * Particle Seeding for Satellite Aerodynamics" (AIAA).  A drag query seeds N
+ * test particles on a spherical control volume (CV) enclosing the body with
+ * the flux-correct drifting-Maxwellian boundary distribution (Sec. III.A),
+ * follows each through a triangulated surface by closest-hit ray tracing with
+ * specular / diffuse (Maxwell) re-emission (Sec. II.A, multiple reflections
+ * Sec. I), and sums the momentum each particle gives each triangle into force,
+ * moment and drag coefficient (eq. drag; effective mass Sec. II.A).
+ *
+ * Conventions
+ *  - Every function returns tpmc_status; TPMC_OK = 0.  No C++ exception
+ *    crosses the ABI.  tpmc_last_error() returns the calling thread's last
+ *    error message (valid until that thread's next call).
+ *  - Handles are opaque and owned by the caller, who destroys them.  Destroy
+ *    functions accept NULL.
+ *  - Host arrays passed in are read during the call and never retained.
+ *  - "Device" pointers are HIP device memory of the context's device.  The
+ *    library allocates device memory only in tpmc_build_mesh (the resident
+ *    BVH); every per-query buffer lives in a caller-provided workspace.
+ *  - Work is enqueued on the context's HIP stream.  tpmc_seed, tpmc_trace and
+ *    tpmc_batch_launch are asynchronous; tpmc_forces, tpmc_tally_copy,
+ *    tpmc_batch_results and tpmc_run_batch synchronise the stream.
+ *  - Velocities are dimensionless, w = v / c_mp (Nomenclature: c_mp is the
+ *    most probable thermal speed of the free stream).  Lengths are metres in
+ *    the body frame.  All results are in the body frame.
+ *  - A context is not thread-safe; calls on one context must not overlap.
+ */
+#ifndef TPMC_H
+#define TPMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPMC_ABI_VERSION 1
+
+typedef enum {
+  TPMC_OK = 0,
+  TPMC_E_INVALID = 1,   /* bad argument: NULL handle, non-finite or out-of-range query field */
+  TPMC_E_MESH = 2,      /* nt == 0, index >= nv, non-finite vertex, BVH deeper than supported */
+  TPMC_E_CV = 3,        /* the control volume does not enclose every vertex */
+  TPMC_E_WORKSPACE = 4, /* workspace NULL, misaligned (256 B) or smaller than required */
+  TPMC_E_DEVICE = 5,    /* a HIP call failed; message has the HIP error string */
+  TPMC_E_BUSY = 6       /* handle belongs to another context / batch not launched */
+} tpmc_status;
+
+typedef struct tpmc_ctx_s* tpmc_ctx;
+typedef struct tpmc_mesh_s* tpmc_mesh;
+typedef struct tpmc_particles_s* tpmc_particles;
+typedef struct tpmc_tally_s* tpmc_tally;
+typedef struct tpmc_batch_s* tpmc_batch;
+
+/* One drag query: the paper's problem statement (mesh separately). */
+typedef struct {
+  double q_wxyz[4];          /* attitude: unit quaternion (|q| within 1e-6 of 1) of the rotation
+                                body -> wind axes; the free stream runs along +x of the wind axes,
+                                so its body-frame direction U is the first row of R(q), and the
+                                second and third rows are the seeding tangents e1, e2 */
+  double S;                  /* speed ratio U_inf / c_mp (Sec. II.B), 0 <= S <= 100; S == 0 is
+                                a gas at rest (then CD, CD_sigma and F_over_q are NaN) */
+  double T_inf, T_w;         /* free-stream and wall temperature, K, > 0; only
+                                tau = sqrt(T_w / T_inf) enters the dimensionless results */
+  double alpha;              /* Maxwell accommodation: probability of diffuse re-emission, [0, 1] */
+  uint64_t n_particles;      /* N >= 1 test particles */
+  uint64_t seed;             /* Philox4x32-10 key; particle p uses counter (p lo, p hi, step, 0) */
+  uint32_t max_reflections;  /* hit cap per particle, 1..64; a particle reaching it retires as capped */
+  uint32_t flags;            /* TPMC_Q_* bits */
+  double cv_center[3];       /* control-volume centre, used when cv_radius > 0 */
+  double cv_radius;          /* CV radius (m); <= 0: centre = vertex-box centre, radius = largest
+                                vertex distance times (1 + 1e-3) */
+} tpmc_query;
+
+#define TPMC_Q_NO_TRIANGLE_TALLY 1u /* batched path: keep only per-query totals */
+
+/* Result of one query.  Force and moment are divided by the dynamic pressure
+ * q = rho U^2 / 2 (so they are areas, m^2, and m^3); Fhat = F / (rho c_mp^2) is
+ * finite at S = 0.  CD = (F/q).U / A_ref; CD_sigma is its one-sigma
+ * statistical error from the per-particle momentum along U. */
+typedef struct {
+  double F_over_q[3], M_over_q[3], Fhat[3];
+  double CD, CD_sigma, Gamma_hat; /* Gamma_hat = Gamma / (n c_mp): CV number flux (Sec. III.A.1) */
+  uint64_t rays;     /* particles traced (= N) */
+  uint64_t hits;     /* particle-surface hits, re-hits included */
+  uint64_t segments; /* rays cast: hits + particles that left the body or missed it */
+  uint64_t missed;   /* particles that never hit */
+  uint64_t escaped;  /* particles that hit at least once and then left */
+  uint64_t capped;   /* particles retired at max_reflections */
+} tpmc_result;
+
+typedef struct {
+  uint64_t nv, nt;
+  uint32_t depth;        /* BVH depth (root = 0) */
+  uint32_t stack_slots;  /* traversal stack depth the trace kernel uses */
+  double box_lo[3], box_hi[3];
+  double sphere_center[3], sphere_radius; /* default control volume */
+  uint64_t device_bytes; /* resident BVH + triangle records */
+} tpmc_mesh_info;
+
+const char* tpmc_last_error(void);
+int tpmc_abi_version(void);
+
+/* Context on HIP device `device` issuing work on `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Reads device properties; allocates nothing. */
+tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out);
+tpmc_status tpmc_set_stream(tpmc_ctx ctx, void* hip_stream);
+void tpmc_destroy_ctx(tpmc_ctx ctx);
+
+/* Mesh and its linear BVH (Karras 2012 hierarchy over 30-bit Morton codes of
+ * the triangle centroids; closest-hit tracing on a triangulation, Sec. II.A).
+ *   xyz: host float [nv][3], metres, body frame.  tri: host uint32 [nt][3].
+ * Triangles are two-sided; zero-area triangles are accepted and never hit.
+ * Builds on the device (synchronises); the handle owns its device memory. */
+tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
+                            tpmc_mesh* out);
+tpmc_status tpmc_get_mesh_info(tpmc_mesh mesh, tpmc_mesh_info* out);
+void tpmc_destroy_mesh(tpmc_mesh mesh);
+
+/* Bytes of device workspace tpmc_seed needs for these nq queries (particle
+ * states 24 B each, per-triangle tallies 56 B per triangle per query, tables). */
+tpmc_status tpmc_workspace_bytes(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, uint32_t nq,
+                                 uint64_t* bytes);
+
+/* Seed all particles of the nq queries (Sec. III.A.1-3) into the workspace:
+ * FP64 inverse-CDF sampling of the incidence latitude (g(phi|S)) and of the
+ * inward normal speed (eq. vel_dist1), Gaussian tangential components (eqs.
+ * vel_dist2-3), stored as FP32 structure-of-arrays.  `dev_workspace` is device
+ * memory of at least tpmc_workspace_bytes, 256-byte aligned, owned by the
+ * caller and used until the particles and tally handles are destroyed. */
+tpmc_status tpmc_seed(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, uint32_t nq, void* dev_workspace,
+                      uint64_t ws_bytes, tpmc_particles* out);
+
+/* Device views of the seeded states: six FP32 planes x0, x1, x2, w0, w1, w2,
+ * each of n_total entries (query i occupies [sum_{j<i} N_j, ... + N_i)). */
+tpmc_status tpmc_particles_planes(tpmc_particles p, float* dev_planes[6], uint64_t* n_total);
+
+/* Trace every seeded particle: closest two-sided hit with t > 0 excluding the
+ * triangle just left (equal t: lower triangle index), FP32 watertight test
+ * (Woop, Benthin & Wald 2013); re-emission diffuse with probability alpha at
+ * T_w (cosine law), else specular; per-triangle momentum and moment tallies in
+ * exact int64 fixed point.  dev_first_tri (optional, int32 [n_total]) receives
+ * each particle's first-hit triangle index, -1 when it missed.  dev_counters
+ * (optional, uint64 [2], accumulated into, caller zeroes) receives the BVH
+ * nodes visited and the ray-triangle tests made; it selects a counting
+ * variant of the kernel, so leave it NULL when timing. */
+tpmc_status tpmc_trace(tpmc_ctx ctx, tpmc_mesh mesh, tpmc_particles p, tpmc_tally* out);
+tpmc_status tpmc_trace_ex(tpmc_ctx ctx, tpmc_mesh mesh, tpmc_particles p, int32_t* dev_first_tri,
+                          uint64_t* dev_counters, tpmc_tally* out);
+
+/* Reduce the tallies to force, moment about ref_point (body frame, m) and C_D
+ * with reference area A_ref > 0 (eq. drag).  out: host [nq].  Synchronises. */
+tpmc_status tpmc_forces(tpmc_ctx ctx, tpmc_tally t, const double ref_point[3], double A_ref, tpmc_result* out);
+
+/* Per-triangle sums of one query, host double [nt][7]: sum of (w - w') xyz,
+ * sum of p x (w - w') xyz about the body origin, hit count.  Synchronises. */
+tpmc_status tpmc_tally_copy(tpmc_ctx ctx, tpmc_tally t, uint32_t query, double* host_per_tri);
+
+void tpmc_destroy_particles(tpmc_particles p);
+void tpmc_destroy_tally(tpmc_tally t);
+
+/* ---- Batched path: many queries on one mesh in one persistent launch ----
+ * Work items are (query, tile of particles); workgroups take them from a
+ * device counter, seed the tile into LDS and trace it, so particle states
+ * never go to HBM.  Results equal the plain path's bit for bit (same Philox
+ * streams, same per-particle arithmetic, exact integer tallies). */
+tpmc_status tpmc_batch_workspace_bytes(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, uint32_t nq,
+                                       uint64_t* bytes);
+/* Upload the query table and work map; returns a batch handle bound to the
+ * workspace.  Does not launch the trace. */
+tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, uint32_t nq,
+                              void* dev_workspace, uint64_t ws_bytes, tpmc_batch* out);
+/* Enqueue zeroing, the persistent kernel and the reduction (asynchronous).
+ * use_graph != 0 replays a HIP graph captured on the first call. */
+tpmc_status tpmc_batch_launch(tpmc_ctx ctx, tpmc_batch b, int use_graph);
+/* Wait and convert: out host [nq]. */
+tpmc_status tpmc_batch_results(tpmc_ctx ctx, tpmc_batch b, const double ref_point[3], double A_ref,
+                               tpmc_result* out);
+void tpmc_destroy_batch(tpmc_batch b);
+
+/* Host-only checks (no device needed): the validation the entry points above
+ * apply.  tpmc_check_query also needs the mesh vertices for the CV test. */
+tpmc_status tpmc_check_mesh(const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt);
+tpmc_status tpmc_check_query(const tpmc_query* q, const float* xyz, uint64_t nv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,88 @@
+"""Build libtpmc.so (HIP for gfx950) in-tree with hipcc.
+
+    python -m paper_1312_3691_amd.build        # or build() from Python
+
+Every HIP source is compiled with packed-FP32 instruction selection disabled
+(-Xclang -target-feature -Xclang -packed-fp32-ops).
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libtpmc.so")
+SOURCES = ["tpmc_capi.hip", "tpmc_kernels.hip", "tpmc_bvh.hip"]
+HEADERS = ["tpmc_device.hpp", "tpmc_internal.h", "tpmc_launch.h"]
+ARCH = os.environ.get("TPMC_OFFLOAD_ARCH", "gfx950")
+
+
+def hipcc() -> str:
+    for cand in (shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found (ROCm is required to build libtpmc.so)")
+
+
+BUILD_DIR = os.path.join(HERE, "..", "_build")
+
+
+def torch_lib_dir() -> str:
+    """PyTorch's lib directory (found without importing torch).  The library is
+    linked against PyTorch's HIP runtime so that one process holds exactly one
+    HIP runtime: device pointers and streams from PyTorch are then valid here."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.submodule_search_locations:
+        raise RuntimeError("PyTorch (ROCm build) is required")
+    d = os.path.join(list(spec.submodule_search_locations)[0], "lib")
+    if not os.path.exists(os.path.join(d, "libamdhip64.so")):
+        raise RuntimeError(f"no libamdhip64.so in {d}: a ROCm build of PyTorch is required")
+    return d
+
+
+def compile_command(src: str, obj: str) -> list:
+    return [hipcc(), f"--offload-arch={ARCH}", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC", "-c",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+            "-I", os.path.join(HERE, "..", "include"), "-o", obj, src]
+
+
+def link_command(objs: list, out: str) -> list:
+    tl = torch_lib_dir()
+    # the system linker driver, so that no ROCm library path is added implicitly
+    return ["g++", "-shared", "-fPIC", "-o", out] + objs + [
+        "-L" + tl, "-l:libamdhip64.so", "-Wl,--disable-new-dtags,-rpath," + tl, "-lstdc++", "-lm"]
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("build step failed: " + " ".join(cmd[:3]))
+    noise = [ln for ln in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
+    if verbose and noise:
+        print("\n".join(noise))
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP source and link paper_1312_3691_amd/libtpmc.so (always rebuilds)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    objs = []
+    for s in SOURCES:
+        obj = os.path.join(BUILD_DIR, s.replace(".hip", ".o"))
+        _run(compile_command(os.path.join(CSRC, s), obj), verbose)
+        objs.append(obj)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run(link_command(objs, tmp), verbose)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,343 @@
+// tpmc_bvh.hip -- linear BVH over the triangle mesh, built on the device.
+//
+// Closest-hit tracing on a triangulation (Sec. II.A) needs an acceleration
+// structure; this is an LBVH: 30-bit Morton codes of triangle centroids, a
+// stable LSD radix sort (4-bit digits, wave-ballot ranking), the binary radix
+// tree of Karras (HPG 2012) and a bottom-up box refit with atomic flags.
+// Triangles are then packed in Morton order for locality.
+#include <hip/hip_runtime.h>
+
+#include "tpmc_device.hpp"
+#include "tpmc_launch.h"
+
+namespace tpmc {
+
+namespace {
+
+constexpr int kSortItems = 4;
+constexpr int kSortTile = kBlock * kSortItems;
+
+__device__ __forceinline__ uint32_t spread_bits10(uint32_t v) {
+  v = (v * 0x00010001u) & 0xFF0000FFu;
+  v = (v * 0x00000101u) & 0x0F00F00Fu;
+  v = (v * 0x00000011u) & 0xC30C30C3u;
+  v = (v * 0x00000005u) & 0x49249249u;
+  return v;
+}
+
+__global__ void morton_kernel(const float* __restrict__ xyz, const uint32_t* __restrict__ tri, uint32_t nt, float lox,
+                              float loy, float loz, float sx, float sy, float sz, uint32_t* __restrict__ keys,
+                              uint32_t* __restrict__ vals) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const uint32_t a = tri[3 * i], b = tri[3 * i + 1], c = tri[3 * i + 2];
+  const float cx = (xyz[3 * a] + xyz[3 * b] + xyz[3 * c]) * (1.0f / 3.0f);
+  const float cy = (xyz[3 * a + 1] + xyz[3 * b + 1] + xyz[3 * c + 1]) * (1.0f / 3.0f);
+  const float cz = (xyz[3 * a + 2] + xyz[3 * b + 2] + xyz[3 * c + 2]) * (1.0f / 3.0f);
+  const uint32_t qx = (uint32_t)fminf(fmaxf((cx - lox) * sx, 0.0f), 1023.0f);
+  const uint32_t qy = (uint32_t)fminf(fmaxf((cy - loy) * sy, 0.0f), 1023.0f);
+  const uint32_t qz = (uint32_t)fminf(fmaxf((cz - loz) * sz, 0.0f), 1023.0f);
+  keys[i] = (spread_bits10(qx) << 2) | (spread_bits10(qy) << 1) | spread_bits10(qz);
+  vals[i] = i;
+}
+
+// ---- stable LSD radix sort, 4-bit digits ----
+
+__global__ void radix_count_kernel(const uint32_t* __restrict__ keys, uint32_t n, int shift,
+                                   uint32_t* __restrict__ counts, uint32_t nblocks) {
+  __shared__ uint32_t h[16];
+  if (threadIdx.x < 16) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kSortTile;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    const uint32_t idx = base + j * kBlock + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 15u], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) counts[threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of m entries by one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) scan_kernel(uint32_t* __restrict__ a, uint32_t m) {
+  __shared__ uint32_t s[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t base = 0; base < m; base += 1024) {
+    const uint32_t idx = base + threadIdx.x;
+    const uint32_t v = idx < m ? a[idx] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const uint32_t add = threadIdx.x >= (uint32_t)o ? s[threadIdx.x - o] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += add;
+      __syncthreads();
+    }
+    const uint32_t incl = s[threadIdx.x];
+    if (idx < m) a[idx] = carry + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += incl;
+    __syncthreads();
+  }
+}
+
+__global__ void radix_scatter_kernel(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n, int shift,
+                                     const uint32_t* __restrict__ offsets, uint32_t nblocks) {
+  __shared__ uint32_t run[16];
+  __shared__ uint32_t wc[kBlock / 64][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < 16) run[threadIdx.x] = offsets[threadIdx.x * nblocks + blockIdx.x];
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  const uint32_t base = blockIdx.x * kSortTile;
+  for (int j = 0; j < kSortItems; ++j) {
+    if (threadIdx.x < kBlock / 64 * 16) wc[threadIdx.x >> 4][threadIdx.x & 15] = 0;
+    __syncthreads();
+    const uint32_t idx = base + j * kBlock + threadIdx.x;
+    const bool valid = idx < n;
+    const uint32_t key = valid ? kin[idx] : 0u;
+    const uint32_t d = (key >> shift) & 15u;
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint64_t bal = __ballot(valid && ((d >> b) & 1u));
+      same &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    const uint32_t rank = __popcll(same & lt_mask);
+    if (valid && rank == 0) wc[wave][d] = __popcll(same);
+    __syncthreads();
+    if (threadIdx.x < 16) {
+      uint32_t r = run[threadIdx.x];
+      for (int w = 0; w < kBlock / 64; ++w) {
+        const uint32_t c = wc[w][threadIdx.x];
+        wc[w][threadIdx.x] = r;
+        r += c;
+      }
+      run[threadIdx.x] = r;
+    }
+    __syncthreads();
+    if (valid) {
+      const uint32_t pos = wc[wave][d] + rank;
+      kout[pos] = key;
+      vout[pos] = vin[idx];
+    }
+    __syncthreads();
+  }
+}
+
+// ---- Karras (2012) binary radix tree over sorted unique keys ----
+
+__device__ __forceinline__ int common_prefix(const uint32_t* __restrict__ k, int n, int i, int j) {
+  if (j < 0 || j >= n) return -1;
+  const uint32_t a = k[i], b = k[j];
+  if (a == b) return 32 + __clz((uint32_t)(i ^ j));
+  return __clz(a ^ b);
+}
+
+__global__ void karras_kernel(const uint32_t* __restrict__ keys, int n, Node* __restrict__ nodes,
+                              int32_t* __restrict__ leaf_parent) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int d = (common_prefix(keys, n, i, i + 1) - common_prefix(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+  const int dmin = common_prefix(keys, n, i, i - d);
+  int lmax = 2;
+  while (common_prefix(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int l = 0;
+  for (int t = lmax >> 1; t >= 1; t >>= 1)
+    if (common_prefix(keys, n, i, i + (l + t) * d) > dmin) l += t;
+  const int j = i + l * d;
+  const int dnode = common_prefix(keys, n, i, j);
+  int s = 0;
+  int div = 2;
+  int t;
+  do {
+    t = (l + div - 1) / div;
+    if (common_prefix(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    div <<= 1;
+  } while (t > 1);
+  const int split = i + s * d + (d < 0 ? -1 : 0);
+  const int lo = i < j ? i : j, hi = i < j ? j : i;
+  int c0, c1;
+  if (lo == split) {
+    c0 = ~split;
+    leaf_parent[split] = i;
+  } else {
+    c0 = split;
+    nodes[split].parent = i;
+  }
+  if (hi == split + 1) {
+    c1 = ~(split + 1);
+    leaf_parent[split + 1] = i;
+  } else {
+    c1 = split + 1;
+    nodes[split + 1].parent = i;
+  }
+  nodes[i].c0 = c0;
+  nodes[i].c1 = c1;
+  if (i == 0) nodes[0].parent = -1;
+}
+
+// Pack triangles in Morton order with their unit normals (computed in FP64).
+__global__ void pack_tris_kernel(const float* __restrict__ xyz, const uint32_t* __restrict__ tri,
+                                 const uint32_t* __restrict__ order, uint32_t nt, TriRec* __restrict__ recs,
+                                 uint32_t* __restrict__ orig) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  const uint32_t id = order[k];
+  const uint32_t a = tri[3 * id], b = tri[3 * id + 1], c = tri[3 * id + 2];
+  TriRec r;
+  r.v0x = xyz[3 * a]; r.v0y = xyz[3 * a + 1]; r.v0z = xyz[3 * a + 2];
+  r.v1x = xyz[3 * b]; r.v1y = xyz[3 * b + 1]; r.v1z = xyz[3 * b + 2];
+  r.v2x = xyz[3 * c]; r.v2y = xyz[3 * c + 1]; r.v2z = xyz[3 * c + 2];
+  const double e1x = (double)r.v1x - r.v0x, e1y = (double)r.v1y - r.v0y, e1z = (double)r.v1z - r.v0z;
+  const double e2x = (double)r.v2x - r.v0x, e2y = (double)r.v2y - r.v0y, e2z = (double)r.v2z - r.v0z;
+  double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  const double len = sqrt(nx * nx + ny * ny + nz * nz);
+  const double inv = len > 0.0 ? 1.0 / len : 0.0;
+  r.nx = (float)(nx * inv);
+  r.ny = (float)(ny * inv);
+  r.nz = (float)(nz * inv);
+  recs[k] = r;
+  orig[k] = id;
+}
+
+__device__ __forceinline__ float ld_relaxed(const float* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void child_box(const Node* nodes, const float* nbox, const TriRec* tris, int c, float b[6]) {
+  if (c < 0) {
+    const TriRec& t = tris[~c];
+    b[0] = fminf(fminf(t.v0x, t.v1x), t.v2x);
+    b[1] = fminf(fminf(t.v0y, t.v1y), t.v2y);
+    b[2] = fminf(fminf(t.v0z, t.v1z), t.v2z);
+    b[3] = fmaxf(fmaxf(t.v0x, t.v1x), t.v2x);
+    b[4] = fmaxf(fmaxf(t.v0y, t.v1y), t.v2y);
+    b[5] = fmaxf(fmaxf(t.v0z, t.v1z), t.v2z);
+  } else {
+    for (int k = 0; k < 6; ++k) b[k] = ld_relaxed(nbox + 6 * c + k);
+  }
+}
+
+// Bottom-up refit: one thread per leaf climbs; the second thread to reach a
+// node writes its children's boxes and continues upward.
+__global__ void refit_kernel(Node* __restrict__ nodes, const int32_t* __restrict__ leaf_parent,
+                             const TriRec* __restrict__ tris, uint32_t nt, uint32_t* __restrict__ flags,
+                             float* __restrict__ nbox) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  int p = leaf_parent[k];
+  for (int level = 0; p >= 0 && level < 4096; ++level) {  // bounded climb
+    __threadfence();
+    if (atomicAdd(&flags[p], 1u) == 0u) return;
+    __threadfence();
+    const int c0 = __hip_atomic_load(&nodes[p].c0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int c1 = __hip_atomic_load(&nodes[p].c1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    float b0[6], b1[6];
+    child_box(nodes, nbox, tris, c0, b0);
+    child_box(nodes, nbox, tris, c1, b1);
+    Node& nd = nodes[p];
+    nd.lo0x = b0[0]; nd.lo0y = b0[1]; nd.lo0z = b0[2]; nd.hi0x = b0[3]; nd.hi0y = b0[4]; nd.hi0z = b0[5];
+    nd.lo1x = b1[0]; nd.lo1y = b1[1]; nd.lo1z = b1[2]; nd.hi1x = b1[3]; nd.hi1y = b1[4]; nd.hi1z = b1[5];
+    for (int q = 0; q < 3; ++q) {
+      __hip_atomic_store(nbox + 6 * p + q, fminf(b0[q], b1[q]), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(nbox + 6 * p + 3 + q, fmaxf(b0[3 + q], b1[3 + q]), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    p = __hip_atomic_load(&nodes[p].parent, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Depth of every leaf (root = depth 0), maximum kept.
+__global__ void depth_kernel(const Node* __restrict__ nodes, const int32_t* __restrict__ leaf_parent, uint32_t nt,
+                             uint32_t* __restrict__ max_depth) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nt) return;
+  uint32_t dpt = 0;
+  int p = leaf_parent[k];
+  while (p >= 0 && dpt < 4096) {  // bounded climb
+    ++dpt;
+    p = nodes[p].parent;
+  }
+  atomicMax(max_depth, dpt);
+}
+
+// One-triangle mesh: a single node whose two links both name leaf 0.
+__global__ void single_node_kernel(Node* nodes, const TriRec* tris) {
+  const TriRec& t = tris[0];
+  Node nd;
+  nd.lo0x = nd.lo1x = fminf(fminf(t.v0x, t.v1x), t.v2x);
+  nd.lo0y = nd.lo1y = fminf(fminf(t.v0y, t.v1y), t.v2y);
+  nd.lo0z = nd.lo1z = fminf(fminf(t.v0z, t.v1z), t.v2z);
+  nd.hi0x = nd.hi1x = fmaxf(fmaxf(t.v0x, t.v1x), t.v2x);
+  nd.hi0y = nd.hi1y = fmaxf(fmaxf(t.v0y, t.v1y), t.v2y);
+  nd.hi0z = nd.hi1z = fmaxf(fmaxf(t.v0z, t.v1z), t.v2z);
+  nd.c0 = ~0;
+  nd.c1 = ~0;
+  nd.parent = -1;
+  nd.pad = 0;
+  nodes[0] = nd;
+}
+
+}  // namespace
+
+size_t bvh_scratch_bytes(uint64_t nt) {
+  const uint64_t nblocks = (nt + kSortTile - 1) / kSortTile;
+  // xyz/tri copies are separate; here: keys x2, vals x2, counts, leaf_parent, flags, nbox, depth
+  return (4 * nt + 16 * nblocks + 2 * nt + 6 * nt + 64) * sizeof(uint32_t) + 4096;
+}
+
+hipError_t build_bvh(const float* d_xyz, const uint32_t* d_tri, uint64_t nt64, const float box_lo[3],
+                     const float box_hi[3], void* scratch, Node* d_nodes, TriRec* d_tris, uint32_t* d_orig,
+                     uint32_t* h_depth, hipStream_t st) {
+  const uint32_t nt = (uint32_t)nt64;
+  const uint32_t nblocks = (nt + kSortTile - 1) / kSortTile;
+  uint32_t* k0 = static_cast<uint32_t*>(scratch);
+  uint32_t* v0 = k0 + nt;
+  uint32_t* k1 = v0 + nt;
+  uint32_t* v1 = k1 + nt;
+  uint32_t* counts = v1 + nt;
+  int32_t* leaf_parent = reinterpret_cast<int32_t*>(counts + 16 * nblocks);
+  uint32_t* flags = reinterpret_cast<uint32_t*>(leaf_parent + nt);
+  float* nbox = reinterpret_cast<float*>(flags + nt);
+  uint32_t* depth = reinterpret_cast<uint32_t*>(nbox + 6 * nt);
+
+  float ext[3], sc[3];
+  for (int k = 0; k < 3; ++k) {
+    ext[k] = box_hi[k] - box_lo[k];
+    sc[k] = ext[k] > 0.0f ? 1024.0f / ext[k] : 0.0f;
+  }
+  const uint32_t g = (nt + kBlock - 1) / kBlock;
+  morton_kernel<<<g, kBlock, 0, st>>>(d_xyz, d_tri, nt, box_lo[0], box_lo[1], box_lo[2], sc[0], sc[1], sc[2], k0, v0);
+  for (int shift = 0; shift < 30; shift += 4) {
+    radix_count_kernel<<<nblocks, kBlock, 0, st>>>(k0, nt, shift, counts, nblocks);
+    scan_kernel<<<1, 1024, 0, st>>>(counts, 16 * nblocks);
+    radix_scatter_kernel<<<nblocks, kBlock, 0, st>>>(k0, v0, k1, v1, nt, shift, counts, nblocks);
+    uint32_t* t = k0; k0 = k1; k1 = t;
+    t = v0; v0 = v1; v1 = t;
+  }
+  pack_tris_kernel<<<g, kBlock, 0, st>>>(d_xyz, d_tri, v0, nt, d_tris, d_orig);
+  hipError_t e;
+  if (nt == 1) {
+    single_node_kernel<<<1, 1, 0, st>>>(d_nodes, d_tris);
+    *h_depth = 1;
+    e = hipStreamSynchronize(st);
+    return e != hipSuccess ? e : hipGetLastError();
+  }
+  zero_u32(flags, nt, st);
+  zero_u32(depth, 1, st);
+  e = hipMemsetAsync(leaf_parent, 0xFF, nt * sizeof(int32_t), st);  // -1: no parent yet
+  if (e != hipSuccess) return e;
+  const uint32_t gi = (nt - 1 + kBlock - 1) / kBlock;
+  karras_kernel<<<gi, kBlock, 0, st>>>(k0, (int)nt, d_nodes, leaf_parent);
+  refit_kernel<<<g, kBlock, 0, st>>>(d_nodes, leaf_parent, d_tris, nt, flags, nbox);
+  depth_kernel<<<g, kBlock, 0, st>>>(d_nodes, leaf_parent, nt, depth);
+  e = hipMemcpyAsync(h_depth, depth, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+}  // namespace tpmc

@@ -1,0 +1,804 @@
+// tpmc_capi.hip -- host side of the libtpmc C ABI (include/tpmc.h): argument
+// validation, per-query FP64 set-up (a1), workspace layout, kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tpmc.h"
+#include "tpmc_internal.h"
+#include "tpmc_launch.h"
+
+using namespace tpmc;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static tpmc_status fail(tpmc_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                              \
+  do {                                                                                             \
+    hipError_t e_ = (expr);                                                                        \
+    if (e_ != hipSuccess) return fail(TPMC_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));      \
+  } while (0)
+
+#define HIP_CHECK_LAUNCH(what)                                                                     \
+  do {                                                                                             \
+    hipError_t e_ = hipGetLastError();                                                             \
+    if (e_ != hipSuccess) return fail(TPMC_E_DEVICE, "%s launch: %s", what, hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// handles
+// ---------------------------------------------------------------------------
+struct tpmc_ctx_s {
+  int device;
+  hipStream_t stream;
+  hipStream_t capture_stream;
+  int n_cu;
+};
+
+struct tpmc_mesh_s {
+  tpmc_ctx ctx;
+  uint64_t nv, nt;
+  uint32_t depth;
+  int stack_slots;
+  Node* nodes;
+  TriRec* tris;
+  uint32_t* orig;
+  std::vector<float> host_xyz;  // for control-volume checks
+  double lo[3], hi[3], c0[3], r;
+  uint64_t device_bytes;
+};
+
+struct Layout {
+  QueryDev* qs;
+  ResultDev* res;
+  long long* scal;
+  long long* tally;
+  uint64_t* tile_end;
+  uint32_t* counter;
+  float* planes[6];
+  uint64_t bytes;
+};
+
+struct tpmc_particles_s {
+  tpmc_ctx ctx;
+  tpmc_mesh mesh;
+  uint32_t nq;
+  std::vector<QueryDev> hq;
+  Layout lay;
+  uint64_t n_total;
+};
+
+struct tpmc_tally_s {
+  tpmc_particles p;
+};
+
+struct tpmc_batch_s {
+  tpmc_ctx ctx;
+  tpmc_mesh mesh;
+  uint32_t nq;
+  std::vector<QueryDev> hq;
+  std::vector<uint64_t> tile_end;
+  Layout lay;
+  uint64_t total_tiles;
+  uint64_t tally_words;
+  TallyMode mode;
+  int grid;
+  hipGraphExec_t exec;
+  bool launched;
+};
+
+// ---------------------------------------------------------------------------
+// validation and per-query set-up
+// ---------------------------------------------------------------------------
+static bool finite3(const double* v) { return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]); }
+
+extern "C" tpmc_status tpmc_check_mesh(const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt) {
+  if (!xyz || !tri) return fail(TPMC_E_INVALID, "mesh arrays must not be NULL");
+  if (nt == 0) return fail(TPMC_E_MESH, "mesh has no triangles");
+  if (nv == 0) return fail(TPMC_E_MESH, "mesh has no vertices");
+  if (nt >= (1ull << 30)) return fail(TPMC_E_MESH, "mesh has too many triangles (%llu)", (unsigned long long)nt);
+  for (uint64_t i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(xyz[i])) return fail(TPMC_E_MESH, "vertex %llu is not finite", (unsigned long long)(i / 3));
+  for (uint64_t i = 0; i < 3 * nt; ++i)
+    if (tri[i] >= nv)
+      return fail(TPMC_E_MESH, "triangle %llu names vertex %u >= nv = %llu", (unsigned long long)(i / 3), tri[i],
+                  (unsigned long long)nv);
+  return TPMC_OK;
+}
+
+static void bounding_sphere(const float* xyz, uint64_t nv, double lo[3], double hi[3], double c0[3], double* r) {
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = INFINITY;
+    hi[k] = -INFINITY;
+  }
+  for (uint64_t i = 0; i < nv; ++i)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::fmin(lo[k], (double)xyz[3 * i + k]);
+      hi[k] = std::fmax(hi[k], (double)xyz[3 * i + k]);
+    }
+  for (int k = 0; k < 3; ++k) c0[k] = 0.5 * (lo[k] + hi[k]);
+  double rr = 0.0;
+  for (uint64_t i = 0; i < nv; ++i) {
+    const double a = xyz[3 * i] - c0[0], b = xyz[3 * i + 1] - c0[1], c = xyz[3 * i + 2] - c0[2];
+    rr = std::fmax(rr, std::sqrt(a * a + b * b + c * c));
+  }
+  *r = rr * (1.0 + 1e-3);
+}
+
+static tpmc_status check_query_fields(const tpmc_query* q) {
+  if (!q) return fail(TPMC_E_INVALID, "query is NULL");
+  const double n2 = q->q_wxyz[0] * q->q_wxyz[0] + q->q_wxyz[1] * q->q_wxyz[1] + q->q_wxyz[2] * q->q_wxyz[2] +
+                    q->q_wxyz[3] * q->q_wxyz[3];
+  if (!std::isfinite(n2) || std::fabs(std::sqrt(n2) - 1.0) > 1e-6)
+    return fail(TPMC_E_INVALID, "attitude quaternion must have unit norm (|q| = %g)", std::sqrt(n2));
+  if (!std::isfinite(q->S) || q->S < 0.0 || q->S > 100.0)
+    return fail(TPMC_E_INVALID, "speed ratio S = %g outside [0, 100]", q->S);
+  if (!std::isfinite(q->T_inf) || !(q->T_inf > 0.0) || !std::isfinite(q->T_w) || !(q->T_w > 0.0))
+    return fail(TPMC_E_INVALID, "temperatures must be finite and > 0 (T_inf = %g, T_w = %g)", q->T_inf, q->T_w);
+  if (!std::isfinite(q->alpha) || q->alpha < 0.0 || q->alpha > 1.0)
+    return fail(TPMC_E_INVALID, "accommodation alpha = %g outside [0, 1]", q->alpha);
+  if (q->n_particles == 0 || q->n_particles > (1ull << 40))
+    return fail(TPMC_E_INVALID, "n_particles = %llu outside [1, 2^40]", (unsigned long long)q->n_particles);
+  if (q->max_reflections == 0 || q->max_reflections > (uint32_t)kMaxReflections)
+    return fail(TPMC_E_INVALID, "max_reflections = %u outside [1, %d]", q->max_reflections, kMaxReflections);
+  if (q->flags & ~TPMC_Q_NO_TRIANGLE_TALLY) return fail(TPMC_E_INVALID, "unknown query flags 0x%x", q->flags);
+  if (!finite3(q->cv_center) || !std::isfinite(q->cv_radius))
+    return fail(TPMC_E_INVALID, "control volume must be finite");
+  return TPMC_OK;
+}
+
+static tpmc_status check_cv(const tpmc_query* q, const float* xyz, uint64_t nv) {
+  if (!(q->cv_radius > 0.0)) return TPMC_OK;
+  double worst = 0.0;
+  for (uint64_t i = 0; i < nv; ++i) {
+    const double a = xyz[3 * i] - q->cv_center[0], b = xyz[3 * i + 1] - q->cv_center[1],
+                 c = xyz[3 * i + 2] - q->cv_center[2];
+    worst = std::fmax(worst, std::sqrt(a * a + b * b + c * c));
+  }
+  if (worst > q->cv_radius)
+    return fail(TPMC_E_CV, "control volume (radius %g) does not enclose the mesh (farthest vertex at %g)",
+                q->cv_radius, worst);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_check_query(const tpmc_query* q, const float* xyz, uint64_t nv) {
+  tpmc_status s = check_query_fields(q);
+  if (s != TPMC_OK) return s;
+  if (!xyz && q->cv_radius > 0.0) return fail(TPMC_E_INVALID, "vertices needed for the control-volume check");
+  return xyz ? check_cv(q, xyz, nv) : TPMC_OK;
+}
+
+static double pow2_floor(double v) { return std::ldexp(1.0, (int)std::floor(std::log2(v))); }
+
+// a1: FP64 constants of one query (Sec. II.B, III.A.1, III.A.3).
+static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
+  std::memset(q, 0, sizeof *q);
+  double w = in->q_wxyz[0], x = in->q_wxyz[1], y = in->q_wxyz[2], z = in->q_wxyz[3];
+  const double n = std::sqrt(w * w + x * x + y * y + z * z);
+  w /= n; x /= n; y /= n; z /= n;
+  // rows of the body->wind rotation: free stream U, seeding tangents e1, e2
+  const double U[3] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)};
+  const double e1[3] = {2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)};
+  const double e2[3] = {2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+  for (int k = 0; k < 3; ++k) {
+    q->U[k] = U[k];
+    q->e1[k] = e1[k];
+    q->e2[k] = e2[k];
+    q->Uf[k] = (float)U[k];
+  }
+  if (in->cv_radius > 0.0) {
+    for (int k = 0; k < 3; ++k) q->c0[k] = in->cv_center[k];
+    q->r = in->cv_radius;
+  } else {
+    for (int k = 0; k < 3; ++k) q->c0[k] = m->c0[k];
+    q->r = m->r;
+  }
+  for (int k = 0; k < 3; ++k) q->c0f[k] = (float)q->c0[k];
+  const double S = in->S;
+  q->S = S;
+  q->s_zero = S < 1e-8 ? 1u : 0u;
+  const double sqrtpi = 1.77245385090551602730, pi = 3.14159265358979323846;
+  q->erfS = std::erf(S);
+  q->erfcS = std::erfc(S);
+  q->expmS2 = std::exp(-S * S);
+  // Z(S) = e^{-S^2} + sqrt(pi) (S + 1/(2S)) erf S; Gamma/(n c_mp) = sqrt(pi) r^2 Z (Sec. III.A.1)
+  q->Z = q->s_zero ? 2.0 : q->expmS2 + sqrtpi * (S + 0.5 / S) * q->erfS;
+  q->Gamma_hat = q->s_zero ? 2.0 * sqrtpi * q->r * q->r
+                           : (sqrtpi * q->expmS2 + (pi / (2.0 * S) + pi * S) * q->erfS) * q->r * q->r;
+  const double tau = std::sqrt(in->T_w / in->T_inf);
+  q->tau = (float)tau;
+  q->alpha = (float)in->alpha;
+  q->N = in->n_particles;
+  q->key0 = (uint32_t)in->seed;
+  q->key1 = (uint32_t)(in->seed >> 32);
+  q->rmax = in->max_reflections;
+  q->per_tri = (in->flags & TPMC_Q_NO_TRIANGLE_TALLY) ? 0u : 1u;
+  // Fixed point: every sampled speed is bounded (the variates never reach 0 or 1),
+  // |w| <= S + 15 for seeded and specular velocities and |w| <= 8 tau after a
+  // diffuse re-emission, so one hit moves at most Dmax; scales are the largest
+  // powers of two keeping N * rmax hits of Dmax inside 2^62.
+  const double Dmax = 2.0 * std::fmax(S + 15.0, 8.0 * tau);
+  const double hits_max = (double)in->n_particles * (double)in->max_reflections;
+  const double sF = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax)), std::ldexp(1.0, 50));
+  const double sL = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax * q->r * 1.01)), std::ldexp(1.0, 50));
+  const double pD = (double)in->max_reflections * Dmax;
+  const double sD2 = std::fmin(pow2_floor(std::ldexp(1.0, 62) / ((double)in->n_particles * pD * pD)),
+                               std::ldexp(1.0, 50));
+  q->scaleF = (float)sF;
+  q->scaleL = (float)sL;
+  q->scaleD = (float)sF;
+  q->scaleD2 = (float)sD2;
+  q->inv_scaleF = 1.0 / sF;
+  q->inv_scaleL = 1.0 / sL;
+  q->inv_scaleD = 1.0 / sF;
+  q->inv_scaleD2 = 1.0 / sD2;
+}
+
+static tpmc_status make_queries(tpmc_mesh m, const tpmc_query* q, uint32_t nq, std::vector<QueryDev>& out) {
+  if (!q || nq == 0) return fail(TPMC_E_INVALID, "need at least one query");
+  out.resize(nq);
+  for (uint32_t i = 0; i < nq; ++i) {
+    tpmc_status s = check_query_fields(&q[i]);
+    if (s != TPMC_OK) return fail(s, "query %u: %s", i, g_err.c_str());
+    s = check_cv(&q[i], m->host_xyz.data(), m->nv);
+    if (s != TPMC_OK) return fail(s, "query %u: %s", i, g_err.c_str());
+    setup_query(&q[i], m, &out[i]);
+  }
+  return TPMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+static uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
+
+// Lays out [queries | results | scalar blocks | tallies | tile map | counter | 6 planes].
+static void layout(std::vector<QueryDev>& hq, uint64_t nt, uint64_t n_planes, bool batch, uint8_t* base, Layout& L) {
+  const uint64_t nq = hq.size();
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) {
+    const uint64_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const uint64_t o_q = take(nq * sizeof(QueryDev));
+  const uint64_t o_r = take(nq * sizeof(ResultDev));
+  const uint64_t o_s = take(nq * kScalarSlots * sizeof(long long));
+  uint64_t words = 0;
+  for (uint64_t i = 0; i < nq; ++i) {
+    hq[i].scalar_offset = i * kScalarSlots;
+    hq[i].tally_offset = words;
+    if (hq[i].per_tri) words += nt * 7;
+  }
+  const uint64_t o_t = take(words * sizeof(long long));
+  const uint64_t o_te = take(batch ? nq * sizeof(uint64_t) : 0);
+  const uint64_t o_c = take(batch ? 64 : 0);
+  uint64_t o_p[6];
+  for (int k = 0; k < 6; ++k) o_p[k] = take(n_planes * sizeof(float));
+  L.bytes = off;
+  L.qs = reinterpret_cast<QueryDev*>(base + o_q);
+  L.res = reinterpret_cast<ResultDev*>(base + o_r);
+  L.scal = reinterpret_cast<long long*>(base + o_s);
+  L.tally = reinterpret_cast<long long*>(base + o_t);
+  L.tile_end = reinterpret_cast<uint64_t*>(base + o_te);
+  L.counter = reinterpret_cast<uint32_t*>(base + o_c);
+  for (int k = 0; k < 6; ++k) L.planes[k] = reinterpret_cast<float*>(base + o_p[k]);
+}
+
+static uint64_t total_particles(const std::vector<QueryDev>& hq) {
+  uint64_t n = 0;
+  for (const auto& q : hq) n += q.N;
+  return n;
+}
+
+static TallyMode plain_mode(const QueryDev& q, uint64_t nt) {
+  if (!q.per_tri) return kTallyTotals;
+  if (nt <= (uint64_t)kWaveTallyMaxTris) return kTallyWave;
+  if (nt <= (uint64_t)kLdsTallyMaxTris) return kTallyLds;
+  return kTallyGlobal;
+}
+
+// ---------------------------------------------------------------------------
+// context and mesh
+// ---------------------------------------------------------------------------
+extern "C" const char* tpmc_last_error(void) { return g_err.c_str(); }
+extern "C" int tpmc_abi_version(void) { return TPMC_ABI_VERSION; }
+
+extern "C" tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out) {
+  if (!out) return fail(TPMC_E_INVALID, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  HIP_TRY(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(TPMC_E_INVALID, "device %d not present (%d devices)", device, count);
+  HIP_TRY(hipSetDevice(device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device));
+  tpmc_ctx c = new (std::nothrow) tpmc_ctx_s;
+  if (!c) return fail(TPMC_E_INVALID, "out of host memory");
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->capture_stream = nullptr;
+  c->n_cu = prop.multiProcessorCount;
+  *out = c;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_set_stream(tpmc_ctx ctx, void* hip_stream) {
+  if (!ctx) return fail(TPMC_E_INVALID, "ctx is NULL");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return TPMC_OK;
+}
+
+extern "C" void tpmc_destroy_ctx(tpmc_ctx ctx) {
+  if (!ctx) return;
+  if (ctx->capture_stream) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamDestroy(ctx->capture_stream);
+  }
+  delete ctx;
+}
+
+extern "C" tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
+                                       tpmc_mesh* out) {
+  if (!ctx || !out) return fail(TPMC_E_INVALID, "ctx and out must not be NULL");
+  *out = nullptr;
+  tpmc_status s = tpmc_check_mesh(xyz, nv, tri, nt);
+  if (s != TPMC_OK) return s;
+  HIP_TRY(hipSetDevice(ctx->device));
+  tpmc_mesh m = new (std::nothrow) tpmc_mesh_s;
+  if (!m) return fail(TPMC_E_INVALID, "out of host memory");
+  m->ctx = ctx;
+  m->nv = nv;
+  m->nt = nt;
+  m->host_xyz.assign(xyz, xyz + 3 * nv);
+  bounding_sphere(xyz, nv, m->lo, m->hi, m->c0, &m->r);
+  m->nodes = nullptr;
+  m->tris = nullptr;
+  m->orig = nullptr;
+  const uint64_t nnodes = nt > 1 ? nt - 1 : 1;
+  float* d_xyz = nullptr;
+  uint32_t* d_tri = nullptr;
+  void* scratch = nullptr;
+  hipError_t e = hipMalloc(&d_xyz, 3 * nv * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&d_tri, 3 * nt * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMalloc(&scratch, bvh_scratch_bytes(nt));
+  if (e == hipSuccess) e = hipMalloc(&m->nodes, nnodes * sizeof(Node));
+  if (e == hipSuccess) e = hipMalloc(&m->tris, nt * sizeof(TriRec));
+  if (e == hipSuccess) e = hipMalloc(&m->orig, nt * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_xyz, xyz, 3 * nv * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_tri, tri, 3 * nt * sizeof(uint32_t), hipMemcpyHostToDevice, ctx->stream);
+  uint32_t depth = 0;
+  if (e == hipSuccess) {
+    const float lo[3] = {(float)m->lo[0], (float)m->lo[1], (float)m->lo[2]};
+    const float hi[3] = {(float)m->hi[0], (float)m->hi[1], (float)m->hi[2]};
+    e = build_bvh(d_xyz, d_tri, nt, lo, hi, scratch, m->nodes, m->tris, m->orig, &depth, ctx->stream);
+  }
+  if (d_xyz) (void)hipFree(d_xyz);
+  if (d_tri) (void)hipFree(d_tri);
+  if (scratch) (void)hipFree(scratch);
+  if (e != hipSuccess) {
+    tpmc_destroy_mesh(m);
+    return fail(TPMC_E_DEVICE, "BVH build: %s", hipGetErrorString(e));
+  }
+  m->depth = depth;
+  m->stack_slots = stack_slots_for_depth(depth);
+  if (m->stack_slots == 0) {
+    tpmc_destroy_mesh(m);
+    return fail(TPMC_E_MESH, "BVH depth %u exceeds the supported 64 levels", depth);
+  }
+  m->device_bytes = nnodes * sizeof(Node) + nt * (sizeof(TriRec) + sizeof(uint32_t));
+  *out = m;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_get_mesh_info(tpmc_mesh m, tpmc_mesh_info* out) {
+  if (!m || !out) return fail(TPMC_E_INVALID, "mesh and out must not be NULL");
+  out->nv = m->nv;
+  out->nt = m->nt;
+  out->depth = m->depth;
+  out->stack_slots = (uint32_t)m->stack_slots;
+  for (int k = 0; k < 3; ++k) {
+    out->box_lo[k] = m->lo[k];
+    out->box_hi[k] = m->hi[k];
+    out->sphere_center[k] = m->c0[k];
+  }
+  out->sphere_radius = m->r;
+  out->device_bytes = m->device_bytes;
+  return TPMC_OK;
+}
+
+extern "C" void tpmc_destroy_mesh(tpmc_mesh m) {
+  if (!m) return;
+  (void)hipSetDevice(m->ctx->device);
+  if (m->nodes) (void)hipFree(m->nodes);
+  if (m->tris) (void)hipFree(m->tris);
+  if (m->orig) (void)hipFree(m->orig);
+  delete m;
+}
+
+// ---------------------------------------------------------------------------
+// plain path: seed -> trace -> forces
+// ---------------------------------------------------------------------------
+static tpmc_status check_ws(void* ws, uint64_t ws_bytes, uint64_t need) {
+  if (!ws) return fail(TPMC_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(TPMC_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(TPMC_E_WORKSPACE, "workspace of %llu bytes is smaller than the %llu needed",
+                (unsigned long long)ws_bytes, (unsigned long long)need);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_workspace_bytes(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq,
+                                            uint64_t* bytes) {
+  if (!ctx || !m || !bytes) return fail(TPMC_E_INVALID, "ctx, mesh and bytes must not be NULL");
+  std::vector<QueryDev> hq;
+  tpmc_status s = make_queries(m, q, nq, hq);
+  if (s != TPMC_OK) return s;
+  Layout L;
+  layout(hq, m->nt, total_particles(hq), false, nullptr, L);
+  *bytes = L.bytes;
+  return TPMC_OK;
+}
+
+static int seed_grid(tpmc_ctx ctx, uint64_t n) {
+  const uint64_t g = (n + kBlock - 1) / kBlock;
+  const uint64_t cap = (uint64_t)ctx->n_cu * 16;
+  return (int)(g < cap ? (g ? g : 1) : cap);
+}
+
+extern "C" tpmc_status tpmc_seed(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq, void* ws,
+                                 uint64_t ws_bytes, tpmc_particles* out) {
+  if (!ctx || !m || !out) return fail(TPMC_E_INVALID, "ctx, mesh and out must not be NULL");
+  *out = nullptr;
+  if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
+  tpmc_particles p = new (std::nothrow) tpmc_particles_s;
+  if (!p) return fail(TPMC_E_INVALID, "out of host memory");
+  tpmc_status s = make_queries(m, q, nq, p->hq);
+  if (s != TPMC_OK) {
+    delete p;
+    return s;
+  }
+  p->ctx = ctx;
+  p->mesh = m;
+  p->nq = nq;
+  p->n_total = total_particles(p->hq);
+  uint64_t off = 0;
+  for (auto& hq : p->hq) {
+    hq.p_offset = off;
+    off += hq.N;
+  }
+  layout(p->hq, m->nt, p->n_total, false, static_cast<uint8_t*>(ws), p->lay);
+  s = check_ws(ws, ws_bytes, p->lay.bytes);
+  if (s != TPMC_OK) {
+    delete p;
+    return s;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(p->lay.qs, p->hq.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice, ctx->stream);
+  if (e != hipSuccess) {
+    delete p;
+    return fail(TPMC_E_DEVICE, "query upload: %s", hipGetErrorString(e));
+  }
+  uint64_t words = 0;
+  for (const auto& hq : p->hq) words += hq.per_tri ? m->nt * 7 : 0;
+  zero_i64(p->lay.scal, (uint64_t)nq * kScalarSlots, ctx->stream);
+  zero_i64(p->lay.tally, words, ctx->stream);
+  for (uint32_t i = 0; i < nq; ++i) {
+    const QueryDev& hq = p->hq[i];
+    float* const x[3] = {p->lay.planes[0] + hq.p_offset, p->lay.planes[1] + hq.p_offset,
+                         p->lay.planes[2] + hq.p_offset};
+    float* const w[3] = {p->lay.planes[3] + hq.p_offset, p->lay.planes[4] + hq.p_offset,
+                         p->lay.planes[5] + hq.p_offset};
+    launch_seed(p->lay.qs + i, hq.N, x, w, seed_grid(ctx, hq.N), ctx->stream);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete p;
+    return fail(TPMC_E_DEVICE, "seed launch: %s", hipGetErrorString(e));
+  }
+  *out = p;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_particles_planes(tpmc_particles p, float* dev_planes[6], uint64_t* n_total) {
+  if (!p || !dev_planes) return fail(TPMC_E_INVALID, "particles and planes must not be NULL");
+  for (int k = 0; k < 6; ++k) dev_planes[k] = p->lay.planes[k];
+  if (n_total) *n_total = p->n_total;
+  return TPMC_OK;
+}
+
+static int trace_grid(tpmc_ctx ctx, uint64_t n) {
+  const uint64_t g = (n + kBlock - 1) / kBlock;
+  const uint64_t cap = (uint64_t)ctx->n_cu * 8;
+  return (int)(g < cap ? (g ? g : 1) : cap);
+}
+
+extern "C" tpmc_status tpmc_trace_ex(tpmc_ctx ctx, tpmc_mesh m, tpmc_particles p, int32_t* dev_first_tri,
+                                     uint64_t* dev_counters, tpmc_tally* out) {
+  if (!ctx || !m || !p || !out) return fail(TPMC_E_INVALID, "ctx, mesh, particles and out must not be NULL");
+  *out = nullptr;
+  if (p->mesh != m || p->ctx != ctx) return fail(TPMC_E_BUSY, "particles were seeded for another mesh or context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  for (uint32_t i = 0; i < p->nq; ++i) {
+    const QueryDev& hq = p->hq[i];
+    TraceArgs a;
+    a.nodes = m->nodes;
+    a.tris = m->tris;
+    a.orig = m->orig;
+    a.q = p->lay.qs + i;
+    for (int k = 0; k < 3; ++k) {
+      a.x[k] = p->lay.planes[k] + hq.p_offset;
+      a.w[k] = p->lay.planes[3 + k] + hq.p_offset;
+    }
+    a.n = hq.N;
+    a.tally = hq.per_tri ? p->lay.tally + hq.tally_offset : nullptr;
+    a.scal = p->lay.scal + hq.scalar_offset;
+    a.first_tri = dev_first_tri ? dev_first_tri + hq.p_offset : nullptr;
+    a.counters = reinterpret_cast<unsigned long long*>(dev_counters);
+    a.nt = (uint32_t)m->nt;
+    launch_trace(a, m->stack_slots, plain_mode(hq, m->nt), trace_grid(ctx, hq.N), ctx->stream);
+    HIP_CHECK_LAUNCH("trace");
+  }
+  tpmc_tally t = new (std::nothrow) tpmc_tally_s;
+  if (!t) return fail(TPMC_E_INVALID, "out of host memory");
+  t->p = p;
+  *out = t;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_trace(tpmc_ctx ctx, tpmc_mesh m, tpmc_particles p, tpmc_tally* out) {
+  return tpmc_trace_ex(ctx, m, p, nullptr, nullptr, out);
+}
+
+static void copy_result(const ResultDev& r, tpmc_result* o) {
+  for (int k = 0; k < 3; ++k) {
+    o->F_over_q[k] = r.F_over_q[k];
+    o->M_over_q[k] = r.M_over_q[k];
+    o->Fhat[k] = r.Fhat[k];
+  }
+  o->CD = r.CD;
+  o->CD_sigma = r.CD_sigma;
+  o->Gamma_hat = r.Gamma_hat;
+  o->rays = r.rays;
+  o->hits = r.hits;
+  o->segments = r.segments;
+  o->missed = r.missed;
+  o->escaped = r.escaped;
+  o->capped = r.capped;
+}
+
+// Clears the per-query totals the reduction writes (slots kFx..kCount).
+static void clear_totals(long long* scal, uint32_t nq, const std::vector<QueryDev>& hq, hipStream_t st) {
+  for (uint32_t i = 0; i < nq; ++i)
+    if (hq[i].per_tri) zero_i64(scal + hq[i].scalar_offset + kFx, 7, st);
+}
+
+static tpmc_status finalize_results(tpmc_ctx ctx, const Layout& L, uint32_t nq, const double ref_point[3],
+                                    double A_ref, tpmc_result* out) {
+  const double xr = ref_point ? ref_point[0] : 0.0, yr = ref_point ? ref_point[1] : 0.0,
+               zr = ref_point ? ref_point[2] : 0.0;
+  launch_finalize(L.qs, L.scal, nq, xr, yr, zr, A_ref, L.res, ctx->stream);
+  HIP_CHECK_LAUNCH("finalize");
+  std::vector<ResultDev> hr(nq);
+  HIP_TRY(hipMemcpyAsync(hr.data(), L.res, nq * sizeof(ResultDev), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (uint32_t i = 0; i < nq; ++i) copy_result(hr[i], out + i);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_forces(tpmc_ctx ctx, tpmc_tally t, const double ref_point[3], double A_ref,
+                                   tpmc_result* out) {
+  if (!ctx || !t || !out) return fail(TPMC_E_INVALID, "ctx, tally and out must not be NULL");
+  if (!(A_ref > 0.0) || !std::isfinite(A_ref)) return fail(TPMC_E_INVALID, "A_ref = %g must be > 0", A_ref);
+  if (ref_point && !finite3(ref_point)) return fail(TPMC_E_INVALID, "reference point must be finite");
+  tpmc_particles p = t->p;
+  if (p->ctx != ctx) return fail(TPMC_E_BUSY, "tally belongs to another context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  clear_totals(p->lay.scal, p->nq, p->hq, ctx->stream);
+  for (uint32_t i = 0; i < p->nq; ++i)
+    if (p->hq[i].per_tri)
+      launch_reduce(p->lay.tally + p->hq[i].tally_offset, (uint32_t)p->mesh->nt,
+                    p->lay.scal + p->hq[i].scalar_offset, ctx->stream);
+  HIP_CHECK_LAUNCH("reduce");
+  return finalize_results(ctx, p->lay, p->nq, ref_point, A_ref, out);
+}
+
+extern "C" tpmc_status tpmc_tally_copy(tpmc_ctx ctx, tpmc_tally t, uint32_t query, double* host_per_tri) {
+  if (!ctx || !t || !host_per_tri) return fail(TPMC_E_INVALID, "ctx, tally and output must not be NULL");
+  tpmc_particles p = t->p;
+  if (query >= p->nq) return fail(TPMC_E_INVALID, "query %u >= nq = %u", query, p->nq);
+  const QueryDev& q = p->hq[query];
+  if (!q.per_tri) return fail(TPMC_E_INVALID, "query %u keeps no per-triangle tallies", query);
+  const uint64_t nt = p->mesh->nt;
+  std::vector<long long> raw(nt * 7);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemcpyAsync(raw.data(), p->lay.tally + q.tally_offset, nt * 7 * sizeof(long long),
+                         hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (uint64_t k = 0; k < nt; ++k) {
+    double F[3], L[3];
+    for (int c = 0; c < 3; ++c) {
+      F[c] = (double)raw[7 * k + c] * q.inv_scaleF;
+      L[c] = (double)raw[7 * k + 3 + c] * q.inv_scaleL;
+    }
+    // moment about the body origin: (p - c0) x dw + c0 x dw
+    double* o = host_per_tri + 7 * k;
+    o[0] = F[0];
+    o[1] = F[1];
+    o[2] = F[2];
+    o[3] = L[0] + (q.c0[1] * F[2] - q.c0[2] * F[1]);
+    o[4] = L[1] + (q.c0[2] * F[0] - q.c0[0] * F[2]);
+    o[5] = L[2] + (q.c0[0] * F[1] - q.c0[1] * F[0]);
+    o[6] = (double)raw[7 * k + 6];
+  }
+  return TPMC_OK;
+}
+
+extern "C" void tpmc_destroy_particles(tpmc_particles p) { delete p; }
+extern "C" void tpmc_destroy_tally(tpmc_tally t) { delete t; }
+
+// ---------------------------------------------------------------------------
+// batched path
+// ---------------------------------------------------------------------------
+static constexpr uint64_t kBatchTile = 4096;  // must equal the batch kernel's tile
+
+static tpmc_status batch_prepare(tpmc_mesh m, const tpmc_query* q, uint32_t nq, std::vector<QueryDev>& hq,
+                                 std::vector<uint64_t>& tile_end, Layout& L, uint8_t* base) {
+  tpmc_status s = make_queries(m, q, nq, hq);
+  if (s != TPMC_OK) return s;
+  tile_end.resize(nq);
+  uint64_t acc = 0;
+  for (uint32_t i = 0; i < nq; ++i) {
+    acc += (hq[i].N + kBatchTile - 1) / kBatchTile;
+    tile_end[i] = acc;
+  }
+  layout(hq, m->nt, 0, true, base, L);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_batch_workspace_bytes(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq,
+                                                  uint64_t* bytes) {
+  if (!ctx || !m || !bytes) return fail(TPMC_E_INVALID, "ctx, mesh and bytes must not be NULL");
+  std::vector<QueryDev> hq;
+  std::vector<uint64_t> te;
+  Layout L;
+  tpmc_status s = batch_prepare(m, q, nq, hq, te, L, nullptr);
+  if (s != TPMC_OK) return s;
+  *bytes = L.bytes;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq, void* ws,
+                                         uint64_t ws_bytes, tpmc_batch* out) {
+  if (!ctx || !m || !out) return fail(TPMC_E_INVALID, "ctx, mesh and out must not be NULL");
+  *out = nullptr;
+  if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
+  tpmc_batch b = new (std::nothrow) tpmc_batch_s;
+  if (!b) return fail(TPMC_E_INVALID, "out of host memory");
+  tpmc_status s = batch_prepare(m, q, nq, b->hq, b->tile_end, b->lay, static_cast<uint8_t*>(ws));
+  if (s == TPMC_OK) s = check_ws(ws, ws_bytes, b->lay.bytes);
+  if (s != TPMC_OK) {
+    delete b;
+    return s;
+  }
+  b->ctx = ctx;
+  b->mesh = m;
+  b->nq = nq;
+  b->total_tiles = b->tile_end.back();
+  b->tally_words = 0;
+  bool any_tri = false, all_tri = true;
+  for (const auto& hq : b->hq) {
+    b->tally_words += hq.per_tri ? m->nt * 7 : 0;
+    any_tri = any_tri || hq.per_tri;
+    all_tri = all_tri && hq.per_tri;
+  }
+  if (any_tri && !all_tri) {
+    delete b;
+    return fail(TPMC_E_INVALID, "a batch must use one tally kind (TPMC_Q_NO_TRIANGLE_TALLY on all or none)");
+  }
+  b->mode = !any_tri ? kTallyTotals : (m->nt <= (uint64_t)kWaveTallyMaxTris ? kTallyWave : kTallyGlobal);
+  b->grid = ctx->n_cu * 8;
+  b->exec = nullptr;
+  b->launched = false;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->lay.qs, b->hq.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->lay.tile_end, b->tile_end.data(), nq * sizeof(uint64_t), hipMemcpyHostToDevice,
+                       ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return fail(TPMC_E_DEVICE, "batch upload: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return TPMC_OK;
+}
+
+static void batch_enqueue(tpmc_batch b, hipStream_t st) {
+  tpmc_mesh m = b->mesh;
+  zero_u32(b->lay.counter, 2, st);
+  zero_i64(b->lay.scal, (uint64_t)b->nq * kScalarSlots, st);
+  zero_i64(b->lay.tally, b->tally_words, st);
+  BatchArgs a;
+  a.nodes = m->nodes;
+  a.tris = m->tris;
+  a.orig = m->orig;
+  a.qs = b->lay.qs;
+  a.tile_end = b->lay.tile_end;
+  a.work_counter = b->lay.counter;
+  a.tally_base = b->lay.tally;
+  a.scal_base = b->lay.scal;
+  a.total_tiles = b->total_tiles;
+  a.nq = b->nq;
+  a.nt = (uint32_t)m->nt;
+  launch_batch(a, m->stack_slots, b->mode, b->grid, st);
+  if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, a.nt, st);
+}
+
+extern "C" tpmc_status tpmc_batch_launch(tpmc_ctx ctx, tpmc_batch b, int use_graph) {
+  if (!ctx || !b) return fail(TPMC_E_INVALID, "ctx and batch must not be NULL");
+  if (b->ctx != ctx) return fail(TPMC_E_BUSY, "batch belongs to another context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!use_graph) {
+    batch_enqueue(b, ctx->stream);
+    HIP_CHECK_LAUNCH("batch");
+    b->launched = true;
+    return TPMC_OK;
+  }
+  if (!b->exec) {
+    if (!ctx->capture_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    batch_enqueue(b, ctx->capture_stream);
+    hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (e != hipSuccess) return fail(TPMC_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return fail(TPMC_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+  }
+  HIP_TRY(hipGraphLaunch(b->exec, ctx->stream));
+  b->launched = true;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_batch_results(tpmc_ctx ctx, tpmc_batch b, const double ref_point[3], double A_ref,
+                                          tpmc_result* out) {
+  if (!ctx || !b || !out) return fail(TPMC_E_INVALID, "ctx, batch and out must not be NULL");
+  if (!(A_ref > 0.0) || !std::isfinite(A_ref)) return fail(TPMC_E_INVALID, "A_ref = %g must be > 0", A_ref);
+  if (ref_point && !finite3(ref_point)) return fail(TPMC_E_INVALID, "reference point must be finite");
+  if (!b->launched) return fail(TPMC_E_BUSY, "batch has not been launched");
+  HIP_TRY(hipSetDevice(ctx->device));
+  return finalize_results(ctx, b->lay, b->nq, ref_point, A_ref, out);
+}
+
+extern "C" void tpmc_destroy_batch(tpmc_batch b) {
+  if (!b) return;
+  if (b->exec) {
+    (void)hipSetDevice(b->ctx->device);
+    (void)hipGraphExecDestroy(b->exec);
+  }
+  delete b;
+}

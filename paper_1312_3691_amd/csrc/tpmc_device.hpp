@@ -1,0 +1,329 @@
+// tpmc_device.hpp -- device building blocks of the TPMC hot path for gfx950:
+// Philox streams, FP64 boundary seeding, FP32 watertight ray-triangle and
+// ray-box tests, Maxwell re-emission, fixed-point quantisation, wave reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tpmc_internal.h"
+
+// Contraction into FMA only within one source expression, so every kernel that
+// inlines these functions rounds them identically (plain and batched paths
+// must agree bit for bit).
+#pragma clang fp contract(on)
+
+namespace tpmc {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Stream of particle p at
+// step s: counter (p lo, p hi, s, 0), key (seed lo, seed hi).  Steps 0-1 feed
+// the seeding, step 2 + b the b-th re-emission.
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t a, b, c, d;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 stream(const QueryDev& q, uint64_t pid, uint32_t step) {
+  return philox4x32_10((uint32_t)pid, (uint32_t)(pid >> 32), step, 0u, q.key0, q.key1);
+}
+
+// Uniform variates in (0, 1), exact in their type:
+// FP64 u = (k + 1/2) 2^-32; FP32 u = (floor(k / 2^9) + 1/2) 2^-23.
+__device__ __forceinline__ double unif64(uint32_t k) { return ((double)k + 0.5) * 0x1p-32; }
+__device__ __forceinline__ float unif32(uint32_t k) { return ((float)(k >> 9) + 0.5f) * 0x1p-23f; }
+
+// ---------------------------------------------------------------------------
+// Boundary seeding in FP64 (Sec. III.A).
+//
+// Latitude: mu = sin(phi) has density chi(S mu) / Z(S) on [-1, 1], from
+// g(phi|S) with d(mu) = cos(phi) d(phi); chi(s) = e^{-s^2} + sqrt(pi) s (1 + erf s).
+// Its CDF numerator G(t) = int_{-1}^t chi(S m) dm is the difference of the
+// antiderivative sqrt(pi)/(4S) erf(St) + sqrt(pi) S t^2 (1 + erf St)/2 + t e^{-S^2 t^2}/2
+// at t and -1, arranged so that no term cancels.  G' = chi(S t) > 0, so the
+// equation G(mu) = u Z is solved by Newton's method inside a shrinking bracket.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG) {
+  const double S = q.S;
+  const double St = S * t;
+  const double e = exp(-St * St);
+  const double c = erfc(-St);  // 1 + erf(S t)
+  double E;                    // erf(S t) + erf(S)
+  if (St < -1.0) E = c - q.erfcS;
+  else if (S < 0.25) E = erf(St) + q.erfS;
+  else E = (c - 1.0) + q.erfS;
+  G = kSqrtPi / (4.0 * S) * E + 0.5 * kSqrtPi * S * (t * t * c - q.erfcS) + 0.5 * (t * e + q.expmS2);
+  dG = e + kSqrtPi * St * c;
+}
+
+__device__ inline double sample_latitude(const QueryDev& q, double u) {
+  if (q.s_zero) return 2.0 * u - 1.0;  // S -> 0: g -> cos(phi)/2, mu uniform
+  const double target = u * q.Z;
+  // starting point between the S -> 0 law (uniform) and the S -> inf law (density 2 mu)
+  const double wgt = q.S * q.S / (1.0 + q.S * q.S);
+  double x = (1.0 - wgt) * (2.0 * u - 1.0) + wgt * sqrt(u);
+  double lo = -1.0, hi = 1.0;
+  for (int it = 0; it < 100; ++it) {
+    double G, dG;
+    latitude_G(q, x, G, dG);
+    const double f = G - target;
+    if (f < 0.0) lo = x;
+    else hi = x;
+    double xn = x - f / dG;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    const double dx = xn - x;
+    x = xn;
+    if (fabs(dx) <= 1e-15 || hi - lo <= 1e-15) break;
+  }
+  return x;
+}
+
+// Inward normal speed x = v_n / c_mp >= 0 of eq. vel_dist1, p(x|s) = 2x e^{-(x-s)^2} / chi(s).
+// CDF numerator F(x) = e^{-s^2} - e^{-(x-s)^2} + sqrt(pi) s (erf(x-s) + erf s), F' = 2x e^{-(x-s)^2}.
+struct NormalSpeedConsts {
+  double s, es2, erfs, erfcs, erfcms, chi;
+};
+
+__device__ __forceinline__ NormalSpeedConsts normal_speed_consts(double s) {
+  NormalSpeedConsts k;
+  k.s = s;
+  k.es2 = exp(-s * s);
+  k.erfcms = erfc(-s);  // 1 + erf(s)
+  k.erfcs = erfc(s);
+  k.erfs = erf(s);
+  k.chi = k.es2 + kSqrtPi * s * k.erfcms;
+  return k;
+}
+
+__device__ __forceinline__ void normal_speed_F(const NormalSpeedConsts& k, double x, double& F, double& dF) {
+  const double a = x - k.s;
+  const double ea = exp(-a * a);
+  double esum;  // erf(x - s) + erf(s)
+  if (k.s < 0.0) esum = k.erfcms - erfc(a);
+  else if (a < 0.0) esum = erfc(-a) - k.erfcs;
+  else esum = erf(a) + k.erfs;
+  F = k.es2 - ea + kSqrtPi * k.s * esum;
+  dF = 2.0 * x * ea;
+}
+
+__device__ inline double sample_normal_speed(double s, double u) {
+  const NormalSpeedConsts k = normal_speed_consts(s);
+  const double target = u * k.chi;
+  // starting point: near-Gaussian about s for s > 1, Rayleigh law (exact at s = 0) otherwise
+  double x;
+  if (s > 1.0) x = s + 0.5 / s + erfinv(2.0 * u - 1.0);
+  else x = sqrt(-log1p(-u)) + (s > 0.0 ? 0.5 * s : 0.0);
+  double lo = 0.0, hi = (s > 0.0 ? s : 0.0) + 7.0;
+  for (int g = 0; g < 8; ++g) {  // make sure [lo, hi] brackets the root
+    double F, dF;
+    normal_speed_F(k, hi, F, dF);
+    if (F >= target) break;
+    hi *= 2.0;
+  }
+  if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+  for (int it = 0; it < 100; ++it) {
+    double F, dF;
+    normal_speed_F(k, x, F, dF);
+    const double f = F - target;
+    if (f < 0.0) lo = x;
+    else hi = x;
+    double xn = x - f / dF;
+    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+    const double dx = xn - x;
+    x = xn;
+    if (fabs(dx) <= 1e-15 * x || hi - lo <= 1e-15 * x) break;
+  }
+  return x;
+}
+
+// One seeded particle (Sec. III.A.1-3): position on the CV and velocity, FP64.
+__device__ inline void seed_particle(const QueryDev& q, uint64_t pid, double x[3], double w[3]) {
+  const U4 r0 = stream(q, pid, 0u);
+  const U4 r1 = stream(q, pid, 1u);
+  const double mu = sample_latitude(q, unif64(r0.a));
+  const double cphi = sqrt(fmax(0.0, 1.0 - mu * mu));
+  double sth, cth;
+  sincospi(2.0 * unif64(r0.b), &sth, &cth);
+  // inward normal n = mu U - cos(phi) c with c = cos(th) e1 + sin(th) e2; tangent
+  // t1 = cos(phi) U + mu c (unit, along the tangential part of U); t2 = t1 x n = -d,
+  // d = -sin(th) e1 + cos(th) e2.  x = c0 - r n.
+  const double s_n = q.S * mu;
+  const double wn = sample_normal_speed(s_n, unif64(r0.c));
+  const double rad = sqrt(-2.0 * log(unif64(r0.d)));
+  double sb, cb;
+  sincospi(2.0 * unif64(r1.a), &sb, &cb);
+  const double wt1 = q.S * cphi + rad * cb * kInvSqrt2;
+  const double wt2 = rad * sb * kInvSqrt2;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double ck = cth * q.e1[k] + sth * q.e2[k];
+    const double dk = -sth * q.e1[k] + cth * q.e2[k];
+    const double nk = mu * q.U[k] - cphi * ck;
+    const double t1k = cphi * q.U[k] + mu * ck;
+    x[k] = q.c0[k] - q.r * nk;
+    w[k] = wn * nk + wt1 * t1k - wt2 * dk;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Ray set-up for the watertight test of Woop, Benthin & Wald (JCGT 2013):
+// permute so that z is the dominant direction axis, shear so the ray is +z.
+// ---------------------------------------------------------------------------
+struct Ray {
+  float ox, oy, oz;
+  float dx, dy, dz;
+  float idx, idy, idz;  // 1 / d for the slab test
+  float Sx, Sy, Sz;
+  int kx, ky, kz;
+};
+
+__device__ __forceinline__ float comp(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
+
+__device__ __forceinline__ void make_ray(Ray& r, float ox, float oy, float oz, float dx, float dy, float dz) {
+  r.ox = ox; r.oy = oy; r.oz = oz;
+  r.dx = dx; r.dy = dy; r.dz = dz;
+  r.idx = 1.0f / dx; r.idy = 1.0f / dy; r.idz = 1.0f / dz;
+  const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
+  int kz = 0;
+  if (ay > ax) kz = 1;
+  if (az > fmaxf(ax, ay)) kz = 2;
+  int kx = kz == 2 ? 0 : kz + 1;
+  int ky = kx == 2 ? 0 : kx + 1;
+  const float dkz = comp(dx, dy, dz, kz);
+  if (dkz < 0.0f) {
+    const int t = kx;
+    kx = ky;
+    ky = t;
+  }
+  r.kx = kx; r.ky = ky; r.kz = kz;
+  r.Sx = comp(dx, dy, dz, kx) / dkz;
+  r.Sy = comp(dx, dy, dz, ky) / dkz;
+  r.Sz = 1.0f / dkz;
+}
+
+// Two-sided closest-hit candidate test.  Returns true with t and barycentrics
+// (weights of v0, v1, v2) when the triangle is hit at 0 < t <= t_max.  The
+// edge functions are evaluated without contraction so that a shared edge gives
+// exactly opposite values in its two triangles, and re-evaluated in FP64 when
+// one is exactly zero.
+__device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, float t_max, float& t_out,
+                                              float& b0, float& b1, float& b2) {
+#pragma clang fp contract(off)
+  const float Ax0 = tr.v0x - r.ox, Ay0 = tr.v0y - r.oy, Az0 = tr.v0z - r.oz;
+  const float Bx0 = tr.v1x - r.ox, By0 = tr.v1y - r.oy, Bz0 = tr.v1z - r.oz;
+  const float Cx0 = tr.v2x - r.ox, Cy0 = tr.v2y - r.oy, Cz0 = tr.v2z - r.oz;
+  const float Akx = comp(Ax0, Ay0, Az0, r.kx), Aky = comp(Ax0, Ay0, Az0, r.ky), Akz = comp(Ax0, Ay0, Az0, r.kz);
+  const float Bkx = comp(Bx0, By0, Bz0, r.kx), Bky = comp(Bx0, By0, Bz0, r.ky), Bkz = comp(Bx0, By0, Bz0, r.kz);
+  const float Ckx = comp(Cx0, Cy0, Cz0, r.kx), Cky = comp(Cx0, Cy0, Cz0, r.ky), Ckz = comp(Cx0, Cy0, Cz0, r.kz);
+  const float Ax = Akx - r.Sx * Akz, Ay = Aky - r.Sy * Akz;
+  const float Bx = Bkx - r.Sx * Bkz, By = Bky - r.Sy * Bkz;
+  const float Cx = Ckx - r.Sx * Ckz, Cy = Cky - r.Sy * Ckz;
+  float U = Cx * By - Cy * Bx;
+  float V = Ax * Cy - Ay * Cx;
+  float W = Bx * Ay - By * Ax;
+  if (U == 0.0f || V == 0.0f || W == 0.0f) {
+    U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+    V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+    W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+  }
+  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+  const float det = U + V + W;
+  if (det == 0.0f) return false;
+  const float T = U * (r.Sz * Akz) + V * (r.Sz * Bkz) + W * (r.Sz * Ckz);
+  const float t = T / det;
+  if (!(t > 0.0f) || t > t_max) return false;
+  const float inv = 1.0f / det;
+  t_out = t;
+  b0 = U * inv;
+  b1 = V * inv;
+  b2 = W * inv;
+  return true;
+}
+
+// Slab test of a child box; conservative far bound per Ize (JCGT 2013), so a
+// box whose triangle is hit is never culled by rounding.
+__device__ __forceinline__ bool slab(const Ray& r, float lox, float loy, float loz, float hix, float hiy, float hiz,
+                                     float t_max, float& t_near) {
+  const float tx0 = (lox - r.ox) * r.idx, tx1 = (hix - r.ox) * r.idx;
+  const float ty0 = (loy - r.oy) * r.idy, ty1 = (hiy - r.oy) * r.idy;
+  const float tz0 = (loz - r.oz) * r.idz, tz1 = (hiz - r.oz) * r.idz;
+  const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), t_max));
+  t_near = tn;
+  return tn <= tf * 1.0000004f;
+}
+
+// ---------------------------------------------------------------------------
+// Gas-surface interaction (Sec. II.A), FP32.  Maxwell model: diffuse with
+// probability alpha -- the particle leaves the side it arrived on with the
+// flux-weighted half-range Maxwellian of T_w (normal speed tau sqrt(-ln u),
+// tangential components N(0, tau^2/2)) -- else specular.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void reemit(const QueryDev& q, uint64_t pid, uint32_t bounce, float nx, float ny, float nz,
+                                       float& wx, float& wy, float& wz) {
+  const U4 r = stream(q, pid, 2u + bounce);
+  const float wn = wx * nx + wy * ny + wz * nz;
+  if (unif32(r.a) < q.alpha) {
+    const float sg = wn < 0.0f ? 1.0f : -1.0f;
+    const float sx = sg * nx, sy = sg * ny, sz = sg * nz;
+    // orthonormal tangents of (sx, sy, sz) (Duff et al., JCGT 2017)
+    const float sign = sz >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (sign + sz);
+    const float b = sx * sy * a;
+    const float b1x = 1.0f + sign * sx * sx * a, b1y = sign * b, b1z = -sign * sx;
+    const float b2x = b, b2y = sign + sy * sy * a, b2z = -sy;
+    const float vn = q.tau * sqrtf(-logf(unif32(r.b)));
+    const float rad = q.tau * sqrtf(-2.0f * logf(unif32(r.c))) * (float)kInvSqrt2;
+    float sn, cs;
+    sincospif(2.0f * unif32(r.d), &sn, &cs);
+    const float v1 = rad * cs, v2 = rad * sn;
+    wx = vn * sx + v1 * b1x + v2 * b2x;
+    wy = vn * sy + v1 * b1y + v2 * b2y;
+    wz = vn * sz + v1 * b1z + v2 * b2z;
+  } else {
+    const float k = 2.0f * wn;
+    wx -= k * nx;
+    wy -= k * ny;
+    wz -= k * nz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fixed point and wave-level reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long fx(float v, float scale) { return __float2ll_rn(v * scale); }
+__device__ __forceinline__ long long fxd(double v, double scale) { return __double2ll_rn(v * scale); }
+
+__device__ __forceinline__ long long wave_sum(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ void atomic_add_i64(long long* p, long long v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+}
+
+}  // namespace tpmc

@@ -1,0 +1,69 @@
+// tpmc_internal.h -- layouts shared by the host side of libtpmc and its HIP kernels.
+#pragma once
+
+#include <stdint.h>
+
+namespace tpmc {
+
+constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
+constexpr int kMaxReflections = 64;
+constexpr int kLdsTallyMaxTris = 512;  // per-workgroup LDS tallies up to this mesh size
+constexpr int kWaveTallyMaxTris = 8;   // wave-aggregated tallies for tiny meshes
+constexpr int kScalarSlots = 16;       // int64 per query, see ScalarSlot
+
+// Per-query int64 block.  D is the momentum one particle gives the body along
+// the free stream (sum over its hits of (w - w').U); D and D^2 are quantised
+// per particle, so every sum is an exact integer sum and independent of order.
+enum ScalarSlot {
+  kSD = 0, kSD2 = 1, kRays = 2, kHits = 3, kSegments = 4, kMissed = 5, kEscaped = 6, kCapped = 7,
+  kFx = 8, kFy = 9, kFz = 10, kLx = 11, kLy = 12, kLz = 13, kCount = 14
+};
+
+// Device-side constants of one query (a1: FP64 set-up done on the host).
+struct alignas(16) QueryDev {
+  double U[3], e1[3], e2[3], c0[3];  // free stream and seeding frame, CV centre (body frame)
+  double r;                          // CV radius
+  double S;                          // speed ratio
+  double Z;                          // normaliser of the latitude density, = G(1)
+  double erfS, erfcS, expmS2;        // erf(S), erfc(S), exp(-S^2)
+  double inv_scaleF, inv_scaleL, inv_scaleD, inv_scaleD2;
+  double Gamma_hat;
+  uint64_t N;                        // particles of this query
+  uint64_t p_offset;                 // first particle in the SoA planes (plain path)
+  uint64_t tally_offset;             // first int64 of this query's per-triangle tallies
+  uint64_t scalar_offset;            // first int64 of this query's scalar block
+  float Uf[3], c0f[3];
+  float tau, alpha;
+  float scaleF, scaleL, scaleD, scaleD2;  // fixed-point scales, powers of two
+  uint32_t key0, key1;               // Philox key = seed
+  uint32_t rmax;
+  uint32_t s_zero;                   // S treated as exactly 0
+  uint32_t per_tri;                  // per-triangle tallies kept
+  uint32_t pad_[3];
+};
+
+// Device result of the finalisation kernel (mirrors tpmc_result).
+struct ResultDev {
+  double F_over_q[3], M_over_q[3], Fhat[3];
+  double CD, CD_sigma, Gamma_hat;
+  uint64_t rays, hits, segments, missed, escaped, capped;
+};
+
+// BVH node: the boxes of both children and the two child links (64 bytes).
+// A link >= 0 is an internal node; a link < 0 is the leaf ~link, a position in
+// the Morton-sorted triangle array.
+struct alignas(16) Node {
+  float lo0x, lo0y, lo0z, hi0x;
+  float hi0y, hi0z, lo1x, lo1y;
+  float lo1z, hi1x, hi1y, hi1z;
+  int32_t c0, c1, parent, pad;
+};
+
+// Triangle record in Morton order: vertices and unit geometric normal (48 bytes).
+struct alignas(16) TriRec {
+  float v0x, v0y, v0z, nx;
+  float v1x, v1y, v1z, ny;
+  float v2x, v2y, v2z, nz;
+};
+
+}  // namespace tpmc

@@ -1,0 +1,62 @@
+// tpmc_launch.h -- host-side launchers of the HIP kernels (defined in the .hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tpmc_internal.h"
+
+namespace tpmc {
+
+// Tally strategy of the trace kernels.
+enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyWave = 2, kTallyTotals = 3 };
+
+struct TraceArgs {
+  const Node* nodes;
+  const TriRec* tris;
+  const uint32_t* orig;
+  const QueryDev* q;          // device pointer, one query
+  const float* x[3];          // SoA planes, already offset to the query
+  const float* w[3];
+  uint64_t n;
+  long long* tally;           // [nt][7] or null (totals mode)
+  long long* scal;            // [kScalarSlots]
+  int32_t* first_tri;         // optional, already offset to the query
+  unsigned long long* counters;  // optional [2]: BVH nodes visited, triangle tests
+  uint32_t nt;
+};
+
+struct BatchArgs {
+  const Node* nodes;
+  const TriRec* tris;
+  const uint32_t* orig;
+  const QueryDev* qs;         // [nq]
+  const uint64_t* tile_end;   // [nq] inclusive prefix sum of tiles per query
+  uint32_t* work_counter;     // zeroed before the launch
+  long long* tally_base;      // per-triangle tallies, indexed by QueryDev::tally_offset
+  long long* scal_base;       // scalar blocks, indexed by QueryDev::scalar_offset
+  uint64_t total_tiles;
+  uint32_t nq;
+  uint32_t nt;
+};
+
+void zero_i64(long long* p, uint64_t n, hipStream_t st);
+void zero_u32(uint32_t* p, uint64_t n, hipStream_t st);
+
+size_t bvh_scratch_bytes(uint64_t nt);
+hipError_t build_bvh(const float* d_xyz, const uint32_t* d_tri, uint64_t nt, const float box_lo[3],
+                     const float box_hi[3], void* scratch, Node* d_nodes, TriRec* d_tris, uint32_t* d_orig,
+                     uint32_t* h_depth, hipStream_t st);
+
+int stack_slots_for_depth(uint32_t depth);  // 0 when too deep
+void launch_seed(const QueryDev* d_q, uint64_t n, float* const x[3], float* const w[3], int grid, hipStream_t st);
+void launch_trace(const TraceArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
+void launch_reduce(const long long* tally, uint32_t nt, long long* scal, hipStream_t st);
+void launch_finalize(const QueryDev* d_qs, const long long* scal_base, uint32_t nq, double xr, double yr, double zr,
+                     double A_ref, ResultDev* out, hipStream_t st);
+void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
+void launch_reduce_batch(const QueryDev* d_qs, uint32_t nq, long long* tally_base, long long* scal_base, uint32_t nt,
+                         hipStream_t st);
+
+}  // namespace tpmc

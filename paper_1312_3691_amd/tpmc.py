@@ -1,0 +1,338 @@
+"""Python binding of libtpmc.so (C ABI in include/tpmc.h).
+
+Argument marshalling only: every step of the drag computation runs in the
+library's HIP kernels.  PyTorch supplies device memory (the workspaces) and the
+HIP stream.  Importing this module fails loudly when libtpmc.so is missing;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+import torch  # noqa: F401  -- loads PyTorch's HIP runtime, which libtpmc.so is linked against
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpmc.so")
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libtpmc.so not built ({LIB_PATH}); run `python -m paper_1312_3691_amd.build` first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+Q_NO_TRIANGLE_TALLY = 1
+
+STATUS = {0: "TPMC_OK", 1: "TPMC_E_INVALID", 2: "TPMC_E_MESH", 3: "TPMC_E_CV", 4: "TPMC_E_WORKSPACE",
+          5: "TPMC_E_DEVICE", 6: "TPMC_E_BUSY"}
+
+
+class TpmcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Query(ctypes.Structure):
+    _fields_ = [("q_wxyz", ctypes.c_double * 4), ("S", ctypes.c_double), ("T_inf", ctypes.c_double),
+                ("T_w", ctypes.c_double), ("alpha", ctypes.c_double), ("n_particles", ctypes.c_uint64),
+                ("seed", ctypes.c_uint64), ("max_reflections", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("cv_center", ctypes.c_double * 3), ("cv_radius", ctypes.c_double)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("F_over_q", ctypes.c_double * 3), ("M_over_q", ctypes.c_double * 3), ("Fhat", ctypes.c_double * 3),
+                ("CD", ctypes.c_double), ("CD_sigma", ctypes.c_double), ("Gamma_hat", ctypes.c_double),
+                ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64), ("segments", ctypes.c_uint64),
+                ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64), ("capped", ctypes.c_uint64)]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_uint64), ("nt", ctypes.c_uint64), ("depth", ctypes.c_uint32),
+                ("stack_slots", ctypes.c_uint32), ("box_lo", ctypes.c_double * 3), ("box_hi", ctypes.c_double * 3),
+                ("sphere_center", ctypes.c_double * 3), ("sphere_radius", ctypes.c_double),
+                ("device_bytes", ctypes.c_uint64)]
+
+
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_QP = ctypes.POINTER(Query)
+_RP = ctypes.POINTER(Result)
+
+_SIGS = {
+    "tpmc_last_error": ([], ctypes.c_char_p),
+    "tpmc_abi_version": ([], ctypes.c_int),
+    "tpmc_create": ([ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_set_stream": ([_vp, _vp], ctypes.c_int),
+    "tpmc_destroy_ctx": ([_vp], None),
+    "tpmc_build_mesh": ([_vp, _fp, _u64, ctypes.POINTER(_u32), _u64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_get_mesh_info": ([_vp, ctypes.POINTER(MeshInfo)], ctypes.c_int),
+    "tpmc_destroy_mesh": ([_vp], None),
+    "tpmc_workspace_bytes": ([_vp, _vp, _QP, _u32, ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_seed": ([_vp, _vp, _QP, _u32, _vp, _u64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_particles_planes": ([_vp, ctypes.POINTER(_vp), ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_trace": ([_vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_trace_ex": ([_vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_forces": ([_vp, _vp, _dp, ctypes.c_double, _RP], ctypes.c_int),
+    "tpmc_tally_copy": ([_vp, _vp, _u32, _dp], ctypes.c_int),
+    "tpmc_destroy_particles": ([_vp], None),
+    "tpmc_destroy_tally": ([_vp], None),
+    "tpmc_batch_workspace_bytes": ([_vp, _vp, _QP, _u32, ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_batch_create": ([_vp, _vp, _QP, _u32, _vp, _u64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_batch_launch": ([_vp, _vp, ctypes.c_int], ctypes.c_int),
+    "tpmc_batch_results": ([_vp, _vp, _dp, ctypes.c_double, _RP], ctypes.c_int),
+    "tpmc_destroy_batch": ([_vp], None),
+    "tpmc_check_mesh": ([_fp, _u64, ctypes.POINTER(_u32), _u64], ctypes.c_int),
+    "tpmc_check_query": ([_QP, _fp, _u64], ctypes.c_int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def _check(status: int):
+    if status != 0:
+        raise TpmcError(status, _lib.tpmc_last_error().decode())
+
+
+def make_query(qd: dict) -> Query:
+    q = Query()
+    q.q_wxyz[:] = [float(v) for v in qd["q"]]
+    q.S, q.T_inf, q.T_w, q.alpha = float(qd["S"]), float(qd["T_inf"]), float(qd["T_w"]), float(qd["alpha"])
+    q.n_particles, q.seed = int(qd["n"]), int(qd["seed"])
+    q.max_reflections = int(qd.get("max_reflections", 16))
+    q.flags = int(qd.get("flags", 0))
+    q.cv_center[:] = [float(v) for v in qd.get("cv_center", (0.0, 0.0, 0.0))]
+    q.cv_radius = float(qd.get("cv_radius", 0.0))
+    return q
+
+
+def _queries(qds) -> ctypes.Array:
+    arr = (Query * len(qds))()
+    for i, qd in enumerate(qds):
+        arr[i] = make_query(qd)
+    return arr
+
+
+def result_dict(r: Result) -> dict:
+    out = {}
+    for f, _ in Result._fields_:
+        v = getattr(r, f)
+        out[f] = np.array(v[:]) if isinstance(v, ctypes.Array) else v
+    return out
+
+
+def _mesh_arrays(V, T):
+    V = np.ascontiguousarray(np.asarray(V, dtype=np.float32).reshape(-1, 3))
+    T = np.ascontiguousarray(np.asarray(T, dtype=np.uint32).reshape(-1, 3))
+    return V, T
+
+
+def check_mesh(V, T) -> None:
+    """Host-only validation (no device needed)."""
+    V, T = _mesh_arrays(V, T)
+    _check(_lib.tpmc_check_mesh(V.ctypes.data_as(_fp), V.shape[0], T.ctypes.data_as(ctypes.POINTER(_u32)),
+                                T.shape[0]))
+
+
+def check_query(qd: dict, V=None) -> None:
+    """Host-only validation of one query (the control-volume test needs V)."""
+    q = make_query(qd)
+    if V is None:
+        _check(_lib.tpmc_check_query(ctypes.byref(q), None, 0))
+    else:
+        Vc = np.ascontiguousarray(np.asarray(V, dtype=np.float32).reshape(-1, 3))
+        _check(_lib.tpmc_check_query(ctypes.byref(q), Vc.ctypes.data_as(_fp), Vc.shape[0]))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _workspace(nbytes: int, device: int):
+    """Device workspace from PyTorch's allocator, 256-byte aligned."""
+    torch = _torch()
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+    ptr = buf.data_ptr()
+    off = (-ptr) % 256
+    return buf, ptr + off, int(nbytes)
+
+
+class Context:
+    """A libtpmc context on one GPU, issuing work on PyTorch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise TpmcError(5, "no GPU visible: libtpmc runs on MI355X (gfx950) only")
+        self.device = int(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = _vp()
+        _check(_lib.tpmc_create(self.device, _vp(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tpmc_destroy_ctx(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_mesh(self, V, T) -> "Mesh":
+        return Mesh(self, V, T)
+
+
+class Mesh:
+    """Triangle mesh with its device-resident LBVH."""
+
+    def __init__(self, ctx: Context, V, T):
+        V, T = _mesh_arrays(V, T)
+        self.ctx = ctx
+        self.V, self.T = V, T
+        h = _vp()
+        _check(_lib.tpmc_build_mesh(ctx._h, V.ctypes.data_as(_fp), V.shape[0],
+                                    T.ctypes.data_as(ctypes.POINTER(_u32)), T.shape[0], ctypes.byref(h)))
+        self._h = h
+        info = MeshInfo()
+        _check(_lib.tpmc_get_mesh_info(h, ctypes.byref(info)))
+        self.info = {f: (list(getattr(info, f)) if isinstance(getattr(info, f), ctypes.Array) else getattr(info, f))
+                     for f, _ in MeshInfo._fields_}
+        self.nt = int(info.nt)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tpmc_destroy_mesh(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class PlainRun:
+    """seed -> trace -> forces for a list of queries (one kernel launch per
+    query and stage).  Keeps the workspace alive while its handles live."""
+
+    def __init__(self, mesh: Mesh, queries, first_tri: bool = False):
+        torch = _torch()
+        self.mesh, self.ctx = mesh, mesh.ctx
+        self.qds = list(queries)
+        self._qarr = _queries(self.qds)
+        nbytes = _u64()
+        _check(_lib.tpmc_workspace_bytes(self.ctx._h, mesh._h, self._qarr, len(self.qds), ctypes.byref(nbytes)))
+        self.ws_tensor, self.ws_ptr, self.ws_bytes = _workspace(nbytes.value, self.ctx.device)
+        self.n_total = sum(int(q["n"]) for q in self.qds)
+        self.first_tri = (torch.full((self.n_total,), -3, dtype=torch.int32, device=f"cuda:{self.ctx.device}")
+                          if first_tri else None)
+        self._p = None
+        self._t = None
+
+    def seed(self):
+        p = _vp()
+        _check(_lib.tpmc_seed(self.ctx._h, self.mesh._h, self._qarr, len(self.qds), _vp(self.ws_ptr),
+                              self.ws_bytes, ctypes.byref(p)))
+        self._p = p
+        return self
+
+    def planes(self):
+        """Seeded states as six torch FP32 views (x0, x1, x2, w0, w1, w2)."""
+        torch = _torch()
+        arr = (_vp * 6)()
+        n = _u64()
+        _check(_lib.tpmc_particles_planes(self._p, arr, ctypes.byref(n)))
+        base = self.ws_tensor.data_ptr()
+        out = []
+        for k in range(6):
+            off = arr[k] - base
+            out.append(self.ws_tensor[off: off + 4 * n.value].view(torch.float32))
+        return out
+
+    def trace(self, counters=None):
+        """counters: optional torch int64 device tensor [2] (nodes visited, triangle tests)."""
+        t = _vp()
+        ft = _vp(self.first_tri.data_ptr()) if self.first_tri is not None else None
+        ct = _vp(counters.data_ptr()) if counters is not None else None
+        _check(_lib.tpmc_trace_ex(self.ctx._h, self.mesh._h, self._p, ft, ct, ctypes.byref(t)))
+        self._t = t
+        return self
+
+    def forces(self, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0):
+        res = (Result * len(self.qds))()
+        xr = (ctypes.c_double * 3)(*[float(v) for v in x_ref])
+        _check(_lib.tpmc_forces(self.ctx._h, self._t, xr, float(A_ref), res))
+        return [result_dict(r) for r in res]
+
+    def tally(self, query: int = 0) -> np.ndarray:
+        out = np.zeros((self.mesh.nt, 7))
+        _check(_lib.tpmc_tally_copy(self.ctx._h, self._t, int(query), out.ctypes.data_as(_dp)))
+        return out
+
+    def close(self):
+        if self._t:
+            _lib.tpmc_destroy_tally(self._t)
+            self._t = None
+        if self._p:
+            _lib.tpmc_destroy_particles(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(mesh: Mesh, queries, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, first_tri: bool = False):
+    """Plain path: seed, trace and reduce; returns (results, PlainRun)."""
+    pr = PlainRun(mesh, queries, first_tri=first_tri).seed().trace()
+    return pr.forces(x_ref, A_ref), pr
+
+
+class Batch:
+    """Batched path: all queries in one persistent launch (optionally replayed
+    from a captured HIP graph)."""
+
+    def __init__(self, mesh: Mesh, queries):
+        self.mesh, self.ctx = mesh, mesh.ctx
+        self.qds = list(queries)
+        self._qarr = _queries(self.qds)
+        nbytes = _u64()
+        _check(_lib.tpmc_batch_workspace_bytes(self.ctx._h, mesh._h, self._qarr, len(self.qds), ctypes.byref(nbytes)))
+        self.ws_tensor, self.ws_ptr, self.ws_bytes = _workspace(nbytes.value, self.ctx.device)
+        h = _vp()
+        _check(_lib.tpmc_batch_create(self.ctx._h, mesh._h, self._qarr, len(self.qds), _vp(self.ws_ptr),
+                                      self.ws_bytes, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, use_graph: bool = False):
+        _check(_lib.tpmc_batch_launch(self.ctx._h, self._h, 1 if use_graph else 0))
+        return self
+
+    def results(self, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0):
+        res = (Result * len(self.qds))()
+        xr = (ctypes.c_double * 3)(*[float(v) for v in x_ref])
+        _check(_lib.tpmc_batch_results(self.ctx._h, self._h, xr, float(A_ref), res))
+        return [result_dict(r) for r in res]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tpmc_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
