@@ -181,6 +181,35 @@ tpmc_status tpmc_batch_results(tpmc_ctx ctx, tpmc_batch b, const double ref_poin
                                tpmc_result* out);
 void tpmc_destroy_batch(tpmc_batch b);
 
+/* ---- Serving: continuous batching over resident meshes ----
+ * A server is a table of request slots in a caller workspace.  A request is
+ * admitted into a free slot (its constants uploaded, its tallies zeroed); each
+ * step is ONE persistent launch over any set of (slot, tile range) entries --
+ * slots of different meshes and sizes run together -- and tallies accumulate
+ * exactly across steps, so a request's result does not depend on how its tiles
+ * were spread over steps or which requests shared them.  Tiles hold 4096
+ * particles.  Slot and pool bookkeeping (admission by memory budget) is the
+ * caller's policy; the library checks bounds. */
+typedef struct tpmc_server_s* tpmc_server;
+/* Workspace for max_slots slots and a per-triangle tally pool of tally_words int64. */
+tpmc_status tpmc_server_workspace_bytes(uint32_t max_slots, uint64_t tally_words, uint64_t* bytes);
+tpmc_status tpmc_server_create(tpmc_ctx ctx, uint32_t max_slots, uint64_t tally_words, void* dev_workspace,
+                               uint64_t ws_bytes, tpmc_server* out);
+/* Admit query q on mesh into slot (asynchronous).  Unless TPMC_Q_NO_TRIANGLE_TALLY,
+ * its per-triangle tallies occupy pool words [tally_offset, tally_offset + 7 nt).
+ * n_tiles receives the query's tile count. */
+tpmc_status tpmc_server_admit(tpmc_server s, uint32_t slot, tpmc_mesh mesh, const tpmc_query* q,
+                              uint64_t tally_offset, uint64_t* n_tiles);
+/* One step: entry i traces tiles [tile0[i], tile0[i] + count[i]) of slots[i]
+ * (n <= max_slots entries, each slot at most once).  Asynchronous. */
+tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, const uint64_t* tile0, const uint64_t* count,
+                             uint32_t n);
+/* Wait for the stream; results of the listed slots (out: host [n]). */
+tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
+                                double A_ref, tpmc_result* out);
+tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot);
+void tpmc_destroy_server(tpmc_server s);
+
 /* Host-only checks (no device needed): the validation the entry points above
  * apply.  tpmc_check_query also needs the mesh vertices for the CV test. */
 tpmc_status tpmc_check_mesh(const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt);

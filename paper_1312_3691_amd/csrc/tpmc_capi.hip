@@ -231,6 +231,10 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   q->key1 = (uint32_t)(in->seed >> 32);
   q->rmax = in->max_reflections;
   q->per_tri = (in->flags & TPMC_Q_NO_TRIANGLE_TALLY) ? 0u : 1u;
+  q->nodes = m->nodes;
+  q->tris = m->tris;
+  q->orig = m->orig;
+  q->nt = (uint32_t)m->nt;
   // Fixed point: every sampled speed is bounded (the variates never reach 0 or 1),
   // |w| <= S + 15 for seeded and specular velocities and |w| <= 8 tau after a
   // diffuse re-emission, so one hit moves at most Dmax; scales are the largest
@@ -596,7 +600,7 @@ static tpmc_status finalize_results(tpmc_ctx ctx, const Layout& L, uint32_t nq, 
                                     double A_ref, tpmc_result* out) {
   const double xr = ref_point ? ref_point[0] : 0.0, yr = ref_point ? ref_point[1] : 0.0,
                zr = ref_point ? ref_point[2] : 0.0;
-  launch_finalize(L.qs, L.scal, nq, xr, yr, zr, A_ref, L.res, ctx->stream);
+  launch_finalize(L.qs, nullptr, L.scal, nq, xr, yr, zr, A_ref, L.res, ctx->stream);
   HIP_CHECK_LAUNCH("finalize");
   std::vector<ResultDev> hr(nq);
   HIP_TRY(hipMemcpyAsync(hr.data(), L.res, nq * sizeof(ResultDev), hipMemcpyDeviceToHost, ctx->stream));
@@ -659,7 +663,6 @@ extern "C" void tpmc_destroy_tally(tpmc_tally t) { delete t; }
 // ---------------------------------------------------------------------------
 // batched path
 // ---------------------------------------------------------------------------
-static constexpr uint64_t kBatchTile = 4096;  // must equal the batch kernel's tile
 
 static tpmc_status batch_prepare(tpmc_mesh m, const tpmc_query* q, uint32_t nq, std::vector<QueryDev>& hq,
                                  std::vector<uint64_t>& tile_end, Layout& L, uint8_t* base) {
@@ -740,19 +743,17 @@ static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   zero_i64(b->lay.scal, (uint64_t)b->nq * kScalarSlots, st);
   zero_i64(b->lay.tally, b->tally_words, st);
   BatchArgs a;
-  a.nodes = m->nodes;
-  a.tris = m->tris;
-  a.orig = m->orig;
   a.qs = b->lay.qs;
+  a.entry_query = nullptr;
+  a.entry_tile0 = nullptr;
   a.tile_end = b->lay.tile_end;
   a.work_counter = b->lay.counter;
   a.tally_base = b->lay.tally;
   a.scal_base = b->lay.scal;
   a.total_tiles = b->total_tiles;
-  a.nq = b->nq;
-  a.nt = (uint32_t)m->nt;
+  a.n_entries = b->nq;
   launch_batch(a, m->stack_slots, b->mode, b->grid, st);
-  if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, a.nt, st);
+  if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, (uint32_t)m->nt, st);
 }
 
 extern "C" tpmc_status tpmc_batch_launch(tpmc_ctx ctx, tpmc_batch b, int use_graph) {
@@ -802,3 +803,185 @@ extern "C" void tpmc_destroy_batch(tpmc_batch b) {
   }
   delete b;
 }
+
+// ---------------------------------------------------------------------------
+// serving: a slot table plus one persistent launch per continuous-batching step
+// ---------------------------------------------------------------------------
+struct tpmc_server_s {
+  tpmc_ctx ctx;
+  uint32_t max_slots;
+  uint64_t tally_words;
+  QueryDev* qs;          // [max_slots]
+  ResultDev* res;        // [max_slots]
+  long long* scal;       // [max_slots][kScalarSlots]
+  long long* tally;      // pool of tally_words
+  uint32_t* e_query;     // step entries
+  uint64_t* e_tile0;
+  uint64_t* e_tile_end;
+  uint32_t* r_idx;       // slots whose results are read
+  uint32_t* counter;
+  std::vector<QueryDev> hq;
+  std::vector<tpmc_mesh> mesh_of;
+  std::vector<uint8_t> used;
+  std::vector<uint32_t> h_query, h_idx;  // staging, alive until the copies complete
+  std::vector<uint64_t> h_tile0, h_tile_end;
+};
+
+static void server_layout(uint32_t max_slots, uint64_t tally_words, uint8_t* base, tpmc_server_s* s,
+                          uint64_t* bytes) {
+  uint64_t off = 0;
+  auto take = [&](uint64_t b) {
+    const uint64_t o = off;
+    off = align256(off + b);
+    return o;
+  };
+  const uint64_t oq = take(max_slots * sizeof(QueryDev)), orr = take(max_slots * sizeof(ResultDev)),
+                 os = take((uint64_t)max_slots * kScalarSlots * 8), ot = take(tally_words * 8),
+                 oeq = take(max_slots * 4ull), oe0 = take(max_slots * 8ull), oee = take(max_slots * 8ull),
+                 ori = take(max_slots * 4ull), oc = take(64);
+  *bytes = off;
+  if (!s) return;
+  s->qs = reinterpret_cast<QueryDev*>(base + oq);
+  s->res = reinterpret_cast<ResultDev*>(base + orr);
+  s->scal = reinterpret_cast<long long*>(base + os);
+  s->tally = reinterpret_cast<long long*>(base + ot);
+  s->e_query = reinterpret_cast<uint32_t*>(base + oeq);
+  s->e_tile0 = reinterpret_cast<uint64_t*>(base + oe0);
+  s->e_tile_end = reinterpret_cast<uint64_t*>(base + oee);
+  s->r_idx = reinterpret_cast<uint32_t*>(base + ori);
+  s->counter = reinterpret_cast<uint32_t*>(base + oc);
+}
+
+extern "C" tpmc_status tpmc_server_workspace_bytes(uint32_t max_slots, uint64_t tally_words, uint64_t* bytes) {
+  if (!bytes || max_slots == 0) return fail(TPMC_E_INVALID, "need max_slots >= 1 and an output");
+  server_layout(max_slots, tally_words, nullptr, nullptr, bytes);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_create(tpmc_ctx ctx, uint32_t max_slots, uint64_t tally_words, void* ws,
+                                          uint64_t ws_bytes, tpmc_server* out) {
+  if (!ctx || !out || max_slots == 0) return fail(TPMC_E_INVALID, "ctx, out and max_slots >= 1 required");
+  *out = nullptr;
+  uint64_t need = 0;
+  server_layout(max_slots, tally_words, nullptr, nullptr, &need);
+  tpmc_status st = check_ws(ws, ws_bytes, need);
+  if (st != TPMC_OK) return st;
+  tpmc_server s = new (std::nothrow) tpmc_server_s;
+  if (!s) return fail(TPMC_E_INVALID, "out of host memory");
+  s->ctx = ctx;
+  s->max_slots = max_slots;
+  s->tally_words = tally_words;
+  server_layout(max_slots, tally_words, static_cast<uint8_t*>(ws), s, &need);
+  s->hq.assign(max_slots, QueryDev{});
+  s->mesh_of.assign(max_slots, nullptr);
+  s->used.assign(max_slots, 0);
+  *out = s;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_admit(tpmc_server s, uint32_t slot, tpmc_mesh m, const tpmc_query* q,
+                                         uint64_t tally_offset, uint64_t* n_tiles) {
+  if (!s || !m || !q) return fail(TPMC_E_INVALID, "server, mesh and query must not be NULL");
+  if (slot >= s->max_slots) return fail(TPMC_E_INVALID, "slot %u >= max_slots %u", slot, s->max_slots);
+  if (m->ctx != s->ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
+  std::vector<QueryDev> one;
+  tpmc_status st = make_queries(m, q, 1, one);
+  if (st != TPMC_OK) return st;
+  QueryDev& d = one[0];
+  d.scalar_offset = (uint64_t)slot * kScalarSlots;
+  d.tally_offset = tally_offset;
+  if (d.per_tri && (tally_offset > s->tally_words || m->nt * 7 > s->tally_words - tally_offset))
+    return fail(TPMC_E_WORKSPACE, "per-triangle tallies of %llu words at offset %llu exceed the pool of %llu",
+                (unsigned long long)(m->nt * 7), (unsigned long long)tally_offset,
+                (unsigned long long)s->tally_words);
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  s->hq[slot] = d;
+  s->mesh_of[slot] = m;
+  s->used[slot] = 1;
+  hipStream_t stv = s->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(s->qs + slot, &s->hq[slot], sizeof(QueryDev), hipMemcpyHostToDevice, stv));
+  zero_i64(s->scal + d.scalar_offset, kScalarSlots, stv);
+  if (d.per_tri) zero_i64(s->tally + tally_offset, m->nt * 7, stv);
+  HIP_CHECK_LAUNCH("admit");
+  if (n_tiles) *n_tiles = (d.N + kBatchTile - 1) / kBatchTile;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, const uint64_t* tile0,
+                                        const uint64_t* count, uint32_t n) {
+  if (!s || (n && (!slots || !tile0 || !count))) return fail(TPMC_E_INVALID, "server and step arrays required");
+  if (n == 0) return TPMC_OK;
+  if (n > s->max_slots) return fail(TPMC_E_INVALID, "%u entries > max_slots %u", n, s->max_slots);
+  s->h_query.assign(slots, slots + n);
+  s->h_tile0.assign(tile0, tile0 + n);
+  s->h_tile_end.resize(n);
+  uint64_t acc = 0;
+  int stack = 8;
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t sl = slots[i];
+    if (sl >= s->max_slots || !s->used[sl]) return fail(TPMC_E_INVALID, "entry %u names an empty slot %u", i, sl);
+    const uint64_t tiles = (s->hq[sl].N + kBatchTile - 1) / kBatchTile;
+    if (tile0[i] > tiles || count[i] > tiles - tile0[i])
+      return fail(TPMC_E_INVALID, "entry %u: tiles [%llu, +%llu) beyond the slot's %llu", i,
+                  (unsigned long long)tile0[i], (unsigned long long)count[i], (unsigned long long)tiles);
+    acc += count[i];
+    s->h_tile_end[i] = acc;
+    if (s->mesh_of[sl]->stack_slots > stack) stack = s->mesh_of[sl]->stack_slots;
+  }
+  if (acc == 0) return TPMC_OK;
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(s->e_query, s->h_query.data(), n * 4ull, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->e_tile0, s->h_tile0.data(), n * 8ull, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(s->e_tile_end, s->h_tile_end.data(), n * 8ull, hipMemcpyHostToDevice, st));
+  zero_u32(s->counter, 2, st);
+  BatchArgs a;
+  a.qs = s->qs;
+  a.entry_query = s->e_query;
+  a.entry_tile0 = s->e_tile0;
+  a.tile_end = s->e_tile_end;
+  a.work_counter = s->counter;
+  a.tally_base = s->tally;
+  a.scal_base = s->scal;
+  a.total_tiles = acc;
+  a.n_entries = n;
+  launch_batch(a, stack, kTallyAuto, s->ctx->n_cu * 8, st);
+  HIP_CHECK_LAUNCH("server step");
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
+                                           double A_ref, tpmc_result* out) {
+  if (!s || !slots || !out || n == 0) return fail(TPMC_E_INVALID, "server, slots and out required");
+  if (n > s->max_slots) return fail(TPMC_E_INVALID, "%u slots > max_slots %u", n, s->max_slots);
+  if (!(A_ref > 0.0) || !std::isfinite(A_ref)) return fail(TPMC_E_INVALID, "A_ref = %g must be > 0", A_ref);
+  if (ref_point && !finite3(ref_point)) return fail(TPMC_E_INVALID, "reference point must be finite");
+  uint32_t max_nt = 1;
+  for (uint32_t i = 0; i < n; ++i) {
+    if (slots[i] >= s->max_slots || !s->used[slots[i]]) return fail(TPMC_E_INVALID, "slot %u is empty", slots[i]);
+    if (s->hq[slots[i]].nt > max_nt) max_nt = s->hq[slots[i]].nt;
+  }
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  s->h_idx.assign(slots, slots + n);
+  HIP_TRY(hipMemcpyAsync(s->r_idx, s->h_idx.data(), n * 4ull, hipMemcpyHostToDevice, st));
+  launch_reduce_slots(s->qs, s->r_idx, n, s->tally, s->scal, max_nt, st);
+  const double xr = ref_point ? ref_point[0] : 0.0, yr = ref_point ? ref_point[1] : 0.0,
+               zr = ref_point ? ref_point[2] : 0.0;
+  launch_finalize(s->qs, s->r_idx, s->scal, n, xr, yr, zr, A_ref, s->res, st);
+  HIP_CHECK_LAUNCH("server results");
+  std::vector<ResultDev> hr(n);
+  HIP_TRY(hipMemcpyAsync(hr.data(), s->res, n * sizeof(ResultDev), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (uint32_t i = 0; i < n; ++i) copy_result(hr[i], out + i);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot) {
+  if (!s || slot >= s->max_slots) return fail(TPMC_E_INVALID, "bad server or slot");
+  s->used[slot] = 0;
+  s->mesh_of[slot] = nullptr;
+  return TPMC_OK;
+}
+
+extern "C" void tpmc_destroy_server(tpmc_server s) { delete s; }

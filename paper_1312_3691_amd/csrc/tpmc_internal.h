@@ -19,6 +19,9 @@ enum ScalarSlot {
   kFx = 8, kFy = 9, kFz = 10, kLx = 11, kLy = 12, kLz = 13, kCount = 14
 };
 
+struct Node;
+struct TriRec;
+
 // Device-side constants of one query (a1: FP64 set-up done on the host).
 struct alignas(16) QueryDev {
   double U[3], e1[3], e2[3], c0[3];  // free stream and seeding frame, CV centre (body frame)
@@ -32,6 +35,9 @@ struct alignas(16) QueryDev {
   uint64_t p_offset;                 // first particle in the SoA planes (plain path)
   uint64_t tally_offset;             // first int64 of this query's per-triangle tallies
   uint64_t scalar_offset;            // first int64 of this query's scalar block
+  const Node* nodes;                 // the query's mesh (resident BVH)
+  const TriRec* tris;
+  const uint32_t* orig;
   float Uf[3], c0f[3];
   float tau, alpha;
   float scaleF, scaleL, scaleD, scaleD2;  // fixed-point scales, powers of two
@@ -39,7 +45,8 @@ struct alignas(16) QueryDev {
   uint32_t rmax;
   uint32_t s_zero;                   // S treated as exactly 0
   uint32_t per_tri;                  // per-triangle tallies kept
-  uint32_t pad_[3];
+  uint32_t nt;                       // triangles of the query's mesh
+  uint32_t pad_[2];
 };
 
 // Device result of the finalisation kernel (mirrors tpmc_result).

@@ -187,7 +187,16 @@ __device__ __forceinline__ bool segment(const Node* __restrict__ nodes, const Tr
   if (L.hits == 0) first_id = (int32_t)id;
   ++L.hits;
   ++A.hits;
-  L.ox = px; L.oy = py; L.oz = pz;
+  // The next ray starts at the hit point moved to the side the particle leaves
+  // from by 8 FP32 ulps of the triangle's coordinate scale: the rounded
+  // barycentric point can lie a few ulps behind the surface, and a ray started
+  // there would cross a coplanar or adjacent triangle from the wrong side.
+  const float scale = fmaxf(fmaxf(fmaxf(fabsf(tr.v0x), fabsf(tr.v0y)), fmaxf(fabsf(tr.v0z), fabsf(tr.v1x))),
+                            fmaxf(fmaxf(fabsf(tr.v1y), fabsf(tr.v1z)),
+                                  fmaxf(fmaxf(fabsf(tr.v2x), fabsf(tr.v2y)), fabsf(tr.v2z))));
+  const float side = (L.wx * tr.nx + L.wy * tr.ny + L.wz * tr.nz) < 0.0f ? 1.0f : -1.0f;
+  const float eps = side * scale * 0x1p-20f;
+  L.ox = px + eps * tr.nx; L.oy = py + eps * tr.ny; L.oz = pz + eps * tr.nz;
   L.wx = nwx; L.wy = nwy; L.wz = nwz;
   L.prev = k;
   if (L.hits >= q.rmax) {
@@ -211,12 +220,12 @@ __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long
   v[0] = fx(h.dx, q.scaleF); v[1] = fx(h.dy, q.scaleF); v[2] = fx(h.dz, q.scaleF);
   v[3] = fx(h.lx, q.scaleL); v[4] = fx(h.ly, q.scaleL); v[5] = fx(h.lz, q.scaleL);
   v[6] = 1;
-  if (MODE == kTallyTotals) {
+  if (MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) {
     if (h.valid) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) A.tot[c] += v[c];
     }
-  } else if (MODE == kTallyGlobal) {
+  } else if (MODE == kTallyGlobal || MODE == kTallyAuto) {
     if (h.valid) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) atomic_add_i64(g + 7ull * h.id + c, v[c]);
@@ -240,8 +249,7 @@ __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long
 }
 
 // Wave-reduce the per-lane accumulators into a query's scalar block.
-template <bool TOTALS>
-__device__ __forceinline__ void flush_acc(const Acc& A, long long* __restrict__ scal) {
+__device__ __forceinline__ void flush_acc(const Acc& A, long long* __restrict__ scal, bool TOTALS) {
   long long s[8 + 7];
   s[0] = wave_sum(A.sD);
   s[1] = wave_sum(A.sD2);
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
       }
     }
   }
-  flush_acc<MODE == kTallyTotals>(A, a.scal);
+  flush_acc(A, a.scal, MODE == kTallyTotals);
   if (COUNT) {
     const long long nn = wave_sum((long long)A.nodes), nt2 = wave_sum((long long)A.tests);
     if ((threadIdx.x & 63) == 0) {
@@ -336,7 +344,6 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
 // queue; particle states never leave the chip.  Per-particle arithmetic is the
 // plain path's, so results match it bit for bit.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kTile = 4096;  // particles per work item
 
 template <int STACK, int MODE>
 __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
@@ -351,18 +358,19 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     const uint64_t tile = __builtin_amdgcn_readfirstlane((uint32_t)tile_sh[wave]) |
                           ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tile_sh[wave] >> 32)) << 32);
     if (tile >= a.total_tiles) break;
-    // query of this tile: first qi with tile_end[qi] > tile
-    uint32_t lo = 0, hi = a.nq - 1;
+    // entry of this tile: first j with tile_end[j] > tile
+    uint32_t lo = 0, hi = a.n_entries - 1;
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
       if (a.tile_end[mid] > tile) hi = mid;
       else lo = mid + 1;
     }
-    const uint32_t qi = lo;
-    const QueryDev& q = a.qs[qi];
-    const uint64_t first_tile = qi == 0 ? 0ull : a.tile_end[qi - 1];
-    const uint64_t p_begin = (tile - first_tile) * kTile;
-    const uint64_t p_end = p_begin + kTile < q.N ? p_begin + kTile : q.N;
+    const uint32_t j = lo;
+    const QueryDev& q = a.qs[a.entry_query ? a.entry_query[j] : j];
+    const uint64_t first_tile = j == 0 ? 0ull : a.tile_end[j - 1];
+    const uint64_t tile_in_q = (a.entry_tile0 ? a.entry_tile0[j] : 0ull) + (tile - first_tile);
+    const uint64_t p_begin = tile_in_q * kBatchTile;
+    const uint64_t p_end = p_begin + kBatchTile < q.N ? p_begin + kBatchTile : q.N;
     long long* qtally = q.per_tri ? a.tally_base + q.tally_offset : nullptr;
     long long* scal = a.scal_base + q.scalar_offset;
 
@@ -419,14 +427,14 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       h.valid = false;
       bool done = false;
       int32_t fid;
-      if (L.live) done = segment<STACK, false>(a.nodes, a.tris, a.orig, q, L, A, h, stk, fid);
-      tally<MODE>(q, h, qtally, nullptr, a.nt, A);
+      if (L.live) done = segment<STACK, false>(q.nodes, q.tris, q.orig, q, L, A, h, stk, fid);
+      tally<MODE>(q, h, qtally, nullptr, q.nt, A);
       if (L.live && done) {
         retire(q, L, A);
         L.live = false;
       }
     }
-    flush_acc<MODE == kTallyTotals>(A, scal);
+    flush_acc(A, scal, MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri));
   }
 }
 
@@ -464,19 +472,20 @@ __global__ __launch_bounds__(kBlock) void reduce_kernel(const long long* __restr
 
 __global__ __launch_bounds__(kBlock) void reduce_batch_kernel(const QueryDev* __restrict__ qs,
                                                               long long* __restrict__ tally_base,
-                                                              long long* __restrict__ scal_base, uint32_t nt) {
+                                                              long long* __restrict__ scal_base) {
   const QueryDev& q = qs[blockIdx.y];
-  if (!q.per_tri) return;
-  reduce_one(tally_base + q.tally_offset, nt, scal_base + q.scalar_offset, blockIdx.x);
+  if (!q.per_tri || blockIdx.x * (uint32_t)kReduceChunk >= q.nt) return;
+  reduce_one(tally_base + q.tally_offset, q.nt, scal_base + q.scalar_offset, blockIdx.x);
 }
 
 // F/q = K sum(w - w'), K = 2 Gamma_hat / (N S^2) (eq. drag with the effective
 // mass of Sec. II.A); moment about x_ref from the moment about the CV centre.
-__global__ void finalize_kernel(const QueryDev* __restrict__ qs, const long long* __restrict__ scal_base, uint32_t nq,
-                                double xr, double yr, double zr, double A_ref, ResultDev* __restrict__ out) {
+__global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ idx,
+                                const long long* __restrict__ scal_base, uint32_t nq, double xr, double yr, double zr,
+                                double A_ref, ResultDev* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nq) return;
-  const QueryDev& q = qs[i];
+  const QueryDev& q = qs[idx ? idx[i] : i];
   const long long* s = scal_base + q.scalar_offset;
   const double N = (double)q.N;
   double F[3], Lc[3];
@@ -530,6 +539,7 @@ void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t
   switch (mode) {
     case kTallyWave: batch_kernel<STACK, kTallyWave><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyTotals: batch_kernel<STACK, kTallyTotals><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyAuto: batch_kernel<STACK, kTallyAuto><<<grid, kBlock, 0, st>>>(a); break;
     default: batch_kernel<STACK, kTallyGlobal><<<grid, kBlock, 0, st>>>(a); break;
   }
 }
@@ -579,15 +589,41 @@ void launch_reduce(const long long* tally, uint32_t nt, long long* scal, hipStre
   reduce_kernel<<<g, kBlock, 0, st>>>(tally, nt, scal);
 }
 
-void launch_reduce_batch(const QueryDev* d_qs, uint32_t nq, long long* tally_base, long long* scal_base, uint32_t nt,
-                         hipStream_t st) {
-  dim3 g((nt + kReduceChunk - 1) / kReduceChunk, nq);
-  reduce_batch_kernel<<<g, kBlock, 0, st>>>(d_qs, tally_base, scal_base, nt);
+void launch_reduce_batch(const QueryDev* d_qs, uint32_t nq, long long* tally_base, long long* scal_base,
+                         uint32_t max_nt, hipStream_t st) {
+  dim3 g((max_nt + kReduceChunk - 1) / kReduceChunk, nq);
+  reduce_batch_kernel<<<g, kBlock, 0, st>>>(d_qs, tally_base, scal_base);
 }
 
-void launch_finalize(const QueryDev* d_qs, const long long* scal_base, uint32_t nq, double xr, double yr, double zr,
-                     double A_ref, ResultDev* out, hipStream_t st) {
-  finalize_kernel<<<(nq + 63) / 64, 64, 0, st>>>(d_qs, scal_base, nq, xr, yr, zr, A_ref, out);
+void launch_finalize(const QueryDev* d_qs, const uint32_t* d_idx, const long long* scal_base, uint32_t nq, double xr,
+                     double yr, double zr, double A_ref, ResultDev* out, hipStream_t st) {
+  finalize_kernel<<<(nq + 63) / 64, 64, 0, st>>>(d_qs, d_idx, scal_base, nq, xr, yr, zr, A_ref, out);
+}
+
+// Per-triangle reduction of a list of slots (serving): entry y reduces slot idx[y].
+__global__ __launch_bounds__(kBlock) void reduce_slots_kernel(const QueryDev* __restrict__ qs,
+                                                              const uint32_t* __restrict__ idx,
+                                                              long long* __restrict__ tally_base,
+                                                              long long* __restrict__ scal_base) {
+  const QueryDev& q = qs[idx[blockIdx.y]];
+  if (!q.per_tri || blockIdx.x * (uint32_t)kReduceChunk >= q.nt) return;
+  reduce_one(tally_base + q.tally_offset, q.nt, scal_base + q.scalar_offset, blockIdx.x);
+}
+
+// Clears slots kFx..kCount of the listed per-triangle queries before a reduction.
+__global__ void clear_totals_kernel(const QueryDev* __restrict__ qs, const uint32_t* __restrict__ idx,
+                                    long long* __restrict__ scal_base, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * 7u) return;
+  const QueryDev& q = qs[idx ? idx[i / 7u] : i / 7u];
+  if (q.per_tri) scal_base[q.scalar_offset + kFx + i % 7u] = 0;
+}
+
+void launch_reduce_slots(const QueryDev* d_qs, const uint32_t* d_idx, uint32_t n, long long* tally_base,
+                         long long* scal_base, uint32_t max_nt, hipStream_t st) {
+  clear_totals_kernel<<<(n * 7 + 255) / 256, 256, 0, st>>>(d_qs, d_idx, scal_base, n);
+  dim3 g((max_nt + kReduceChunk - 1) / kReduceChunk, n);
+  reduce_slots_kernel<<<g, kBlock, 0, st>>>(d_qs, d_idx, tally_base, scal_base);
 }
 
 }  // namespace tpmc

@@ -10,7 +10,9 @@
 namespace tpmc {
 
 // Tally strategy of the trace kernels.
-enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyWave = 2, kTallyTotals = 3 };
+// Auto: per query, global per-triangle atomics or register totals (serving steps
+// that mix both kinds of request).
+enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyWave = 2, kTallyTotals = 3, kTallyAuto = 4 };
 
 struct TraceArgs {
   const Node* nodes;
@@ -27,19 +29,22 @@ struct TraceArgs {
   uint32_t nt;
 };
 
+// One persistent launch covers n_entries entries; entry j is a range of tiles
+// of query entry_query[j] starting at tile entry_tile0[j] (a whole batch:
+// entry j = query j from tile 0; a serving step: any slots, any ranges).
 struct BatchArgs {
-  const Node* nodes;
-  const TriRec* tris;
-  const uint32_t* orig;
-  const QueryDev* qs;         // [nq]
-  const uint64_t* tile_end;   // [nq] inclusive prefix sum of tiles per query
-  uint32_t* work_counter;     // zeroed before the launch
-  long long* tally_base;      // per-triangle tallies, indexed by QueryDev::tally_offset
-  long long* scal_base;       // scalar blocks, indexed by QueryDev::scalar_offset
+  const QueryDev* qs;           // query / slot table (meshes referenced per query)
+  const uint32_t* entry_query;  // [n_entries] or null (entry j is query j)
+  const uint64_t* entry_tile0;  // [n_entries] or null (start at tile 0)
+  const uint64_t* tile_end;     // [n_entries] inclusive prefix sum of the entries' tile counts
+  uint32_t* work_counter;       // 64-bit counter, zeroed before the launch
+  long long* tally_base;        // per-triangle tallies, indexed by QueryDev::tally_offset
+  long long* scal_base;         // scalar blocks, indexed by QueryDev::scalar_offset
   uint64_t total_tiles;
-  uint32_t nq;
-  uint32_t nt;
+  uint32_t n_entries;
 };
+
+constexpr uint64_t kBatchTile = 4096;  // particles per work item of the persistent kernel
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
 void zero_u32(uint32_t* p, uint64_t n, hipStream_t st);
@@ -53,10 +58,12 @@ int stack_slots_for_depth(uint32_t depth);  // 0 when too deep
 void launch_seed(const QueryDev* d_q, uint64_t n, float* const x[3], float* const w[3], int grid, hipStream_t st);
 void launch_trace(const TraceArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
 void launch_reduce(const long long* tally, uint32_t nt, long long* scal, hipStream_t st);
-void launch_finalize(const QueryDev* d_qs, const long long* scal_base, uint32_t nq, double xr, double yr, double zr,
-                     double A_ref, ResultDev* out, hipStream_t st);
+void launch_finalize(const QueryDev* d_qs, const uint32_t* d_idx, const long long* scal_base, uint32_t nq, double xr,
+                     double yr, double zr, double A_ref, ResultDev* out, hipStream_t st);
+void launch_reduce_slots(const QueryDev* d_qs, const uint32_t* d_idx, uint32_t n, long long* tally_base,
+                         long long* scal_base, uint32_t max_nt, hipStream_t st);
 void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
-void launch_reduce_batch(const QueryDev* d_qs, uint32_t nq, long long* tally_base, long long* scal_base, uint32_t nt,
-                         hipStream_t st);
+void launch_reduce_batch(const QueryDev* d_qs, uint32_t nq, long long* tally_base, long long* scal_base,
+                         uint32_t max_nt, hipStream_t st);
 
 }  // namespace tpmc

@@ -84,6 +84,13 @@ _SIGS = {
     "tpmc_batch_launch": ([_vp, _vp, ctypes.c_int], ctypes.c_int),
     "tpmc_batch_results": ([_vp, _vp, _dp, ctypes.c_double, _RP], ctypes.c_int),
     "tpmc_destroy_batch": ([_vp], None),
+    "tpmc_server_workspace_bytes": ([_u32, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_server_create": ([_vp, _u32, _u64, _vp, _u64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_server_admit": ([_vp, _u32, _vp, _QP, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_server_step": ([_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64), _u32], ctypes.c_int),
+    "tpmc_server_results": ([_vp, ctypes.POINTER(_u32), _u32, _dp, ctypes.c_double, _RP], ctypes.c_int),
+    "tpmc_server_release": ([_vp, _u32], ctypes.c_int),
+    "tpmc_destroy_server": ([_vp], None),
     "tpmc_check_mesh": ([_fp, _u64, ctypes.POINTER(_u32), _u64], ctypes.c_int),
     "tpmc_check_query": ([_QP, _fp, _u64], ctypes.c_int),
 }
@@ -329,6 +336,62 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             _lib.tpmc_destroy_batch(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """libtpmc serving slots (continuous batching); see paper_1312_3691_amd.serve."""
+
+    def __init__(self, ctx: Context, max_slots: int, pool_words: int):
+        self.ctx = ctx
+        self.max_slots = int(max_slots)
+        nbytes = _u64()
+        _check(_lib.tpmc_server_workspace_bytes(self.max_slots, int(pool_words), ctypes.byref(nbytes)))
+        self.ws_tensor, self.ws_ptr, self.ws_bytes = _workspace(nbytes.value, ctx.device)
+        h = _vp()
+        _check(_lib.tpmc_server_create(ctx._h, self.max_slots, int(pool_words), _vp(self.ws_ptr), self.ws_bytes,
+                                       ctypes.byref(h)))
+        self._h = h
+        self._q = {}
+
+    def admit(self, slot: int, mesh: Mesh, qd: dict, tally_offset: int = 0) -> int:
+        q = make_query(qd)
+        self._q[slot] = (q, mesh)
+        nt = _u64()
+        _check(_lib.tpmc_server_admit(self._h, int(slot), mesh._h, ctypes.byref(q), int(tally_offset),
+                                      ctypes.byref(nt)))
+        return int(nt.value)
+
+    def step(self, entries):
+        n = len(entries)
+        if n == 0:
+            return
+        sl = (_u32 * n)(*[int(e[0]) for e in entries])
+        t0 = (_u64 * n)(*[int(e[1]) for e in entries])
+        ct = (_u64 * n)(*[int(e[2]) for e in entries])
+        _check(_lib.tpmc_server_step(self._h, sl, t0, ct, n))
+
+    def results(self, slots, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0):
+        n = len(slots)
+        sl = (_u32 * n)(*[int(s) for s in slots])
+        res = (Result * n)()
+        xr = (ctypes.c_double * 3)(*[float(v) for v in x_ref])
+        _check(_lib.tpmc_server_results(self._h, sl, n, xr, float(A_ref), res))
+        return [result_dict(r) for r in res]
+
+    def release(self, slot: int):
+        _check(_lib.tpmc_server_release(self._h, int(slot)))
+        self._q.pop(slot, None)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.tpmc_destroy_server(self._h)
             self._h = None
 
     def __del__(self):
