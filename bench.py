@@ -99,7 +99,7 @@ def cpu_baseline(case_list, mesh_map, budget_s=15.0):
     threads = min(os.cpu_count() or 1, 16)
     # calibrate on one plate and one cylinder case
     t0 = time.perf_counter()
-    probe = 2000
+    probe = 20000
     for c in (case_list[0], case_list[-1]):
         V, T = mesh_map[c["kind"]]
         O.run(V, T, c["query"], p_range=(0, probe), threads=threads)

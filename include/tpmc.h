@@ -187,7 +187,7 @@ void tpmc_destroy_batch(tpmc_batch b);
  * step is ONE persistent launch over any set of (slot, tile range) entries --
  * slots of different meshes and sizes run together -- and tallies accumulate
  * exactly across steps, so a request's result does not depend on how its tiles
- * were spread over steps or which requests shared them.  Tiles hold 4096
+ * were spread over steps or which requests shared them.  Tiles hold 16384
  * particles.  Slot and pool bookkeeping (admission by memory budget) is the
  * caller's policy; the library checks bounds. */
 typedef struct tpmc_server_s* tpmc_server;

@@ -183,6 +183,10 @@ __global__ void karras_kernel(const uint32_t* __restrict__ keys, int n, Node* __
 __global__ void pack_tris_kernel(const float* __restrict__ xyz, const uint32_t* __restrict__ tri,
                                  const uint32_t* __restrict__ order, uint32_t nt, TriRec* __restrict__ recs,
                                  uint32_t* __restrict__ orig) {
+  // Products evaluated without contraction: a component that is exactly zero
+  // (e.g. a vertical face) stays zero instead of becoming an FMA residue whose
+  // sign would choose a different tangent basis at re-emission.
+#pragma clang fp contract(off)
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nt) return;
   const uint32_t id = order[k];

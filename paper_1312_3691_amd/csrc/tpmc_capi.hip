@@ -315,7 +315,7 @@ static uint64_t total_particles(const std::vector<QueryDev>& hq) {
 
 static TallyMode plain_mode(const QueryDev& q, uint64_t nt) {
   if (!q.per_tri) return kTallyTotals;
-  if (nt <= (uint64_t)kWaveTallyMaxTris) return kTallyWave;
+  if (nt <= (uint64_t)kRegTallyMaxTris) return kTallyRegs;
   if (nt <= (uint64_t)kLdsTallyMaxTris) return kTallyLds;
   return kTallyGlobal;
 }
@@ -718,7 +718,9 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
     delete b;
     return fail(TPMC_E_INVALID, "a batch must use one tally kind (TPMC_Q_NO_TRIANGLE_TALLY on all or none)");
   }
-  b->mode = !any_tri ? kTallyTotals : (m->nt <= (uint64_t)kWaveTallyMaxTris ? kTallyWave : kTallyGlobal);
+  b->mode = !any_tri ? kTallyTotals
+                     : (m->nt <= (uint64_t)kRegTallyMaxTris ? kTallyRegs
+                                                            : (m->nt <= (uint64_t)kLdsTallyMaxTris ? kTallyLds : kTallyGlobal));
   b->grid = ctx->n_cu * 8;
   b->exec = nullptr;
   b->launched = false;

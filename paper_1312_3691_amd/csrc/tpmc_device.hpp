@@ -62,20 +62,41 @@ __device__ __forceinline__ float unif32(uint32_t k) { return ((float)(k >> 9) + 
 // g(phi|S) with d(mu) = cos(phi) d(phi); chi(s) = e^{-s^2} + sqrt(pi) s (1 + erf s).
 // Its CDF numerator G(t) = int_{-1}^t chi(S m) dm is the difference of the
 // antiderivative sqrt(pi)/(4S) erf(St) + sqrt(pi) S t^2 (1 + erf St)/2 + t e^{-S^2 t^2}/2
-// at t and -1, arranged so that no term cancels.  G' = chi(S t) > 0, so the
-// equation G(mu) = u Z is solved by Newton's method inside a shrinking bracket.
+// at t and -1, arranged so that no term cancels.  G' = chi(S t) > 0 and
+// G'' = S sqrt(pi) (1 + erf St), so the equation G(mu) = u Z is solved by
+// Halley's method inside a shrinking bracket.  Every evaluation costs one exp
+// and one erfc: the alternative forms below are selected values, not calls.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG) {
+__device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG, double& d2G) {
   const double S = q.S;
   const double St = S * t;
   const double e = exp(-St * St);
   const double c = erfc(-St);  // 1 + erf(S t)
   double E;                    // erf(S t) + erf(S)
-  if (St < -1.0) E = c - q.erfcS;
-  else if (S < 0.25) E = erf(St) + q.erfS;
-  else E = (c - 1.0) + q.erfS;
+  if (S < 0.25) E = erf(St) + q.erfS;  // uniform branch: small S keeps erf(St) exact
+  else E = St < -1.0 ? c - q.erfcS : (c - 1.0) + q.erfS;
   G = kSqrtPi / (4.0 * S) * E + 0.5 * kSqrtPi * S * (t * t * c - q.erfcS) + 0.5 * (t * e + q.expmS2);
   dG = e + kSqrtPi * St * c;
+  d2G = S * kSqrtPi * c;
+}
+
+// One Halley step inside the bracket [lo, hi], bisection when the step leaves
+// it.  Returns |step| of a Halley (or Newton) step, or +inf after a bisection,
+// so that only a genuine iteration step can end the solve.  The bounds are
+// inclusive: a step below one ulp leaves x unchanged and ends the solve.
+__device__ __forceinline__ double halley_step(double& x, double f, double df, double d2f, double& lo, double& hi) {
+  if (f < 0.0) lo = x;
+  else hi = x;
+  const double nt = f / df;
+  const double den = 1.0 - 0.5 * nt * d2f / df;
+  const double xn = x - (den > 0.5 && den < 2.0 ? nt / den : nt);
+  if (xn >= lo && xn <= hi) {
+    const double dx = fabs(xn - x);
+    x = xn;
+    return dx;
+  }
+  x = 0.5 * (lo + hi);
+  return __builtin_inf();
 }
 
 __device__ inline double sample_latitude(const QueryDev& q, double u) {
@@ -85,23 +106,21 @@ __device__ inline double sample_latitude(const QueryDev& q, double u) {
   const double wgt = q.S * q.S / (1.0 + q.S * q.S);
   double x = (1.0 - wgt) * (2.0 * u - 1.0) + wgt * sqrt(u);
   double lo = -1.0, hi = 1.0;
+#pragma unroll 1
   for (int it = 0; it < 100; ++it) {
-    double G, dG;
-    latitude_G(q, x, G, dG);
-    const double f = G - target;
-    if (f < 0.0) lo = x;
-    else hi = x;
-    double xn = x - f / dG;
-    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-    const double dx = xn - x;
-    x = xn;
-    if (fabs(dx) <= 1e-15 || hi - lo <= 1e-15) break;
+    double G, dG, d2G;
+    latitude_G(q, x, G, dG, d2G);
+    const double dx = halley_step(x, G - target, dG, d2G, lo, hi);
+    // cubic convergence: after a step below 1e-7 the remaining error is far
+    // below the FP64 resolution of mu
+    if (dx <= 1e-7 || hi - lo <= 1e-15) break;
   }
   return x;
 }
 
 // Inward normal speed x = v_n / c_mp >= 0 of eq. vel_dist1, p(x|s) = 2x e^{-(x-s)^2} / chi(s).
-// CDF numerator F(x) = e^{-s^2} - e^{-(x-s)^2} + sqrt(pi) s (erf(x-s) + erf s), F' = 2x e^{-(x-s)^2}.
+// CDF numerator F(x) = e^{-s^2} - e^{-(x-s)^2} + sqrt(pi) s (erf(x-s) + erf s),
+// F' = 2x e^{-(x-s)^2}, F'' = 2 e^{-(x-s)^2} (1 - 2x(x-s)).
 struct NormalSpeedConsts {
   double s, es2, erfs, erfcs, erfcms, chi;
 };
@@ -110,22 +129,24 @@ __device__ __forceinline__ NormalSpeedConsts normal_speed_consts(double s) {
   NormalSpeedConsts k;
   k.s = s;
   k.es2 = exp(-s * s);
-  k.erfcms = erfc(-s);  // 1 + erf(s)
-  k.erfcs = erfc(s);
-  k.erfs = erf(s);
+  const double t = erfc(fabs(s));  // the small one of erfc(s), erfc(-s)
+  k.erfcs = s >= 0.0 ? t : 2.0 - t;
+  k.erfcms = s >= 0.0 ? 2.0 - t : t;  // 1 + erf(s)
+  k.erfs = s >= 0.0 ? 1.0 - t : t - 1.0;
   k.chi = k.es2 + kSqrtPi * s * k.erfcms;
   return k;
 }
 
-__device__ __forceinline__ void normal_speed_F(const NormalSpeedConsts& k, double x, double& F, double& dF) {
+__device__ __forceinline__ void normal_speed_F(const NormalSpeedConsts& k, double x, double& F, double& dF,
+                                               double& d2F) {
   const double a = x - k.s;
   const double ea = exp(-a * a);
-  double esum;  // erf(x - s) + erf(s)
-  if (k.s < 0.0) esum = k.erfcms - erfc(a);
-  else if (a < 0.0) esum = erfc(-a) - k.erfcs;
-  else esum = erf(a) + k.erfs;
+  const double t = erfc(fabs(a));
+  // erf(x - s) + erf(s) as a difference of small erfc values wherever a sum would cancel
+  const double esum = k.s < 0.0 ? k.erfcms - t : (a < 0.0 ? t - k.erfcs : (1.0 - t) + k.erfs);
   F = k.es2 - ea + kSqrtPi * k.s * esum;
   dF = 2.0 * x * ea;
+  d2F = 2.0 * ea * (1.0 - 2.0 * x * a);
 }
 
 __device__ inline double sample_normal_speed(double s, double u) {
@@ -135,25 +156,16 @@ __device__ inline double sample_normal_speed(double s, double u) {
   double x;
   if (s > 1.0) x = s + 0.5 / s + erfinv(2.0 * u - 1.0);
   else x = sqrt(-log1p(-u)) + (s > 0.0 ? 0.5 * s : 0.0);
+  // The root lies below max(s, 0) + 7: the upper tail there is below e^{-49},
+  // far under the smallest 1 - u the variates produce (2^-33).
   double lo = 0.0, hi = (s > 0.0 ? s : 0.0) + 7.0;
-  for (int g = 0; g < 8; ++g) {  // make sure [lo, hi] brackets the root
-    double F, dF;
-    normal_speed_F(k, hi, F, dF);
-    if (F >= target) break;
-    hi *= 2.0;
-  }
   if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+#pragma unroll 1
   for (int it = 0; it < 100; ++it) {
-    double F, dF;
-    normal_speed_F(k, x, F, dF);
-    const double f = F - target;
-    if (f < 0.0) lo = x;
-    else hi = x;
-    double xn = x - f / dF;
-    if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-    const double dx = xn - x;
-    x = xn;
-    if (fabs(dx) <= 1e-15 * x || hi - lo <= 1e-15 * x) break;
+    double F, dF, d2F;
+    normal_speed_F(k, x, F, dF, d2F);
+    const double dx = halley_step(x, F - target, dF, d2F, lo, hi);
+    if (dx <= 1e-7 * x || hi - lo <= 1e-15 * x) break;
   }
   return x;
 }

@@ -135,6 +135,7 @@ struct Hit {
 // Per-lane exact integer accumulators.
 struct Acc {
   long long sD, sD2, tot[7];
+  long long tri2[2 * 7];  // per-triangle sums of a mesh of at most two triangles
   uint32_t rays, hits, segs, missed, escaped, capped;
   uint32_t nodes, tests;  // traversal work (counting kernels only)
 };
@@ -143,6 +144,8 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
   A.sD = A.sD2 = 0;
 #pragma unroll
   for (int c = 0; c < 7; ++c) A.tot[c] = 0;
+#pragma unroll
+  for (int c = 0; c < 14; ++c) A.tri2[c] = 0;
   A.rays = A.hits = A.segs = A.missed = A.escaped = A.capped = 0;
   A.nodes = A.tests = 0;
 }
@@ -235,16 +238,23 @@ __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long
 #pragma unroll
       for (int c = 0; c < 7; ++c) atomicAdd(lds + 7u * h.id + c, (unsigned long long)v[c]);
     }
-  } else {  // kTallyWave: aggregate lanes that hit the same triangle, one atomic per wave
-    for (uint32_t tri = 0; tri < nt; ++tri) {
-      const bool mine = h.valid && h.id == tri;
-      if (__ballot(mine) == 0ull) continue;
+  } else {  // kTallyRegs: per-lane registers, flushed once (meshes of <= 2 triangles)
+    if (h.valid) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) {
-        const long long s = wave_sum(mine ? v[c] : 0ll);
-        if ((threadIdx.x & 63) == 0) atomic_add_i64(g + 7ull * tri + c, s);
+        A.tri2[c] += h.id == 0 ? v[c] : 0ll;
+        A.tri2[7 + c] += h.id == 1 ? v[c] : 0ll;
       }
     }
+  }
+}
+
+// Flush of the register tallies of a <= 2-triangle mesh (convergent).
+__device__ __forceinline__ void flush_tri2(const Acc& A, long long* __restrict__ g, uint32_t nt) {
+#pragma unroll
+  for (int c = 0; c < 14; ++c) {
+    const long long s = wave_sum(A.tri2[c]);
+    if ((threadIdx.x & 63) == 0 && s != 0 && c < (int)nt * 7) atomic_add_i64(g + c, s);
   }
 }
 
@@ -322,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
     }
   }
   flush_acc(A, a.scal, MODE == kTallyTotals);
+  if (MODE == kTallyRegs) flush_tri2(A, a.tally, a.nt);
   if (COUNT) {
     const long long nn = wave_sum((long long)A.nodes), nt2 = wave_sum((long long)A.tests);
     if ((threadIdx.x & 63) == 0) {
@@ -337,27 +348,31 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// a11: persistent batched kernel.  Each wave takes (query, tile) work items
-// from a device counter.  It seeds 64 particles at a time with every lane
-// active (the FP64 seeding is the costliest per-particle step) into a
-// wave-private LDS queue, and lanes whose particle retires refill from that
-// queue; particle states never leave the chip.  Per-particle arithmetic is the
+// a11: persistent batched kernel.  Each workgroup takes (query, tile) work
+// items from a device counter; its four waves share the tile, claiming 64
+// particles at a time from a workgroup counter in LDS.  A wave seeds its 64
+// particles with every lane active (the FP64 seeding is the costliest
+// per-particle step) into a wave-private LDS queue, and lanes whose particle
+// retires refill from that queue; particle states never leave the chip.  For
+// meshes of up to kLdsTallyMaxTris triangles the per-triangle sums go to a
+// workgroup LDS tally flushed once per tile.  Per-particle arithmetic is the
 // plain path's, so results match it bit for bit.
 // ---------------------------------------------------------------------------
 
 template <int STACK, int MODE>
 __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
+  constexpr bool kMayLds = MODE == kTallyLds || MODE == kTallyAuto;
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
-  __shared__ uint64_t tile_sh[kBlock / 64];
+  __shared__ unsigned long long lt[kMayLds ? kLdsTallyMaxTris * 7 : 1];
+  __shared__ unsigned long long tile_sh, next_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
   for (;;) {
-    if (lane == 0) tile_sh[wave] = atomicAdd(reinterpret_cast<unsigned long long*>(a.work_counter), 1ull);
-    __builtin_amdgcn_wave_barrier();
-    const uint64_t tile = __builtin_amdgcn_readfirstlane((uint32_t)tile_sh[wave]) |
-                          ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(tile_sh[wave] >> 32)) << 32);
-    if (tile >= a.total_tiles) break;
+    if (threadIdx.x == 0) tile_sh = atomicAdd(reinterpret_cast<unsigned long long*>(a.work_counter), 1ull);
+    __syncthreads();
+    const uint64_t tile = tile_sh;
+    if (tile >= a.total_tiles) break;  // uniform over the workgroup
     // entry of this tile: first j with tile_end[j] > tile
     uint32_t lo = 0, hi = a.n_entries - 1;
     while (lo < hi) {
@@ -373,36 +388,48 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     const uint64_t p_end = p_begin + kBatchTile < q.N ? p_begin + kBatchTile : q.N;
     long long* qtally = q.per_tri ? a.tally_base + q.tally_offset : nullptr;
     long long* scal = a.scal_base + q.scalar_offset;
+    const bool use_lds = kMayLds && q.per_tri && q.nt <= (uint32_t)kLdsTallyMaxTris;
+    if (threadIdx.x == 0) next_sh = p_begin;
+    if (use_lds)
+      for (uint32_t i = threadIdx.x; i < q.nt * 7u; i += kBlock) lt[i] = 0ull;
+    __syncthreads();
 
     Acc A;
     acc_zero(A);
     Lane L;
     L.live = false;
-    uint64_t next_seed = p_begin;   // next particle to seed (wave-uniform)
+    bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
     uint64_t q_pid0 = 0;               // particle id of queue slot 0
     for (;;) {
       const uint64_t dead = __ballot(!L.live);
       const uint32_t ndead = __popcll(dead);
-      if (q_count == 0 && next_seed < p_end && (ndead >= 16 || ndead == 64)) {
-        // seed the next (up to) 64 particles, one per lane
-        const uint64_t pid = next_seed + lane;
-        if (pid < p_end) {
-          double x[3], w[3];
-          seed_particle(q, pid, x, w);
-          qbuf[wave][0][lane] = (float)x[0];
-          qbuf[wave][1][lane] = (float)x[1];
-          qbuf[wave][2][lane] = (float)x[2];
-          qbuf[wave][3][lane] = (float)w[0];
-          qbuf[wave][4][lane] = (float)w[1];
-          qbuf[wave][5][lane] = (float)w[2];
+      if (q_count == 0 && !exhausted && ndead >= 16) {
+        // claim and seed the next (up to) 64 particles, one per lane
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&next_sh, 64ull);
+        base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
+               ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
+        if (base >= p_end) {
+          exhausted = true;
+        } else {
+          const uint64_t pid = base + lane;
+          if (pid < p_end) {
+            double x[3], w[3];
+            seed_particle(q, pid, x, w);
+            qbuf[wave][0][lane] = (float)x[0];
+            qbuf[wave][1][lane] = (float)x[1];
+            qbuf[wave][2][lane] = (float)x[2];
+            qbuf[wave][3][lane] = (float)w[0];
+            qbuf[wave][4][lane] = (float)w[1];
+            qbuf[wave][5][lane] = (float)w[2];
+          }
+          const uint64_t left = p_end - base;
+          q_count = left < 64 ? (uint32_t)left : 64u;
+          q_head = 0;
+          q_pid0 = base;
+          __builtin_amdgcn_wave_barrier();
         }
-        const uint64_t left = p_end - next_seed;
-        q_count = left < 64 ? (uint32_t)left : 64u;
-        q_head = 0;
-        q_pid0 = next_seed;
-        next_seed += q_count;
-        __builtin_amdgcn_wave_barrier();
       }
       if (q_count > 0 && dead != 0ull) {
         // dead lanes take queue entries in lane order
@@ -422,19 +449,29 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         q_count -= took;
         __builtin_amdgcn_wave_barrier();
       }
-      if (__ballot(L.live) == 0ull) break;  // queue empty, nothing left to seed
+      if (__ballot(L.live) == 0ull) {
+        if (exhausted && q_count == 0) break;
+        continue;  // nothing in flight: claim more next round
+      }
       Hit h;
       h.valid = false;
       bool done = false;
       int32_t fid;
       if (L.live) done = segment<STACK, false>(q.nodes, q.tris, q.orig, q, L, A, h, stk, fid);
-      tally<MODE>(q, h, qtally, nullptr, q.nt, A);
+      if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
+      else tally<MODE>(q, h, qtally, nullptr, q.nt, A);
       if (L.live && done) {
         retire(q, L, A);
         L.live = false;
       }
     }
     flush_acc(A, scal, MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri));
+    if (MODE == kTallyRegs) flush_tri2(A, qtally, q.nt);
+    __syncthreads();  // every wave is done with the tile
+    if (use_lds)
+      for (uint32_t i = threadIdx.x; i < q.nt * 7u; i += kBlock)
+        if (lt[i]) atomic_add_i64(qtally + i, (long long)lt[i]);
+    __syncthreads();  // before the next tile reuses tile_sh, next_sh and lt
   }
 }
 
@@ -523,7 +560,7 @@ void launch_trace_mode(const TraceArgs& a, TallyMode mode, int grid, hipStream_t
   switch (mode) {
     case kTallyGlobal: trace_kernel<STACK, kTallyGlobal, COUNT><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyLds: trace_kernel<STACK, kTallyLds, COUNT><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyWave: trace_kernel<STACK, kTallyWave, COUNT><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyRegs: trace_kernel<STACK, kTallyRegs, COUNT><<<grid, kBlock, 0, st>>>(a); break;
     default: trace_kernel<STACK, kTallyTotals, COUNT><<<grid, kBlock, 0, st>>>(a); break;
   }
 }
@@ -537,7 +574,8 @@ void launch_trace_stack(const TraceArgs& a, TallyMode mode, int grid, hipStream_
 template <int STACK>
 void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t st) {
   switch (mode) {
-    case kTallyWave: batch_kernel<STACK, kTallyWave><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyRegs: batch_kernel<STACK, kTallyRegs><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyLds: batch_kernel<STACK, kTallyLds><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyTotals: batch_kernel<STACK, kTallyTotals><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyAuto: batch_kernel<STACK, kTallyAuto><<<grid, kBlock, 0, st>>>(a); break;
     default: batch_kernel<STACK, kTallyGlobal><<<grid, kBlock, 0, st>>>(a); break;

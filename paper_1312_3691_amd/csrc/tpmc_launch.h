@@ -12,7 +12,7 @@ namespace tpmc {
 // Tally strategy of the trace kernels.
 // Auto: per query, global per-triangle atomics or register totals (serving steps
 // that mix both kinds of request).
-enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyWave = 2, kTallyTotals = 3, kTallyAuto = 4 };
+enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyRegs = 2, kTallyTotals = 3, kTallyAuto = 4 };
 
 struct TraceArgs {
   const Node* nodes;
@@ -44,7 +44,7 @@ struct BatchArgs {
   uint32_t n_entries;
 };
 
-constexpr uint64_t kBatchTile = 4096;  // particles per work item of the persistent kernel
+constexpr uint64_t kBatchTile = 16384;  // particles per work item (one workgroup) of the persistent kernel
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
 void zero_u32(uint32_t* p, uint64_t n, hipStream_t st);

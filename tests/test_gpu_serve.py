@@ -29,7 +29,7 @@ def test_served_results_equal_solo_runs():
                     flags=(1 if i % 4 == 0 else 0))
         reqs.append((mesh, q))
     ex = GpuExecutor(ctx, meshes, max_slots=5, pool_words=7 * 4000 * 3)
-    sched = Scheduler(ex, max_slots=5, pool_words=7 * 4000 * 3, tiles_per_step=6)
+    sched = Scheduler(ex, max_slots=5, pool_words=7 * 4000 * 3, tiles_per_step=2)
 
     async def main():
         stop = asyncio.Event()
@@ -46,7 +46,7 @@ def test_served_results_equal_solo_runs():
         return res
 
     served = asyncio.run(main())
-    assert sched.stats.max_active > 1 and sched.stats.steps > len(reqs)
+    assert sched.stats.max_active > 1 and sched.stats.steps >= 8  # several requests per step, several steps each
     for (mesh, q), got in zip(reqs, served):
         solo, pr = tpmc.run(meshes[mesh], [q])
         for k, v in solo[0].items():
