@@ -117,6 +117,225 @@ def cpu_baseline(case_list, mesh_map, budget_s=15.0):
                       f"({m * len(case_list)} particles, {hits} hits, {dt:.1f} s wall)"}
 
 
+COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read + 1 GiB written per launch
+COPY_LAUNCHES = 4
+
+
+def copy_calibration():
+    """Plain device-to-device copies of known size, for scaling the HBM counters."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(COPY_LAUNCHES):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": COPY_LAUNCHES}))
+
+
+def _counter_rows(path, counter):
+    """(kernel name, dispatch id, value in KiB) from a rocprofv3 counter_collection.csv."""
+    import csv
+    rows = []
+    for fn in [os.path.join(dp, f) for dp, _, fs in os.walk(path) for f in fs if f.endswith("counter_collection.csv")]:
+        for r in csv.DictReader(open(fn)):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    return rows
+
+
+def summarize_traffic(pmc_dir, path=None):
+    """Writes profiles/traffic.json from four rocprofv3 --pmc runs under pmc_dir:
+    bench_fetch, bench_write (this benchmark with --steps 1 --warmup 0 --no-cpu
+    --no-plain) and copy_fetch, copy_write (--copy-calibration)."""
+    out = {}
+    scale = {}
+    for c, sub in (("FETCH_SIZE", "copy_fetch"), ("WRITE_SIZE", "copy_write")):
+        vals = [v for n, _, v in _counter_rows(os.path.join(pmc_dir, sub), c) if "copy" in n.lower() or "elementwise" in n.lower()]
+        per = sorted(vals)[len(vals) // 2] * 1024.0  # median dispatch, bytes as the counter reads them
+        scale[c] = COPY_BYTES / per
+    per_mesh = {}
+    for c, sub in (("FETCH_SIZE", "bench_fetch"), ("WRITE_SIZE", "bench_write")):
+        import re
+        for n, d, v in _counter_rows(os.path.join(pmc_dir, sub), c):
+            m = re.search(r"(?<![a-z_])batch_kernel<[^>]*>", n)
+            if m:
+                per_mesh.setdefault(m.group(0), {}).setdefault(c, []).append(v * 1024.0 * scale[c])
+    step_bytes = 0.0
+    detail = {}
+    for k, d in per_mesh.items():
+        f = sorted(d["FETCH_SIZE"])[len(d["FETCH_SIZE"]) // 2]
+        w = sorted(d["WRITE_SIZE"])[len(d["WRITE_SIZE"]) // 2]
+        detail[k] = {"fetch_bytes": f, "write_bytes": w}
+        step_bytes += f + w
+    out["batch_kernel"] = {"plate+cylinder sweep, 120 cases x 1e7 particles": {
+        "bytes_per_launch": step_bytes, "unit_note": "both mesh launches of one step", "kernel_hash": kernel_hash(),
+        "counter_scale": scale, "per_kernel": detail}}
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def _line(metric, value, unit, dt, steps, warmup, config, extra):
+    d = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps, "warmup": warmup,
+         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+         "dtype": "f32+f64", "data": "synthetic", "config": config}
+    d.update(extra)
+    print(json.dumps(d), flush=True)
+
+
+def workload_satellite(args):
+    """Concave satellite (~50k triangles), S = 7, alpha = 0.9, 1e8 particles, one query:
+    plain path (seed -> trace -> forces) and the batched kernel on the same query."""
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    ctx = tpmc.Context(0)
+    V, T = I.satellite(50_000)
+    mesh = ctx.build_mesh(V, T)
+    U = (-0.5, 0.0, -math.sqrt(3.0) / 2.0)
+    n = int(args.particles_sat)
+    q = I.query(q=I.quat_for_flow(U), S=7.0, T_inf=T_INF, T_w=T_W, alpha=0.9, n=n, seed=0, max_reflections=16)
+    b = tpmc.Batch(mesh, [q])
+    b.launch().results()
+    for _ in range(args.warmup):
+        b.launch(use_graph=True).results()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = b.launch(use_graph=True).results()[0]
+    dt = (time.perf_counter() - t0) / args.steps
+    t1 = time.perf_counter()
+    rp, pr = tpmc.run(mesh, [q])
+    pdt = time.perf_counter() - t1
+    pr.close()
+    _line("particle-surface hits/sec on 1 MI355X (concave satellite)", r["hits"] / dt, "hits/s", dt, args.steps,
+          args.warmup, {"workload": f"concave satellite {len(T)} tris, S=7, alpha=0.9, {n} particles, 16 reflections",
+                        "path": "batched persistent launch, graph replay"},
+          {"CD": r["CD"], "CD_sigma": r["CD_sigma"], "hits_per_particle": r["hits"] / n,
+           "segments_per_s": r["segments"] / dt, "capped": r["capped"], "bvh_depth": mesh.info["depth"],
+           "plain_path": {"hits_per_s": rp[0]["hits"] / pdt, "s": pdt, "CD": rp[0]["CD"]}})
+
+
+def workload_sweep(args):
+    """1024 uniform-random attitudes x S ~ U[2, 10], 1e6 particles each, on the ~50k-triangle
+    satellite: one persistent graph-replayed launch against 1024 plain calls (host sync each)."""
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    ctx = tpmc.Context(0)
+    V, T = I.satellite(50_000)
+    mesh = ctx.build_mesh(V, T)
+    nq = 1024
+    quats = I.random_quats(nq, 1)
+    S = 2.0 + 8.0 * np.random.default_rng(1).random(nq)
+    qs = [I.query(q=tuple(quats[i]), S=float(S[i]), T_inf=T_INF, T_w=T_W, alpha=0.9, n=int(args.particles_sweep),
+                  seed=i, flags=1) for i in range(nq)]
+    b = tpmc.Batch(mesh, qs)
+    b.launch().results()
+    for _ in range(args.warmup):
+        b.launch(use_graph=True).results()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = b.launch(use_graph=True).results()
+    dt = (time.perf_counter() - t0) / args.steps
+    hits = sum(r["hits"] for r in res)
+    # plain path on the same queries, one call per query (timed on the first 128, scaled)
+    k = 128
+    for c in qs[:2]:
+        tpmc.run(mesh, [c])[1].close()
+    t1 = time.perf_counter()
+    p_hits = 0
+    lat = []
+    for c in qs[:k]:
+        t2 = time.perf_counter()
+        r, pr = tpmc.run(mesh, [c])
+        lat.append((time.perf_counter() - t2) * 1e3)
+        p_hits += r[0]["hits"]
+        pr.close()
+    pdt = time.perf_counter() - t1
+    same = all(r["CD"] == rr["CD"] for r, rr in zip(tpmc.run(mesh, qs[:4])[0], res[:4]))
+    _line("particle-surface hits/sec on 1 MI355X (batched attitude sweep)", hits / dt, "hits/s", dt, args.steps,
+          args.warmup, {"workload": f"satellite {len(T)} tris, {nq} attitudes x S~U[2,10], "
+                                    f"{int(args.particles_sweep)} particles each, per-query totals",
+                        "path": "one persistent graph-replayed launch"},
+          {"plain_path": {"hits_per_s": p_hits / pdt, "queries_timed": k, "query_ms_p50": float(np.percentile(lat, 50)),
+                          "query_ms_p99": float(np.percentile(lat, 99))},
+           "batched_over_plain": (hits / dt) / (p_hits / pdt), "first_queries_equal_plain": bool(same)})
+
+
+def workload_served(args):
+    """Served stream: Poisson arrivals over four resident satellite meshes (~1k, 20k, 100k,
+    500k triangles), random attitudes, S ~ U[2, 10], N log-uniform in [1e5, 1e7]."""
+    import asyncio
+
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    from paper_1312_3691_amd.serve import GpuExecutor, Scheduler
+    ctx = tpmc.Context(0)
+    sizes = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
+    meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i)) for i, (k, v) in enumerate(sizes.items())}
+    rng = np.random.default_rng(7)
+    n_req = int(args.requests)
+    names = list(sizes)
+    quats = I.random_quats(n_req, 3)
+    reqs = []
+    for i in range(n_req):
+        n = int(10 ** rng.uniform(5, 7))
+        reqs.append((names[rng.integers(0, 4)], I.query(q=tuple(quats[i]), S=float(rng.uniform(2, 10)), T_inf=T_INF,
+                                                         T_w=T_W, alpha=0.9, n=n, seed=10_000 + i, flags=1)))
+    max_slots = 64
+    ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=1 << 20)
+    # saturation: everything submitted at once
+    def run(rate):
+        sched = Scheduler(ex, max_slots=max_slots, pool_words=1 << 20, tiles_per_step=int(args.tiles_per_step))
+        gaps = rng.exponential(1.0 / rate, n_req) if rate else np.zeros(n_req)
+
+        async def main():
+            stop = asyncio.Event()
+            runner = asyncio.ensure_future(sched.run(stop))
+            futs = []
+            for (mesh, q), g in zip(reqs, gaps):
+                if g > 0:
+                    await asyncio.sleep(float(g))
+                futs.append(sched.submit(mesh, q))
+            res = await asyncio.gather(*futs)
+            stop.set()
+            sched._wake.set()
+            await runner
+            return res
+        t0 = time.perf_counter()
+        res = asyncio.run(main())
+        dt = time.perf_counter() - t0
+        p50, p99 = sched.percentiles()
+        return res, dt, p50, p99, sched.stats
+    res, dt, p50, p99, st = run(0)
+    hits = sum(r["hits"] for r in res)
+    sat_rate = n_req / dt
+    loads = {}
+    for frac in (0.5, 0.8):
+        r2, dt2, a, b, st2 = run(frac * sat_rate)
+        loads[str(frac)] = {"offered_req_per_s": frac * sat_rate, "p50_ms": a, "p99_ms": b,
+                            "hits_per_s": sum(x["hits"] for x in r2) / dt2, "steps": st2.steps}
+    # every served result equals its solo run (first 8 requests)
+    same = True
+    for (mesh, q), r in list(zip(reqs, res))[:8]:
+        solo, pr = tpmc.run(meshes[mesh], [q])
+        same = same and all(np.array_equal(np.asarray(solo[0][k]), np.asarray(r[k])) for k in solo[0])
+        pr.close()
+    torch.cuda.synchronize()
+    _line("particle-surface hits/sec on 1 MI355X (served stream); p50/p99 query ms", hits / dt, "hits/s", dt, 1, 0,
+          {"workload": f"{n_req} requests over satellites {list(sizes.values())} tris, N log-uniform 1e5-1e7, "
+                       f"S~U[2,10], alpha=0.9", "path": "continuous batching, one persistent launch per step"},
+          {"saturation": {"req_per_s": sat_rate, "p50_ms": p50, "p99_ms": p99, "steps": st.steps,
+                          "max_active": st.max_active},
+           "loads": loads, "query_ms_p50": p50, "query_ms_p99": p99, "served_equals_solo": bool(same)})
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,11 +344,29 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--particles", type=int, default=N_PER_CASE, help="particles per case (default 1e7)")
+    ap.add_argument("--copy-calibration", action="store_true", help="run only the HBM-counter calibration copies")
+    ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
+    ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
+    ap.add_argument("--workload", default="plate-cylinder", choices=["plate-cylinder", "satellite", "sweep", "served"],
+                    help="plate-cylinder (default, the benchmark line) or an additional configuration")
+    ap.add_argument("--particles-sat", type=float, default=1e8)
+    ap.add_argument("--particles-sweep", type=float, default=1e6)
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--tiles-per-step", type=int, default=2048)
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic, args.traffic_out)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the drag path shards by particle range, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "plate-cylinder":
+        {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served}[args.workload](args)
+        return
 
     import torch
 

@@ -71,8 +71,8 @@ struct Layout {
   ResultDev* res;
   long long* scal;
   long long* tally;
-  uint64_t* tile_end;
-  uint32_t* counter;
+  uint64_t* tiles;       // batch: tiles per query
+  unsigned long long* next;  // batch: claim counter per query
   float* planes[6];
   uint64_t bytes;
 };
@@ -95,7 +95,7 @@ struct tpmc_batch_s {
   tpmc_mesh mesh;
   uint32_t nq;
   std::vector<QueryDev> hq;
-  std::vector<uint64_t> tile_end;
+  std::vector<uint64_t> tiles;
   Layout lay;
   uint64_t total_tiles;
   uint64_t tally_words;
@@ -274,7 +274,7 @@ static tpmc_status make_queries(tpmc_mesh m, const tpmc_query* q, uint32_t nq, s
 // ---------------------------------------------------------------------------
 static uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
-// Lays out [queries | results | scalar blocks | tallies | tile map | counter | 6 planes].
+// Lays out [queries | results | scalar blocks | tallies | tiles | claim counters | 6 planes].
 static void layout(std::vector<QueryDev>& hq, uint64_t nt, uint64_t n_planes, bool batch, uint8_t* base, Layout& L) {
   const uint64_t nq = hq.size();
   uint64_t off = 0;
@@ -294,7 +294,7 @@ static void layout(std::vector<QueryDev>& hq, uint64_t nt, uint64_t n_planes, bo
   }
   const uint64_t o_t = take(words * sizeof(long long));
   const uint64_t o_te = take(batch ? nq * sizeof(uint64_t) : 0);
-  const uint64_t o_c = take(batch ? 64 : 0);
+  const uint64_t o_c = take(batch ? nq * sizeof(uint64_t) : 0);
   uint64_t o_p[6];
   for (int k = 0; k < 6; ++k) o_p[k] = take(n_planes * sizeof(float));
   L.bytes = off;
@@ -302,8 +302,8 @@ static void layout(std::vector<QueryDev>& hq, uint64_t nt, uint64_t n_planes, bo
   L.res = reinterpret_cast<ResultDev*>(base + o_r);
   L.scal = reinterpret_cast<long long*>(base + o_s);
   L.tally = reinterpret_cast<long long*>(base + o_t);
-  L.tile_end = reinterpret_cast<uint64_t*>(base + o_te);
-  L.counter = reinterpret_cast<uint32_t*>(base + o_c);
+  L.tiles = reinterpret_cast<uint64_t*>(base + o_te);
+  L.next = reinterpret_cast<unsigned long long*>(base + o_c);
   for (int k = 0; k < 6; ++k) L.planes[k] = reinterpret_cast<float*>(base + o_p[k]);
 }
 
@@ -665,15 +665,11 @@ extern "C" void tpmc_destroy_tally(tpmc_tally t) { delete t; }
 // ---------------------------------------------------------------------------
 
 static tpmc_status batch_prepare(tpmc_mesh m, const tpmc_query* q, uint32_t nq, std::vector<QueryDev>& hq,
-                                 std::vector<uint64_t>& tile_end, Layout& L, uint8_t* base) {
+                                 std::vector<uint64_t>& tiles, Layout& L, uint8_t* base) {
   tpmc_status s = make_queries(m, q, nq, hq);
   if (s != TPMC_OK) return s;
-  tile_end.resize(nq);
-  uint64_t acc = 0;
-  for (uint32_t i = 0; i < nq; ++i) {
-    acc += (hq[i].N + kBatchTile - 1) / kBatchTile;
-    tile_end[i] = acc;
-  }
+  tiles.resize(nq);
+  for (uint32_t i = 0; i < nq; ++i) tiles[i] = (hq[i].N + kBatchTile - 1) / kBatchTile;
   layout(hq, m->nt, 0, true, base, L);
   return TPMC_OK;
 }
@@ -697,7 +693,7 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
   if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
   tpmc_batch b = new (std::nothrow) tpmc_batch_s;
   if (!b) return fail(TPMC_E_INVALID, "out of host memory");
-  tpmc_status s = batch_prepare(m, q, nq, b->hq, b->tile_end, b->lay, static_cast<uint8_t*>(ws));
+  tpmc_status s = batch_prepare(m, q, nq, b->hq, b->tiles, b->lay, static_cast<uint8_t*>(ws));
   if (s == TPMC_OK) s = check_ws(ws, ws_bytes, b->lay.bytes);
   if (s != TPMC_OK) {
     delete b;
@@ -706,7 +702,8 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
   b->ctx = ctx;
   b->mesh = m;
   b->nq = nq;
-  b->total_tiles = b->tile_end.back();
+  b->total_tiles = 0;
+  for (uint64_t t : b->tiles) b->total_tiles += t;
   b->tally_words = 0;
   bool any_tri = false, all_tri = true;
   for (const auto& hq : b->hq) {
@@ -728,7 +725,7 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->lay.qs, b->hq.data(), nq * sizeof(QueryDev), hipMemcpyHostToDevice, ctx->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(b->lay.tile_end, b->tile_end.data(), nq * sizeof(uint64_t), hipMemcpyHostToDevice,
+    e = hipMemcpyAsync(b->lay.tiles, b->tiles.data(), nq * sizeof(uint64_t), hipMemcpyHostToDevice,
                        ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
@@ -741,18 +738,17 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
 
 static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   tpmc_mesh m = b->mesh;
-  zero_u32(b->lay.counter, 2, st);
+  zero_i64(reinterpret_cast<long long*>(b->lay.next), b->nq, st);
   zero_i64(b->lay.scal, (uint64_t)b->nq * kScalarSlots, st);
   zero_i64(b->lay.tally, b->tally_words, st);
   BatchArgs a;
   a.qs = b->lay.qs;
   a.entry_query = nullptr;
   a.entry_tile0 = nullptr;
-  a.tile_end = b->lay.tile_end;
-  a.work_counter = b->lay.counter;
+  a.entry_tiles = b->lay.tiles;
+  a.entry_next = b->lay.next;
   a.tally_base = b->lay.tally;
   a.scal_base = b->lay.scal;
-  a.total_tiles = b->total_tiles;
   a.n_entries = b->nq;
   launch_batch(a, m->stack_slots, b->mode, b->grid, st);
   if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, (uint32_t)m->nt, st);
@@ -819,14 +815,14 @@ struct tpmc_server_s {
   long long* tally;      // pool of tally_words
   uint32_t* e_query;     // step entries
   uint64_t* e_tile0;
-  uint64_t* e_tile_end;
+  uint64_t* e_tiles;
   uint32_t* r_idx;       // slots whose results are read
-  uint32_t* counter;
+  unsigned long long* e_next;
   std::vector<QueryDev> hq;
   std::vector<tpmc_mesh> mesh_of;
   std::vector<uint8_t> used;
   std::vector<uint32_t> h_query, h_idx;  // staging, alive until the copies complete
-  std::vector<uint64_t> h_tile0, h_tile_end;
+  std::vector<uint64_t> h_tile0, h_tiles;
 };
 
 static void server_layout(uint32_t max_slots, uint64_t tally_words, uint8_t* base, tpmc_server_s* s,
@@ -840,7 +836,7 @@ static void server_layout(uint32_t max_slots, uint64_t tally_words, uint8_t* bas
   const uint64_t oq = take(max_slots * sizeof(QueryDev)), orr = take(max_slots * sizeof(ResultDev)),
                  os = take((uint64_t)max_slots * kScalarSlots * 8), ot = take(tally_words * 8),
                  oeq = take(max_slots * 4ull), oe0 = take(max_slots * 8ull), oee = take(max_slots * 8ull),
-                 ori = take(max_slots * 4ull), oc = take(64);
+                 ori = take(max_slots * 4ull), oc = take(max_slots * 8ull);
   *bytes = off;
   if (!s) return;
   s->qs = reinterpret_cast<QueryDev*>(base + oq);
@@ -849,9 +845,9 @@ static void server_layout(uint32_t max_slots, uint64_t tally_words, uint8_t* bas
   s->tally = reinterpret_cast<long long*>(base + ot);
   s->e_query = reinterpret_cast<uint32_t*>(base + oeq);
   s->e_tile0 = reinterpret_cast<uint64_t*>(base + oe0);
-  s->e_tile_end = reinterpret_cast<uint64_t*>(base + oee);
+  s->e_tiles = reinterpret_cast<uint64_t*>(base + oee);
   s->r_idx = reinterpret_cast<uint32_t*>(base + ori);
-  s->counter = reinterpret_cast<uint32_t*>(base + oc);
+  s->e_next = reinterpret_cast<unsigned long long*>(base + oc);
 }
 
 extern "C" tpmc_status tpmc_server_workspace_bytes(uint32_t max_slots, uint64_t tally_words, uint64_t* bytes) {
@@ -916,7 +912,7 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   if (n > s->max_slots) return fail(TPMC_E_INVALID, "%u entries > max_slots %u", n, s->max_slots);
   s->h_query.assign(slots, slots + n);
   s->h_tile0.assign(tile0, tile0 + n);
-  s->h_tile_end.resize(n);
+  s->h_tiles.assign(count, count + n);
   uint64_t acc = 0;
   int stack = 8;
   for (uint32_t i = 0; i < n; ++i) {
@@ -927,7 +923,6 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
       return fail(TPMC_E_INVALID, "entry %u: tiles [%llu, +%llu) beyond the slot's %llu", i,
                   (unsigned long long)tile0[i], (unsigned long long)count[i], (unsigned long long)tiles);
     acc += count[i];
-    s->h_tile_end[i] = acc;
     if (s->mesh_of[sl]->stack_slots > stack) stack = s->mesh_of[sl]->stack_slots;
   }
   if (acc == 0) return TPMC_OK;
@@ -935,17 +930,16 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   hipStream_t st = s->ctx->stream;
   HIP_TRY(hipMemcpyAsync(s->e_query, s->h_query.data(), n * 4ull, hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(s->e_tile0, s->h_tile0.data(), n * 8ull, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s->e_tile_end, s->h_tile_end.data(), n * 8ull, hipMemcpyHostToDevice, st));
-  zero_u32(s->counter, 2, st);
+  HIP_TRY(hipMemcpyAsync(s->e_tiles, s->h_tiles.data(), n * 8ull, hipMemcpyHostToDevice, st));
+  zero_i64(reinterpret_cast<long long*>(s->e_next), n, st);
   BatchArgs a;
   a.qs = s->qs;
   a.entry_query = s->e_query;
   a.entry_tile0 = s->e_tile0;
-  a.tile_end = s->e_tile_end;
-  a.work_counter = s->counter;
+  a.entry_tiles = s->e_tiles;
+  a.entry_next = s->e_next;
   a.tally_base = s->tally;
   a.scal_base = s->scal;
-  a.total_tiles = acc;
   a.n_entries = n;
   launch_batch(a, stack, kTallyAuto, s->ctx->n_cu * 8, st);
   HIP_CHECK_LAUNCH("server step");

@@ -348,54 +348,84 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// a11: persistent batched kernel.  Each workgroup takes (query, tile) work
-// items from a device counter; its four waves share the tile, claiming 64
-// particles at a time from a workgroup counter in LDS.  A wave seeds its 64
-// particles with every lane active (the FP64 seeding is the costliest
-// per-particle step) into a wave-private LDS queue, and lanes whose particle
-// retires refill from that queue; particle states never leave the chip.  For
-// meshes of up to kLdsTallyMaxTris triangles the per-triangle sums go to a
-// workgroup LDS tally flushed once per tile.  Per-particle arithmetic is the
-// plain path's, so results match it bit for bit.
+// a11: persistent batched kernel.  A workgroup claims tiles of one work entry
+// (a query, or a range of its tiles) from that entry's counter until the entry
+// is exhausted, then moves to the next entry with work left; its four waves
+// share each tile, claiming 64 particles at a time from a workgroup counter in
+// LDS.  A wave seeds its 64 particles with every lane active (the FP64 seeding
+// is the costliest per-particle step) into a wave-private LDS queue, and lanes
+// whose particle retires refill from that queue; particle states never leave
+// the chip.  Partial sums -- per-lane scalars, per-lane register tallies of
+// tiny meshes, the workgroup's LDS tally of meshes up to kLdsTallyMaxTris
+// triangles -- stay on chip while the workgroup stays on one query and are
+// flushed to HBM with atomics only when it changes query or finishes.
+// Per-particle arithmetic is the plain path's, so results match it bit for bit.
 // ---------------------------------------------------------------------------
 
 template <int STACK, int MODE>
 __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   constexpr bool kMayLds = MODE == kTallyLds || MODE == kTallyAuto;
+  constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
   __shared__ unsigned long long lt[kMayLds ? kLdsTallyMaxTris * 7 : 1];
   __shared__ unsigned long long tile_sh, next_sh;
+  __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint32_t scan = blockIdx.x % a.n_entries;  // thread 0's position in the entry list
+  uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
+  Acc A;
+  acc_zero(A);
   for (;;) {
-    if (threadIdx.x == 0) tile_sh = atomicAdd(reinterpret_cast<unsigned long long*>(a.work_counter), 1ull);
-    __syncthreads();
-    const uint64_t tile = tile_sh;
-    if (tile >= a.total_tiles) break;  // uniform over the workgroup
-    // entry of this tile: first j with tile_end[j] > tile
-    uint32_t lo = 0, hi = a.n_entries - 1;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (a.tile_end[mid] > tile) hi = mid;
-      else lo = mid + 1;
+    if (threadIdx.x == 0) {
+      // claim a tile: current entry first, then the following ones (bounded scan)
+      uint32_t found = kNone;
+      unsigned long long t = 0;
+      for (uint32_t k = 0; k < a.n_entries; ++k) {
+        const uint64_t cap = a.entry_tiles[scan];
+        if (__hip_atomic_load(&a.entry_next[scan], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cap) {
+          t = atomicAdd(&a.entry_next[scan], 1ull);
+          if (t < cap) {
+            found = scan;
+            break;
+          }
+        }
+        scan = scan + 1 == a.n_entries ? 0u : scan + 1;
+      }
+      entry_sh = found;
+      tile_sh = t;
     }
-    const uint32_t j = lo;
+    __syncthreads();
+    const uint32_t j = entry_sh;  // uniform over the workgroup
+    const uint64_t tile = tile_sh;
+    if (j != held && held != kNone) {
+      // leaving the held query: flush its partial sums
+      const QueryDev& qh = a.qs[a.entry_query ? a.entry_query[held] : held];
+      long long* htally = qh.per_tri ? a.tally_base + qh.tally_offset : nullptr;
+      flush_acc(A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri));
+      if (MODE == kTallyRegs) flush_tri2(A, htally, qh.nt);
+      acc_zero(A);
+      if (kMayLds && qh.per_tri && qh.nt <= (uint32_t)kLdsTallyMaxTris)
+        for (uint32_t i = threadIdx.x; i < qh.nt * 7u; i += kBlock)
+          if (lt[i]) atomic_add_i64(htally + i, (long long)lt[i]);
+    }
+    if (j == kNone) break;  // uniform
     const QueryDev& q = a.qs[a.entry_query ? a.entry_query[j] : j];
-    const uint64_t first_tile = j == 0 ? 0ull : a.tile_end[j - 1];
-    const uint64_t tile_in_q = (a.entry_tile0 ? a.entry_tile0[j] : 0ull) + (tile - first_tile);
+    const bool use_lds = kMayLds && q.per_tri && q.nt <= (uint32_t)kLdsTallyMaxTris;
+    if (j != held) {
+      __syncthreads();  // the flush above has read lt
+      if (use_lds)
+        for (uint32_t i = threadIdx.x; i < q.nt * 7u; i += kBlock) lt[i] = 0ull;
+      held = j;
+    }
+    const uint64_t tile_in_q = (a.entry_tile0 ? a.entry_tile0[j] : 0ull) + tile;
     const uint64_t p_begin = tile_in_q * kBatchTile;
     const uint64_t p_end = p_begin + kBatchTile < q.N ? p_begin + kBatchTile : q.N;
     long long* qtally = q.per_tri ? a.tally_base + q.tally_offset : nullptr;
-    long long* scal = a.scal_base + q.scalar_offset;
-    const bool use_lds = kMayLds && q.per_tri && q.nt <= (uint32_t)kLdsTallyMaxTris;
     if (threadIdx.x == 0) next_sh = p_begin;
-    if (use_lds)
-      for (uint32_t i = threadIdx.x; i < q.nt * 7u; i += kBlock) lt[i] = 0ull;
     __syncthreads();
 
-    Acc A;
-    acc_zero(A);
     Lane L;
     L.live = false;
     bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
@@ -465,13 +495,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         L.live = false;
       }
     }
-    flush_acc(A, scal, MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri));
-    if (MODE == kTallyRegs) flush_tri2(A, qtally, q.nt);
-    __syncthreads();  // every wave is done with the tile
-    if (use_lds)
-      for (uint32_t i = threadIdx.x; i < q.nt * 7u; i += kBlock)
-        if (lt[i]) atomic_add_i64(qtally + i, (long long)lt[i]);
-    __syncthreads();  // before the next tile reuses tile_sh, next_sh and lt
+    __syncthreads();  // every wave is done with the tile; tile_sh / entry_sh / next_sh may be reused
   }
 }
 

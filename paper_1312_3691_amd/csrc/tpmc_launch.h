@@ -29,18 +29,20 @@ struct TraceArgs {
   uint32_t nt;
 };
 
-// One persistent launch covers n_entries entries; entry j is a range of tiles
-// of query entry_query[j] starting at tile entry_tile0[j] (a whole batch:
+// One persistent launch covers n_entries entries; entry j is entry_tiles[j]
+// tiles of query entry_query[j] starting at tile entry_tile0[j] (a whole batch:
 // entry j = query j from tile 0; a serving step: any slots, any ranges).
+// Workgroups claim tiles entry by entry (entry_next[j] counts the claimed
+// tiles), so a workgroup stays on one query and flushes its partial sums only
+// when it moves to another.
 struct BatchArgs {
-  const QueryDev* qs;           // query / slot table (meshes referenced per query)
-  const uint32_t* entry_query;  // [n_entries] or null (entry j is query j)
-  const uint64_t* entry_tile0;  // [n_entries] or null (start at tile 0)
-  const uint64_t* tile_end;     // [n_entries] inclusive prefix sum of the entries' tile counts
-  uint32_t* work_counter;       // 64-bit counter, zeroed before the launch
-  long long* tally_base;        // per-triangle tallies, indexed by QueryDev::tally_offset
-  long long* scal_base;         // scalar blocks, indexed by QueryDev::scalar_offset
-  uint64_t total_tiles;
+  const QueryDev* qs;              // query / slot table (meshes referenced per query)
+  const uint32_t* entry_query;     // [n_entries] or null (entry j is query j)
+  const uint64_t* entry_tile0;     // [n_entries] or null (start at tile 0)
+  const uint64_t* entry_tiles;     // [n_entries] tiles to trace per entry
+  unsigned long long* entry_next;  // [n_entries] claim counters, zeroed before the launch
+  long long* tally_base;           // per-triangle tallies, indexed by QueryDev::tally_offset
+  long long* scal_base;            // scalar blocks, indexed by QueryDev::scalar_offset
   uint32_t n_entries;
 };
 
