@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 1
+#define TPMC_ABI_VERSION 2
 
 typedef enum {
   TPMC_OK = 0,
@@ -109,6 +109,27 @@ int tpmc_abi_version(void);
 tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out);
 tpmc_status tpmc_set_stream(tpmc_ctx ctx, void* hip_stream);
 void tpmc_destroy_ctx(tpmc_ctx ctx);
+
+/* Launch tuning of a context.  No setting changes any result: particles are
+ * independent (Sec. II.A), each draws from its own counter-based stream, and
+ * every sum is an exact integer sum, so results are bit-identical under any
+ * tuning.  Set by the autotuner (paper_1312_3691_amd/autotune.py) or by hand;
+ * a context starts with the defaults below. */
+typedef struct {
+  uint32_t refill_lanes;   /* 1..64, default 48: a wave serves the lanes whose ray segment has ended
+                              (re-emission, tallies, next segment or particle) once fewer than this
+                              many of its 64 lanes are still traversing */
+  uint32_t tile_particles; /* multiple of 64 in [64, 2^22], default 16384: particles per work tile
+                              of the persistent kernel; read when a batch or server is created */
+  uint32_t groups_per_cu;  /* 1..32, default 8: workgroups (256 lanes) per compute unit of the
+                              persistent launches and the cap of the plain trace grid */
+  uint32_t reserved;       /* must be 0 */
+} tpmc_tuning;
+
+/* Copy out / replace the context's tuning.  set validates every field
+ * (TPMC_E_INVALID, nothing changed, on any field out of range). */
+tpmc_status tpmc_get_tuning(tpmc_ctx ctx, tpmc_tuning* out);
+tpmc_status tpmc_set_tuning(tpmc_ctx ctx, const tpmc_tuning* t);
 
 /* Mesh and its linear BVH (Karras 2012 hierarchy over 30-bit Morton codes of
  * the triangle centroids; closest-hit tracing on a triangulation, Sec. II.A).
@@ -187,7 +208,8 @@ void tpmc_destroy_batch(tpmc_batch b);
  * step is ONE persistent launch over any set of (slot, tile range) entries --
  * slots of different meshes and sizes run together -- and tallies accumulate
  * exactly across steps, so a request's result does not depend on how its tiles
- * were spread over steps or which requests shared them.  Tiles hold 16384
+ * were spread over steps or which requests shared them.  Tiles hold the
+ * context's tile_particles at tpmc_server_create (default 16384)
  * particles.  Slot and pool bookkeeping (admission by memory budget) is the
  * caller's policy; the library checks bounds. */
 typedef struct tpmc_server_s* tpmc_server;

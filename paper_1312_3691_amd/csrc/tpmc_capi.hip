@@ -51,6 +51,7 @@ struct tpmc_ctx_s {
   hipStream_t stream;
   hipStream_t capture_stream;
   int n_cu;
+  tpmc_tuning tune;
 };
 
 struct tpmc_mesh_s {
@@ -101,6 +102,8 @@ struct tpmc_batch_s {
   uint64_t tally_words;
   TallyMode mode;
   int grid;
+  uint32_t tile;
+  uint32_t refill;
   hipGraphExec_t exec;
   bool launched;
 };
@@ -315,7 +318,7 @@ static uint64_t total_particles(const std::vector<QueryDev>& hq) {
 
 static TallyMode plain_mode(const QueryDev& q, uint64_t nt) {
   if (!q.per_tri) return kTallyTotals;
-  if (nt <= (uint64_t)kRegTallyMaxTris) return kTallyRegs;
+  if (nt <= (uint64_t)kLaneTallyMaxTris) return kTallyLane;
   if (nt <= (uint64_t)kLdsTallyMaxTris) return kTallyLds;
   return kTallyGlobal;
 }
@@ -341,7 +344,30 @@ extern "C" tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out) 
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->capture_stream = nullptr;
   c->n_cu = prop.multiProcessorCount;
+  c->tune.refill_lanes = 48;
+  c->tune.tile_particles = 16384;
+  c->tune.groups_per_cu = 8;
+  c->tune.reserved = 0;
   *out = c;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_get_tuning(tpmc_ctx ctx, tpmc_tuning* out) {
+  if (!ctx || !out) return fail(TPMC_E_INVALID, "ctx and out must not be NULL");
+  *out = ctx->tune;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_set_tuning(tpmc_ctx ctx, const tpmc_tuning* t) {
+  if (!ctx || !t) return fail(TPMC_E_INVALID, "ctx and tuning must not be NULL");
+  if (t->refill_lanes < 1 || t->refill_lanes > 64)
+    return fail(TPMC_E_INVALID, "refill_lanes = %u outside 1..64", t->refill_lanes);
+  if (t->tile_particles < 64 || t->tile_particles > (1u << 22) || t->tile_particles % 64 != 0)
+    return fail(TPMC_E_INVALID, "tile_particles = %u is not a multiple of 64 in [64, 2^22]", t->tile_particles);
+  if (t->groups_per_cu < 1 || t->groups_per_cu > 32)
+    return fail(TPMC_E_INVALID, "groups_per_cu = %u outside 1..32", t->groups_per_cu);
+  if (t->reserved != 0) return fail(TPMC_E_INVALID, "reserved must be 0");
+  ctx->tune = *t;
   return TPMC_OK;
 }
 
@@ -532,7 +558,7 @@ extern "C" tpmc_status tpmc_particles_planes(tpmc_particles p, float* dev_planes
 
 static int trace_grid(tpmc_ctx ctx, uint64_t n) {
   const uint64_t g = (n + kBlock - 1) / kBlock;
-  const uint64_t cap = (uint64_t)ctx->n_cu * 8;
+  const uint64_t cap = (uint64_t)ctx->n_cu * ctx->tune.groups_per_cu;
   return (int)(g < cap ? (g ? g : 1) : cap);
 }
 
@@ -559,6 +585,7 @@ extern "C" tpmc_status tpmc_trace_ex(tpmc_ctx ctx, tpmc_mesh m, tpmc_particles p
     a.first_tri = dev_first_tri ? dev_first_tri + hq.p_offset : nullptr;
     a.counters = reinterpret_cast<unsigned long long*>(dev_counters);
     a.nt = (uint32_t)m->nt;
+    a.refill = ctx->tune.refill_lanes;
     launch_trace(a, m->stack_slots, plain_mode(hq, m->nt), trace_grid(ctx, hq.N), ctx->stream);
     HIP_CHECK_LAUNCH("trace");
   }
@@ -664,12 +691,12 @@ extern "C" void tpmc_destroy_tally(tpmc_tally t) { delete t; }
 // batched path
 // ---------------------------------------------------------------------------
 
-static tpmc_status batch_prepare(tpmc_mesh m, const tpmc_query* q, uint32_t nq, std::vector<QueryDev>& hq,
-                                 std::vector<uint64_t>& tiles, Layout& L, uint8_t* base) {
+static tpmc_status batch_prepare(tpmc_mesh m, const tpmc_query* q, uint32_t nq, uint32_t tile,
+                                 std::vector<QueryDev>& hq, std::vector<uint64_t>& tiles, Layout& L, uint8_t* base) {
   tpmc_status s = make_queries(m, q, nq, hq);
   if (s != TPMC_OK) return s;
   tiles.resize(nq);
-  for (uint32_t i = 0; i < nq; ++i) tiles[i] = (hq[i].N + kBatchTile - 1) / kBatchTile;
+  for (uint32_t i = 0; i < nq; ++i) tiles[i] = (hq[i].N + tile - 1) / tile;
   layout(hq, m->nt, 0, true, base, L);
   return TPMC_OK;
 }
@@ -680,7 +707,7 @@ extern "C" tpmc_status tpmc_batch_workspace_bytes(tpmc_ctx ctx, tpmc_mesh m, con
   std::vector<QueryDev> hq;
   std::vector<uint64_t> te;
   Layout L;
-  tpmc_status s = batch_prepare(m, q, nq, hq, te, L, nullptr);
+  tpmc_status s = batch_prepare(m, q, nq, ctx->tune.tile_particles, hq, te, L, nullptr);
   if (s != TPMC_OK) return s;
   *bytes = L.bytes;
   return TPMC_OK;
@@ -693,7 +720,8 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
   if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
   tpmc_batch b = new (std::nothrow) tpmc_batch_s;
   if (!b) return fail(TPMC_E_INVALID, "out of host memory");
-  tpmc_status s = batch_prepare(m, q, nq, b->hq, b->tiles, b->lay, static_cast<uint8_t*>(ws));
+  tpmc_status s = batch_prepare(m, q, nq, ctx->tune.tile_particles, b->hq, b->tiles, b->lay,
+                                static_cast<uint8_t*>(ws));
   if (s == TPMC_OK) s = check_ws(ws, ws_bytes, b->lay.bytes);
   if (s != TPMC_OK) {
     delete b;
@@ -716,9 +744,11 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
     return fail(TPMC_E_INVALID, "a batch must use one tally kind (TPMC_Q_NO_TRIANGLE_TALLY on all or none)");
   }
   b->mode = !any_tri ? kTallyTotals
-                     : (m->nt <= (uint64_t)kRegTallyMaxTris ? kTallyRegs
+                     : (m->nt <= (uint64_t)kLaneTallyMaxTris ? kTallyLane
                                                             : (m->nt <= (uint64_t)kLdsTallyMaxTris ? kTallyLds : kTallyGlobal));
-  b->grid = ctx->n_cu * 8;
+  b->grid = ctx->n_cu * (int)ctx->tune.groups_per_cu;
+  b->tile = ctx->tune.tile_particles;
+  b->refill = ctx->tune.refill_lanes;
   b->exec = nullptr;
   b->launched = false;
   hipError_t e = hipSetDevice(ctx->device);
@@ -750,6 +780,8 @@ static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   a.tally_base = b->lay.tally;
   a.scal_base = b->lay.scal;
   a.n_entries = b->nq;
+  a.refill = b->refill;
+  a.tile = b->tile;
   launch_batch(a, m->stack_slots, b->mode, b->grid, st);
   if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, (uint32_t)m->nt, st);
 }
@@ -809,6 +841,7 @@ struct tpmc_server_s {
   tpmc_ctx ctx;
   uint32_t max_slots;
   uint64_t tally_words;
+  uint32_t tile;         // particles per tile, fixed at creation
   QueryDev* qs;          // [max_slots]
   ResultDev* res;        // [max_slots]
   long long* scal;       // [max_slots][kScalarSlots]
@@ -869,6 +902,7 @@ extern "C" tpmc_status tpmc_server_create(tpmc_ctx ctx, uint32_t max_slots, uint
   s->ctx = ctx;
   s->max_slots = max_slots;
   s->tally_words = tally_words;
+  s->tile = ctx->tune.tile_particles;
   server_layout(max_slots, tally_words, static_cast<uint8_t*>(ws), s, &need);
   s->hq.assign(max_slots, QueryDev{});
   s->mesh_of.assign(max_slots, nullptr);
@@ -901,7 +935,7 @@ extern "C" tpmc_status tpmc_server_admit(tpmc_server s, uint32_t slot, tpmc_mesh
   zero_i64(s->scal + d.scalar_offset, kScalarSlots, stv);
   if (d.per_tri) zero_i64(s->tally + tally_offset, m->nt * 7, stv);
   HIP_CHECK_LAUNCH("admit");
-  if (n_tiles) *n_tiles = (d.N + kBatchTile - 1) / kBatchTile;
+  if (n_tiles) *n_tiles = (d.N + s->tile - 1) / s->tile;
   return TPMC_OK;
 }
 
@@ -918,7 +952,7 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t sl = slots[i];
     if (sl >= s->max_slots || !s->used[sl]) return fail(TPMC_E_INVALID, "entry %u names an empty slot %u", i, sl);
-    const uint64_t tiles = (s->hq[sl].N + kBatchTile - 1) / kBatchTile;
+    const uint64_t tiles = (s->hq[sl].N + s->tile - 1) / s->tile;
     if (tile0[i] > tiles || count[i] > tiles - tile0[i])
       return fail(TPMC_E_INVALID, "entry %u: tiles [%llu, +%llu) beyond the slot's %llu", i,
                   (unsigned long long)tile0[i], (unsigned long long)count[i], (unsigned long long)tiles);
@@ -941,7 +975,9 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   a.tally_base = s->tally;
   a.scal_base = s->scal;
   a.n_entries = n;
-  launch_batch(a, stack, kTallyAuto, s->ctx->n_cu * 8, st);
+  a.refill = s->ctx->tune.refill_lanes;
+  a.tile = s->tile;
+  launch_batch(a, stack, kTallyAuto, s->ctx->n_cu * (int)s->ctx->tune.groups_per_cu, st);
   HIP_CHECK_LAUNCH("server step");
   return TPMC_OK;
 }

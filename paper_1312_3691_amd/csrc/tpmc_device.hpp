@@ -216,7 +216,9 @@ __device__ __forceinline__ float comp(float x, float y, float z, int k) { return
 __device__ __forceinline__ void make_ray(Ray& r, float ox, float oy, float oz, float dx, float dy, float dz) {
   r.ox = ox; r.oy = oy; r.oz = oz;
   r.dx = dx; r.dy = dy; r.dz = dz;
-  r.idx = 1.0f / dx; r.idy = 1.0f / dy; r.idz = 1.0f / dz;
+  // Hardware reciprocals (1 ulp); the slab test's far-bound margin covers
+  // them, and the shear only has to be the same for every triangle of a ray.
+  r.idx = __builtin_amdgcn_rcpf(dx); r.idy = __builtin_amdgcn_rcpf(dy); r.idz = __builtin_amdgcn_rcpf(dz);
   const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
   int kz = 0;
   if (ay > ax) kz = 1;
@@ -230,16 +232,18 @@ __device__ __forceinline__ void make_ray(Ray& r, float ox, float oy, float oz, f
     ky = t;
   }
   r.kx = kx; r.ky = ky; r.kz = kz;
-  r.Sx = comp(dx, dy, dz, kx) / dkz;
-  r.Sy = comp(dx, dy, dz, ky) / dkz;
-  r.Sz = 1.0f / dkz;
+  r.Sz = __builtin_amdgcn_rcpf(dkz);
+  r.Sx = comp(dx, dy, dz, kx) * r.Sz;
+  r.Sy = comp(dx, dy, dz, ky) * r.Sz;
 }
 
 // Two-sided closest-hit candidate test.  Returns true with t and barycentrics
-// (weights of v0, v1, v2) when the triangle is hit at 0 < t <= t_max.  The
-// edge functions are evaluated without contraction so that a shared edge gives
-// exactly opposite values in its two triangles, and re-evaluated in FP64 when
-// one is exactly zero.
+// when the ray meets the triangle at 0 < t <= t_max.  Watertight test of Woop,
+// Benthin & Wald (JCGT 2013): translate to the ray origin, permute so the
+// dominant direction component is z, shear so the ray is +z, and take the
+// three 2-D edge functions; exactly-zero edge functions are recomputed in FP64
+// so that an edge shared by two triangles is never missed by both.  Apart from
+// that rare fallback the test is branch-free.
 __device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, float t_max, float& t_out,
                                               float& b0, float& b1, float& b2) {
 #pragma clang fp contract(off)
@@ -260,18 +264,18 @@ __device__ __forceinline__ bool intersect_tri(const Ray& r, const TriRec& tr, fl
     V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
     W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
   }
-  if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+  const bool mixed = (U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f);
   const float det = U + V + W;
-  if (det == 0.0f) return false;
   const float T = U * (r.Sz * Akz) + V * (r.Sz * Bkz) + W * (r.Sz * Ckz);
-  const float t = T / det;
-  if (!(t > 0.0f) || t > t_max) return false;
-  const float inv = 1.0f / det;
+  // Hardware reciprocal (1 ulp): t and the barycentrics only place the hit;
+  // which side of every edge the ray passes was settled exactly above.
+  const float inv = __builtin_amdgcn_rcpf(det);
+  const float t = T * inv;
   t_out = t;
   b0 = U * inv;
   b1 = V * inv;
   b2 = W * inv;
-  return true;
+  return !mixed && det != 0.0f && t > 0.0f && t <= t_max && t < __builtin_inff();
 }
 
 // Slab test of a child box; conservative far bound per Ize (JCGT 2013), so a
@@ -284,7 +288,9 @@ __device__ __forceinline__ bool slab(const Ray& r, float lox, float loy, float l
   const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
   const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), t_max));
   t_near = tn;
-  return tn <= tf * 1.0000004f;
+  // 1 + 5 * 2^-23 >= 1 + 8u (u = 2^-24): two roundings per t value plus the
+  // 1-ulp reciprocal, for both bounds (Ize, JCGT 2013).
+  return tn <= tf * 1.0000006f;
 }
 
 // ---------------------------------------------------------------------------

@@ -8,7 +8,7 @@ namespace tpmc {
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
 constexpr int kMaxReflections = 64;
 constexpr int kLdsTallyMaxTris = 512;  // per-workgroup LDS tallies up to this mesh size
-constexpr int kRegTallyMaxTris = 2;    // per-lane register tallies for tiny meshes
+constexpr int kLaneTallyMaxTris = 2;   // per-lane LDS tallies for tiny meshes
 constexpr int kScalarSlots = 16;       // int64 per query, see ScalarSlot
 
 // Per-query int64 block.  D is the momentum one particle gives the body along

@@ -52,78 +52,126 @@ __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict
 }
 
 // ---------------------------------------------------------------------------
-// a6: closest hit.  Nearest-child-first traversal of the binary BVH with the
-// far child on a per-lane stack in LDS (stack[slot][lane], conflict free);
-// leaves are tested as soon as their box is hit.  Returns the Morton-order
-// triangle position or -1; equal t keeps the lower original index.
+// Loads through the global address space.  The mesh pointers reach the
+// kernels inside the query record, so the compiler cannot prove that they
+// address global memory and would emit flat loads, which also count against
+// the LDS counter and so delay every LDS access behind them.
 // ---------------------------------------------------------------------------
-template <int STACK, bool COUNT>
-__device__ __forceinline__ int closest_hit(const Node* __restrict__ nodes, const TriRec* __restrict__ tris,
-                                           const uint32_t* __restrict__ orig, const Ray& r, int prev,
-                                           int (*stk)[kBlock], float& t_best, float& b0, float& b1, float& b2,
-                                           uint32_t& n_nodes, uint32_t& n_tests) {
-  const int lane = threadIdx.x;
-  int best = -1;
-  t_best = __builtin_inff();
-  int sp = 0;
-  int node = 0;
-  // Each node is entered at most once per ray; the bound only guarantees that a
-  // damaged tree cannot keep a wave spinning.
-  for (uint32_t guard = 0; guard < (1u << 24); ++guard) {
-    const float4* np = reinterpret_cast<const float4*>(nodes + node);
-    const float4 A = np[0], B = np[1], C = np[2];
-    const int4 L = reinterpret_cast<const int4*>(nodes + node)[3];
-    if (COUNT) ++n_nodes;
-    float tn0, tn1;
-    bool h0 = slab(r, A.x, A.y, A.z, A.w, B.x, B.y, t_best, tn0);
-    bool h1 = slab(r, B.z, B.w, C.x, C.y, C.z, C.w, t_best, tn1);
-    if (h0 && L.x < 0) {
-      const int k = ~L.x;
-      float t, u0, u1, u2;
-      if (COUNT && k != prev) ++n_tests;
-      if (k != prev && intersect_tri(r, tris[k], t_best, t, u0, u1, u2) &&
-          (t < t_best || (best >= 0 && orig[k] < orig[best]))) {
-        best = k; t_best = t; b0 = u0; b1 = u1; b2 = u2;
-      }
-      h0 = false;
-    }
-    if (h1 && L.y < 0) {
-      const int k = ~L.y;
-      float t, u0, u1, u2;
-      if (COUNT && k != prev) ++n_tests;
-      if (k != prev && intersect_tri(r, tris[k], t_best, t, u0, u1, u2) &&
-          (t < t_best || (best >= 0 && orig[k] < orig[best]))) {
-        best = k; t_best = t; b0 = u0; b1 = u1; b2 = u2;
-      }
-      h1 = false;
-    }
-    if (h0 && h1 && sp < STACK) {
-      const bool first0 = tn0 <= tn1;
-      stk[sp][lane] = first0 ? L.y : L.x;
-      ++sp;
-      node = first0 ? L.x : L.y;
-    } else if (h0) {
-      node = L.x;
-    } else if (h1) {
-      node = L.y;
-    } else {
-      if (sp == 0) break;
-      --sp;
-      node = stk[sp][lane];
-    }
-  }
-  return best;
+template <class T>
+using gptr = const T __attribute__((address_space(1)))*;
+typedef float vf4 __attribute__((ext_vector_type(4)));  // native vectors: HIP's float4 cannot
+typedef int vi4 __attribute__((ext_vector_type(4)));    // be copied from an address-space reference
+
+__device__ __forceinline__ TriRec load_tri(const TriRec* p, int k) {
+  const gptr<vf4> g = (gptr<vf4>)(p + k);
+  const vf4 a = g[0], b = g[1], c = g[2];
+  return TriRec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
+}
+
+__device__ __forceinline__ uint32_t load_orig(const uint32_t* p, int k) { return ((gptr<uint32_t>)p)[k]; }
+
+// A pointer every lane holds the same value of, moved to scalar registers.
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return reinterpret_cast<T*>(lo | (hi << 32));
 }
 
 // One lane's particle in flight.
 struct Lane {
-  float ox, oy, oz, wx, wy, wz;
+  float ox = 0.0f, oy = 0.0f, oz = 0.0f, wx = 0.0f, wy = 0.0f, wz = 0.0f;
   float D;        // momentum given along U so far (this particle)
   int prev;       // Morton position of the triangle just left
   uint32_t hits;
   uint64_t pid;   // particle index within its query
   bool live;
 };
+
+// ---------------------------------------------------------------------------
+// a6: closest hit, one BVH node per step.  Nearest-child-first traversal of
+// the binary BVH with the far child on a per-lane stack in LDS
+// (stack[slot][lane], conflict free); leaves are tested as soon as their box
+// is hit.  The traversal state lives in registers between steps, so a lane
+// whose segment has ended can be given its next segment while the other
+// lanes of the wave are still traversing.  The closest hit does not depend
+// on the visiting order: every triangle whose t is at most the final t_best
+// lies in boxes that are never culled (conservative far bound), and equal t
+// keeps the lower original index.  The ray's derived constants (Ray) are
+// recomputed from the lane's origin and direction after every service pass,
+// so they are not held in registers across the seeding code.
+// ---------------------------------------------------------------------------
+constexpr int kDone = -0x7FFFFFFF - 1;  // Seg::cur once the traversal has ended
+
+struct Seg {
+  int cur;   // next node to visit, or kDone
+  int sp;    // stack depth
+  int best;  // closest triangle so far (Morton position), -1 if none
+  float t_best, b0, b1, b2;
+};
+
+__device__ __forceinline__ void seg_begin(Seg& s) {
+  s.cur = 0;
+  s.sp = 0;
+  s.best = -1;
+  s.t_best = __builtin_inff();
+}
+
+// Candidate leaf k: two-sided test, the triangle just left excluded.
+template <bool COUNT>
+__device__ __forceinline__ void test_leaf(const TriRec* tris, const uint32_t* orig, const Ray& r, int k, int prev,
+                                          Seg& s, uint32_t& n_tests) {
+  if (COUNT && k != prev) ++n_tests;
+  float t, u0, u1, u2;
+  if (intersect_tri(r, load_tri(tris, k), s.t_best, t, u0, u1, u2) && k != prev) {
+    // t <= t_best here; an exact tie keeps the lower original index
+    const bool take = t < s.t_best || (s.best >= 0 && load_orig(orig, k) < load_orig(orig, s.best));
+    if (take) {
+      s.best = k;
+      s.t_best = t;
+      s.b0 = u0;
+      s.b1 = u1;
+      s.b2 = u2;
+    }
+  }
+}
+
+// One traversal step of a lane with s.cur != kDone.  Each node is entered at
+// most once per ray, so a segment takes at most nt - 1 steps.
+template <int STACK, bool COUNT>
+__device__ __forceinline__ void trav_step(const Node* nodes, const TriRec* tris, const uint32_t* orig, const Ray& r,
+                                          int prev, Seg& s, int (*stk)[kBlock], uint32_t& n_nodes,
+                                          uint32_t& n_tests) {
+  const int lane = threadIdx.x;
+  const gptr<vf4> np = (gptr<vf4>)(nodes + s.cur);
+  const vf4 A = np[0], B = np[1], C = np[2];
+  const vi4 L = ((gptr<vi4>)(nodes + s.cur))[3];
+  if (COUNT) ++n_nodes;
+  float tn0, tn1;
+  bool h0 = slab(r, A.x, A.y, A.z, A.w, B.x, B.y, s.t_best, tn0);
+  bool h1 = slab(r, B.z, B.w, C.x, C.y, C.z, C.w, s.t_best, tn1);
+  if (h0 && L.x < 0) {
+    test_leaf<COUNT>(tris, orig, r, ~L.x, prev, s, n_tests);
+    h0 = false;
+  }
+  if (h1 && L.y < 0) {
+    test_leaf<COUNT>(tris, orig, r, ~L.y, prev, s, n_tests);
+    h1 = false;
+  }
+  if (h0 && h1 && s.sp < STACK) {
+    const bool first0 = tn0 <= tn1;
+    stk[s.sp][lane] = first0 ? L.y : L.x;
+    ++s.sp;
+    s.cur = first0 ? L.x : L.y;
+  } else if (h0) {
+    s.cur = L.x;
+  } else if (h1) {
+    s.cur = L.y;
+  } else {
+    s.cur = s.sp == 0 ? kDone : stk[--s.sp][lane];
+  }
+}
 
 // Momentum and moment of one hit, ready for the tallies.
 struct Hit {
@@ -135,7 +183,6 @@ struct Hit {
 // Per-lane exact integer accumulators.
 struct Acc {
   long long sD, sD2, tot[7];
-  long long tri2[2 * 7];  // per-triangle sums of a mesh of at most two triangles
   uint32_t rays, hits, segs, missed, escaped, capped;
   uint32_t nodes, tests;  // traversal work (counting kernels only)
 };
@@ -144,38 +191,32 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
   A.sD = A.sD2 = 0;
 #pragma unroll
   for (int c = 0; c < 7; ++c) A.tot[c] = 0;
-#pragma unroll
-  for (int c = 0; c < 14; ++c) A.tri2[c] = 0;
   A.rays = A.hits = A.segs = A.missed = A.escaped = A.capped = 0;
   A.nodes = A.tests = 0;
 }
 
-// a6-a9 for one lane: one ray segment, then re-emission and the per-particle
-// bookkeeping.  Returns true when the particle retires.
-template <int STACK, bool COUNT>
-__device__ __forceinline__ bool segment(const Node* __restrict__ nodes, const TriRec* __restrict__ tris,
-                                        const uint32_t* __restrict__ orig, const QueryDev& q, Lane& L, Acc& A,
-                                        Hit& h, int (*stk)[kBlock], int32_t& first_id) {
-  Ray r;
-  make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
-  float t, b0 = 0.f, b1 = 0.f, b2 = 0.f;
-  const int k = closest_hit<STACK, COUNT>(nodes, tris, orig, r, L.prev, stk, t, b0, b1, b2, A.nodes, A.tests);
-  ++A.segs;
+// Outcome of a finished segment.
+// (names distinct from the scalar-slot indices kMissed, kEscaped, kCapped)
+enum Outcome : int { kOutGoOn = 0, kOutMissed = 1, kOutEscaped = 2, kOutCapped = 3 };
+
+// a7-a9 for a lane whose traversal has ended: re-emission and bookkeeping of
+// the hit, or the particle's exit.  The particle retires unless kOutGoOn.
+__device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t* orig, const QueryDev& q, Lane& L,
+                                              const Seg& s, Hit& h, int32_t& first_id) {
+  const int k = s.best;
   first_id = -2;  // not the first segment's outcome
   if (k < 0) {
     if (L.hits == 0) {
-      ++A.missed;
       first_id = -1;
-    } else {
-      ++A.escaped;
+      return kOutMissed;
     }
-    return true;
+    return kOutEscaped;
   }
-  const TriRec tr = tris[k];
-  const uint32_t id = orig[k];
-  const float px = b0 * tr.v0x + b1 * tr.v1x + b2 * tr.v2x;
-  const float py = b0 * tr.v0y + b1 * tr.v1y + b2 * tr.v2y;
-  const float pz = b0 * tr.v0z + b1 * tr.v1z + b2 * tr.v2z;
+  const TriRec tr = load_tri(tris, k);
+  const uint32_t id = load_orig(orig, k);
+  const float px = s.b0 * tr.v0x + s.b1 * tr.v1x + s.b2 * tr.v2x;
+  const float py = s.b0 * tr.v0y + s.b1 * tr.v1y + s.b2 * tr.v2y;
+  const float pz = s.b0 * tr.v0z + s.b1 * tr.v1z + s.b2 * tr.v2z;
   float nwx = L.wx, nwy = L.wy, nwz = L.wz;
   reemit(q, L.pid, L.hits, tr.nx, tr.ny, tr.nz, nwx, nwy, nwz);
   const float dx = L.wx - nwx, dy = L.wy - nwy, dz = L.wz - nwz;
@@ -189,7 +230,6 @@ __device__ __forceinline__ bool segment(const Node* __restrict__ nodes, const Tr
   L.D += dx * q.Uf[0] + dy * q.Uf[1] + dz * q.Uf[2];
   if (L.hits == 0) first_id = (int32_t)id;
   ++L.hits;
-  ++A.hits;
   // The next ray starts at the hit point moved to the side the particle leaves
   // from by 8 FP32 ulps of the triangle's coordinate scale: the rounded
   // barycentric point can lie a few ulps behind the surface, and a ray started
@@ -202,28 +242,40 @@ __device__ __forceinline__ bool segment(const Node* __restrict__ nodes, const Tr
   L.ox = px + eps * tr.nx; L.oy = py + eps * tr.ny; L.oz = pz + eps * tr.nz;
   L.wx = nwx; L.wy = nwy; L.wz = nwz;
   L.prev = k;
-  if (L.hits >= q.rmax) {
-    ++A.capped;
-    return true;
-  }
-  return false;
+  return L.hits >= q.rmax ? kOutCapped : kOutGoOn;
+}
+
+// Event counts of a lane whose segment ended with outcome `out`.
+__device__ __forceinline__ void count_outcome(Acc& A, int out, bool hit) {
+  ++A.segs;
+  A.hits += hit ? 1u : 0u;
+  A.missed += out == kOutMissed ? 1u : 0u;
+  A.escaped += out == kOutEscaped ? 1u : 0u;
+  A.capped += out == kOutCapped ? 1u : 0u;
+  A.rays += out != kOutGoOn ? 1u : 0u;
 }
 
 __device__ __forceinline__ void retire(const QueryDev& q, const Lane& L, Acc& A) {
   A.sD += fx(L.D, q.scaleD);
   A.sD2 += fx(L.D * L.D, q.scaleD2);
-  ++A.rays;
 }
 
 // Tally of one hit per lane.  Called by every lane of the wave (convergent).
-template <int MODE>
+// Totals-only sums go to the lane's LDS slots when TOT_LDS (the persistent
+// kernel, short of registers), else to registers.
+template <int MODE, bool TOT_LDS = true>
 __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long* __restrict__ g,
                                       unsigned long long* lds, uint32_t nt, Acc& A) {
   long long v[7];
   v[0] = fx(h.dx, q.scaleF); v[1] = fx(h.dy, q.scaleF); v[2] = fx(h.dz, q.scaleF);
   v[3] = fx(h.lx, q.scaleL); v[4] = fx(h.ly, q.scaleL); v[5] = fx(h.lz, q.scaleL);
   v[6] = 1;
-  if (MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) {
+  if (MODE == kTallyTotals && TOT_LDS) {  // the lane's own LDS slots [c][lane]
+    if (h.valid) {
+#pragma unroll
+      for (int c = 0; c < 7; ++c) atomicAdd(lds + c * kBlock + threadIdx.x, (unsigned long long)v[c]);
+    }
+  } else if (MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) {
     if (h.valid) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) A.tot[c] += v[c];
@@ -238,28 +290,37 @@ __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long
 #pragma unroll
       for (int c = 0; c < 7; ++c) atomicAdd(lds + 7u * h.id + c, (unsigned long long)v[c]);
     }
-  } else {  // kTallyRegs: per-lane registers, flushed once (meshes of <= 2 triangles)
+  } else {  // kTallyLane: the lane's own LDS slots [7 * id + c][lane] (meshes of <= 2 triangles)
     if (h.valid) {
 #pragma unroll
-      for (int c = 0; c < 7; ++c) {
-        A.tri2[c] += h.id == 0 ? v[c] : 0ll;
-        A.tri2[7 + c] += h.id == 1 ? v[c] : 0ll;
-      }
+      for (int c = 0; c < 7; ++c) atomicAdd(lds + (7u * h.id + c) * kBlock + threadIdx.x, (unsigned long long)v[c]);
     }
   }
 }
 
-// Flush of the register tallies of a <= 2-triangle mesh (convergent).
-__device__ __forceinline__ void flush_tri2(const Acc& A, long long* __restrict__ g, uint32_t nt) {
+// Flush (and clear) the calling lane's per-lane tallies of a <= 2-triangle
+// mesh: one wave sum per slot, one atomic per wave (convergent).
+__device__ __forceinline__ void flush_lane_tally(unsigned long long* lds, long long* __restrict__ g, uint32_t nt) {
 #pragma unroll
-  for (int c = 0; c < 14; ++c) {
-    const long long s = wave_sum(A.tri2[c]);
+  for (int c = 0; c < 2 * 7; ++c) {
+    const long long s = wave_sum((long long)lds[c * kBlock + threadIdx.x]);
+    lds[c * kBlock + threadIdx.x] = 0ull;
     if ((threadIdx.x & 63) == 0 && s != 0 && c < (int)nt * 7) atomic_add_i64(g + c, s);
   }
 }
 
-// Wave-reduce the per-lane accumulators into a query's scalar block.
-__device__ __forceinline__ void flush_acc(const Acc& A, long long* __restrict__ scal, bool TOTALS) {
+// Wave-reduce the per-lane accumulators into a query's scalar block.  With
+// TOTALS the query's force and moment totals come from the lane's registers,
+// or, when lane_tot is given, from (and clearing) its LDS slots [c][lane].
+__device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, bool TOTALS,
+                                          unsigned long long* lane_tot = nullptr) {
+  if (TOTALS && lane_tot) {
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      A.tot[c] = (long long)lane_tot[c * kBlock + threadIdx.x];
+      lane_tot[c * kBlock + threadIdx.x] = 0ull;
+    }
+  }
   long long s[8 + 7];
   s[0] = wave_sum(A.sD);
   s[1] = wave_sum(A.sD2);
@@ -286,26 +347,32 @@ __device__ __forceinline__ void flush_acc(const Acc& A, long long* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// a6-a9, plain path: one query per launch, particles read from the SoA.  The
-// loop is wave-uniform; a lane whose particle retires loads the next one
-// (grid stride) at once, so lanes stay busy while particles have different
-// numbers of bounces.
+// a6-a9, plain path: one query per launch, particles read from the SoA.  Each
+// loop iteration advances every traversing lane by one BVH step.  Lanes whose
+// segment has ended wait until fewer than a.refill lanes are still
+// traversing; then all of them are served at once (re-emission, tallies, the
+// next segment, or the next particle by grid stride), so the costly per-hit
+// work runs with many lanes active and no lane idles for the rest of a
+// segment's traversal.
 // ---------------------------------------------------------------------------
 template <int STACK, int MODE, bool COUNT>
 __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
   __shared__ int stk[STACK][kBlock];
-  __shared__ unsigned long long lt[MODE == kTallyLds ? kLdsTallyMaxTris * 7 : 1];
+  __shared__ unsigned long long lt[MODE == kTallyLds ? kLdsTallyMaxTris * 7 : (MODE == kTallyLane ? 2 * 7 * kBlock : 1)];
   const QueryDev& q = *a.q;
   if (MODE == kTallyLds) {
     for (uint32_t i = threadIdx.x; i < a.nt * 7u; i += kBlock) lt[i] = 0ull;
     __syncthreads();
   }
+  if (MODE == kTallyLane)
+    for (int c = 0; c < 2 * 7; ++c) lt[c * kBlock + threadIdx.x] = 0ull;
   Acc A;
   acc_zero(A);
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint32_t max_steps = a.nt + 64u;
   Lane L;
-  L.pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  L.live = L.pid < a.n;
+  Seg s;
+  Ray r;
   auto load = [&](Lane& l) {
     l.ox = a.x[0][l.pid]; l.oy = a.x[1][l.pid]; l.oz = a.x[2][l.pid];
     l.wx = a.w[0][l.pid]; l.wy = a.w[1][l.pid]; l.wz = a.w[2][l.pid];
@@ -313,26 +380,49 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
     l.prev = -1;
     l.hits = 0;
   };
-  if (L.live) load(L);
+  L.pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  L.live = L.pid < a.n;
+  s.cur = kDone;
+  if (L.live) {
+    load(L);
+    seg_begin(s);
+  }
+  make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
+  uint32_t guard = 0;  // steps since the last service pass (wave-uniform)
   while (__ballot(L.live) != 0ull) {
-    Hit h;
-    h.valid = false;
-    bool done = false;
-    int32_t fid = -2;
-    if (L.live) done = segment<STACK, COUNT>(a.nodes, a.tris, a.orig, q, L, A, h, stk, fid);
-    tally<MODE>(q, h, a.tally, lt, a.nt, A);
-    if (L.live) {
-      if (a.first_tri && fid != -2) a.first_tri[L.pid] = fid;
-      if (done) {
-        retire(q, L, A);
-        L.pid += stride;
-        L.live = L.pid < a.n;
-        if (L.live) load(L);
+    if ((uint32_t)__popcll(__ballot(L.live && s.cur != kDone)) < a.refill) {
+      const bool fin = L.live && s.cur == kDone;
+      if (__ballot(fin) != 0ull) {
+        Hit h;
+        h.valid = false;
+        int out = kOutGoOn;
+        int32_t fid = -2;
+        if (fin) {
+          out = finish_segment(a.tris, a.orig, q, L, s, h, fid);
+          count_outcome(A, out, h.valid);
+        }
+        tally<MODE, false>(q, h, a.tally, lt, a.nt, A);
+        if (fin) {
+          if (a.first_tri && fid != -2) a.first_tri[L.pid] = fid;
+          if (out != kOutGoOn) {
+            retire(q, L, A);
+            L.pid += stride;
+            L.live = L.pid < a.n;
+            if (L.live) load(L);
+          }
+          if (L.live) seg_begin(s);
+        }
       }
+      make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
+      guard = 0;
     }
+    // Between service passes every traversing lane ends its segment within nt
+    // steps; the bound only keeps a damaged tree from spinning a wave.
+    if (++guard > max_steps) s.cur = kDone;
+    if (L.live && s.cur != kDone) trav_step<STACK, COUNT>(a.nodes, a.tris, a.orig, r, L.prev, s, stk, A.nodes, A.tests);
   }
   flush_acc(A, a.scal, MODE == kTallyTotals);
-  if (MODE == kTallyRegs) flush_tri2(A, a.tally, a.nt);
+  if (MODE == kTallyLane) flush_lane_tally(lt, a.tally, a.nt);
   if (COUNT) {
     const long long nn = wave_sum((long long)A.nodes), nt2 = wave_sum((long long)A.tests);
     if ((threadIdx.x & 63) == 0) {
@@ -353,13 +443,16 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
 // is exhausted, then moves to the next entry with work left; its four waves
 // share each tile, claiming 64 particles at a time from a workgroup counter in
 // LDS.  A wave seeds its 64 particles with every lane active (the FP64 seeding
-// is the costliest per-particle step) into a wave-private LDS queue, and lanes
-// whose particle retires refill from that queue; particle states never leave
-// the chip.  Partial sums -- per-lane scalars, per-lane register tallies of
-// tiny meshes, the workgroup's LDS tally of meshes up to kLdsTallyMaxTris
-// triangles -- stay on chip while the workgroup stays on one query and are
-// flushed to HBM with atomics only when it changes query or finishes.
-// Per-particle arithmetic is the plain path's, so results match it bit for bit.
+// is the costliest per-particle step) into a wave-private LDS queue; the
+// traversal advances one BVH step per iteration as in the plain path, and when
+// fewer than a.refill lanes are still traversing, the lanes whose segment has
+// ended are served together and lanes whose particle retired take the next
+// queued particle.  Particle states never leave the chip.  Partial sums --
+// per-lane scalars, per-lane LDS tallies of tiny meshes, the workgroup's
+// LDS tally of meshes up to kLdsTallyMaxTris triangles -- stay on chip while
+// the workgroup stays on one query and are flushed to HBM with atomics only
+// when it changes query or finishes.  Per-particle arithmetic is the plain
+// path's, so results match it bit for bit.
 // ---------------------------------------------------------------------------
 
 template <int STACK, int MODE>
@@ -368,7 +461,10 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
-  __shared__ unsigned long long lt[kMayLds ? kLdsTallyMaxTris * 7 : 1];
+  __shared__ unsigned long long lt[kMayLds                ? kLdsTallyMaxTris * 7
+                                   : MODE == kTallyLane   ? 2 * 7 * kBlock
+                                   : MODE == kTallyTotals ? 7 * kBlock
+                                                          : 1];
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -377,6 +473,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
   Acc A;
   acc_zero(A);
+  if (MODE == kTallyLane || MODE == kTallyTotals)
+    for (int c = 0; c < (MODE == kTallyLane ? 2 * 7 : 7); ++c) lt[c * kBlock + threadIdx.x] = 0ull;
   for (;;) {
     if (threadIdx.x == 0) {
       // claim a tile: current entry first, then the following ones (bounded scan)
@@ -397,14 +495,16 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       tile_sh = t;
     }
     __syncthreads();
-    const uint32_t j = entry_sh;  // uniform over the workgroup
-    const uint64_t tile = tile_sh;
+    const uint32_t j = __builtin_amdgcn_readfirstlane(entry_sh);  // uniform over the workgroup
+    const uint64_t tile = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tile_sh) |
+                          ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(tile_sh >> 32)) << 32);
     if (j != held && held != kNone) {
       // leaving the held query: flush its partial sums
       const QueryDev& qh = a.qs[a.entry_query ? a.entry_query[held] : held];
       long long* htally = qh.per_tri ? a.tally_base + qh.tally_offset : nullptr;
-      flush_acc(A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri));
-      if (MODE == kTallyRegs) flush_tri2(A, htally, qh.nt);
+      flush_acc(A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri),
+                MODE == kTallyTotals ? lt : nullptr);
+      if (MODE == kTallyLane) flush_lane_tally(lt, htally, qh.nt);
       acc_zero(A);
       if (kMayLds && qh.per_tri && qh.nt <= (uint32_t)kLdsTallyMaxTris)
         for (uint32_t i = threadIdx.x; i < qh.nt * 7u; i += kBlock)
@@ -420,79 +520,111 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       held = j;
     }
     const uint64_t tile_in_q = (a.entry_tile0 ? a.entry_tile0[j] : 0ull) + tile;
-    const uint64_t p_begin = tile_in_q * kBatchTile;
-    const uint64_t p_end = p_begin + kBatchTile < q.N ? p_begin + kBatchTile : q.N;
+    const uint64_t p_begin = tile_in_q * a.tile;
+    const uint64_t p_end = p_begin + a.tile < q.N ? p_begin + a.tile : q.N;
     long long* qtally = q.per_tri ? a.tally_base + q.tally_offset : nullptr;
+    const Node* nodes = uniform_ptr(q.nodes);
+    const TriRec* tris = uniform_ptr(q.tris);
+    const uint32_t* orig = uniform_ptr(q.orig);
     if (threadIdx.x == 0) next_sh = p_begin;
     __syncthreads();
 
     Lane L;
+    Seg s;
+    Ray r;
     L.live = false;
+    s.cur = kDone;
+    const uint32_t max_steps = q.nt + 64u;
+    uint32_t guard = 0;                // steps since the last service pass (wave-uniform)
     bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
     uint64_t q_pid0 = 0;               // particle id of queue slot 0
     for (;;) {
-      const uint64_t dead = __ballot(!L.live);
-      const uint32_t ndead = __popcll(dead);
-      if (q_count == 0 && !exhausted && ndead >= 16) {
-        // claim and seed the next (up to) 64 particles, one per lane
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&next_sh, 64ull);
-        base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
-               ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
-        if (base >= p_end) {
-          exhausted = true;
-        } else {
-          const uint64_t pid = base + lane;
-          if (pid < p_end) {
-            double x[3], w[3];
-            seed_particle(q, pid, x, w);
-            qbuf[wave][0][lane] = (float)x[0];
-            qbuf[wave][1][lane] = (float)x[1];
-            qbuf[wave][2][lane] = (float)x[2];
-            qbuf[wave][3][lane] = (float)w[0];
-            qbuf[wave][4][lane] = (float)w[1];
-            qbuf[wave][5][lane] = (float)w[2];
+      if ((uint32_t)__popcll(__ballot(L.live && s.cur != kDone)) < a.refill) {
+        // serve every lane whose segment has ended
+        const bool fin = L.live && s.cur == kDone;
+        if (__ballot(fin) != 0ull) {
+          Hit h;
+          h.valid = false;
+          int out = kOutGoOn;
+          int32_t fid;
+          if (fin) {
+            out = finish_segment(tris, orig, q, L, s, h, fid);
+            count_outcome(A, out, h.valid);
           }
-          const uint64_t left = p_end - base;
-          q_count = left < 64 ? (uint32_t)left : 64u;
-          q_head = 0;
-          q_pid0 = base;
-          __builtin_amdgcn_wave_barrier();
+          if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
+          else tally<MODE>(q, h, qtally, lt, q.nt, A);
+          if (fin) {
+            if (out != kOutGoOn) {
+              retire(q, L, A);
+              L.live = false;
+            } else {
+              seg_begin(s);
+            }
+          }
         }
-      }
-      if (q_count > 0 && dead != 0ull) {
-        // dead lanes take queue entries in lane order
-        const uint32_t rank = __popcll(dead & lt_mask);
-        if (!L.live && rank < q_count) {
-          const uint32_t slot = q_head + rank;
-          L.ox = qbuf[wave][0][slot]; L.oy = qbuf[wave][1][slot]; L.oz = qbuf[wave][2][slot];
-          L.wx = qbuf[wave][3][slot]; L.wy = qbuf[wave][4][slot]; L.wz = qbuf[wave][5][slot];
-          L.pid = q_pid0 + slot;
-          L.D = 0.0f;
-          L.prev = -1;
-          L.hits = 0;
-          L.live = true;
+        const uint64_t dead = __ballot(!L.live);
+        if (dead != 0ull) {
+          if (q_count == 0 && !exhausted) {
+            // claim and seed the next (up to) 64 particles, one per lane
+            unsigned long long base = 0;
+            if (lane == 0) base = atomicAdd(&next_sh, 64ull);
+            base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
+                   ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
+            if (base >= p_end) {
+              exhausted = true;
+            } else {
+              const uint64_t pid = base + lane;
+              if (pid < p_end) {
+                double x[3], w[3];
+                seed_particle(q, pid, x, w);
+                qbuf[wave][0][lane] = (float)x[0];
+                qbuf[wave][1][lane] = (float)x[1];
+                qbuf[wave][2][lane] = (float)x[2];
+                qbuf[wave][3][lane] = (float)w[0];
+                qbuf[wave][4][lane] = (float)w[1];
+                qbuf[wave][5][lane] = (float)w[2];
+              }
+              const uint64_t left = p_end - base;
+              q_count = left < 64 ? (uint32_t)left : 64u;
+              q_head = 0;
+              q_pid0 = base;
+              __builtin_amdgcn_wave_barrier();
+            }
+          }
+          if (q_count > 0) {
+            // dead lanes take queue entries in lane order
+            const uint32_t rank = __popcll(dead & lt_mask);
+            if (!L.live && rank < q_count) {
+              const uint32_t slot = q_head + rank;
+              L.ox = qbuf[wave][0][slot]; L.oy = qbuf[wave][1][slot]; L.oz = qbuf[wave][2][slot];
+              L.wx = qbuf[wave][3][slot]; L.wy = qbuf[wave][4][slot]; L.wz = qbuf[wave][5][slot];
+              L.pid = q_pid0 + slot;
+              L.D = 0.0f;
+              L.prev = -1;
+              L.hits = 0;
+              L.live = true;
+              seg_begin(s);
+            }
+            const uint32_t ndead = __popcll(dead);
+            const uint32_t took = ndead < q_count ? ndead : q_count;
+            q_head += took;
+            q_count -= took;
+            __builtin_amdgcn_wave_barrier();
+          }
         }
-        const uint32_t took = ndead < q_count ? ndead : q_count;
-        q_head += took;
-        q_count -= took;
-        __builtin_amdgcn_wave_barrier();
+        if (__ballot(L.live) == 0ull) {
+          if (exhausted && q_count == 0) break;
+          continue;  // nothing in flight: claim more next round
+        }
+        make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
+        guard = 0;
       }
-      if (__ballot(L.live) == 0ull) {
-        if (exhausted && q_count == 0) break;
-        continue;  // nothing in flight: claim more next round
-      }
-      Hit h;
-      h.valid = false;
-      bool done = false;
-      int32_t fid;
-      if (L.live) done = segment<STACK, false>(q.nodes, q.tris, q.orig, q, L, A, h, stk, fid);
-      if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
-      else tally<MODE>(q, h, qtally, nullptr, q.nt, A);
-      if (L.live && done) {
-        retire(q, L, A);
-        L.live = false;
+      // as in the plain path: a bound only against a damaged tree
+      if (++guard > max_steps) s.cur = kDone;
+      if (L.live && s.cur != kDone) {
+        uint32_t n0 = 0, n1 = 0;
+        trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
       }
     }
     __syncthreads();  // every wave is done with the tile; tile_sh / entry_sh / next_sh may be reused
@@ -584,7 +716,7 @@ void launch_trace_mode(const TraceArgs& a, TallyMode mode, int grid, hipStream_t
   switch (mode) {
     case kTallyGlobal: trace_kernel<STACK, kTallyGlobal, COUNT><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyLds: trace_kernel<STACK, kTallyLds, COUNT><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyRegs: trace_kernel<STACK, kTallyRegs, COUNT><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyLane: trace_kernel<STACK, kTallyLane, COUNT><<<grid, kBlock, 0, st>>>(a); break;
     default: trace_kernel<STACK, kTallyTotals, COUNT><<<grid, kBlock, 0, st>>>(a); break;
   }
 }
@@ -598,7 +730,7 @@ void launch_trace_stack(const TraceArgs& a, TallyMode mode, int grid, hipStream_
 template <int STACK>
 void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t st) {
   switch (mode) {
-    case kTallyRegs: batch_kernel<STACK, kTallyRegs><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyLane: batch_kernel<STACK, kTallyLane><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyLds: batch_kernel<STACK, kTallyLds><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyTotals: batch_kernel<STACK, kTallyTotals><<<grid, kBlock, 0, st>>>(a); break;
     case kTallyAuto: batch_kernel<STACK, kTallyAuto><<<grid, kBlock, 0, st>>>(a); break;

@@ -12,7 +12,7 @@ namespace tpmc {
 // Tally strategy of the trace kernels.
 // Auto: per query, global per-triangle atomics or register totals (serving steps
 // that mix both kinds of request).
-enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyRegs = 2, kTallyTotals = 3, kTallyAuto = 4 };
+enum TallyMode { kTallyGlobal = 0, kTallyLds = 1, kTallyLane = 2, kTallyTotals = 3, kTallyAuto = 4 };
 
 struct TraceArgs {
   const Node* nodes;
@@ -27,6 +27,7 @@ struct TraceArgs {
   int32_t* first_tri;         // optional, already offset to the query
   unsigned long long* counters;  // optional [2]: BVH nodes visited, triangle tests
   uint32_t nt;
+  uint32_t refill;            // serve ended segments when fewer lanes of a wave traverse (1..64)
 };
 
 // One persistent launch covers n_entries entries; entry j is entry_tiles[j]
@@ -44,9 +45,9 @@ struct BatchArgs {
   long long* tally_base;           // per-triangle tallies, indexed by QueryDev::tally_offset
   long long* scal_base;            // scalar blocks, indexed by QueryDev::scalar_offset
   uint32_t n_entries;
+  uint32_t refill;                 // as TraceArgs::refill
+  uint64_t tile;                   // particles per tile (multiple of 64)
 };
-
-constexpr uint64_t kBatchTile = 16384;  // particles per work item (one workgroup) of the persistent kernel
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
 void zero_u32(uint32_t* p, uint64_t n, hipStream_t st);

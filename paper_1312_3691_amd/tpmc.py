@@ -61,10 +61,16 @@ _fp = ctypes.POINTER(ctypes.c_float)
 _QP = ctypes.POINTER(Query)
 _RP = ctypes.POINTER(Result)
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("refill_lanes", _u32), ("tile_particles", _u32), ("groups_per_cu", _u32), ("reserved", _u32)]
+
+
 _SIGS = {
     "tpmc_last_error": ([], ctypes.c_char_p),
     "tpmc_abi_version": ([], ctypes.c_int),
     "tpmc_create": ([ctypes.c_int, _vp, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_get_tuning": ([_vp, ctypes.POINTER(Tuning)], ctypes.c_int),
+    "tpmc_set_tuning": ([_vp, ctypes.POINTER(Tuning)], ctypes.c_int),
     "tpmc_set_stream": ([_vp, _vp], ctypes.c_int),
     "tpmc_destroy_ctx": ([_vp], None),
     "tpmc_build_mesh": ([_vp, _fp, _u64, ctypes.POINTER(_u32), _u64, ctypes.POINTER(_vp)], ctypes.c_int),
@@ -197,6 +203,23 @@ class Context:
 
     def build_mesh(self, V, T) -> "Mesh":
         return Mesh(self, V, T)
+
+    @property
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(_lib.tpmc_get_tuning(self._h, ctypes.byref(t)))
+        return {"refill_lanes": t.refill_lanes, "tile_particles": t.tile_particles,
+                "groups_per_cu": t.groups_per_cu}
+
+    def set_tuning(self, **kw) -> None:
+        """Replace some fields of the launch tuning (tpmc_set_tuning); results do not change."""
+        cur = self.tuning
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update(kw)
+        t = Tuning(int(cur["refill_lanes"]), int(cur["tile_particles"]), int(cur["groups_per_cu"]), 0)
+        _check(_lib.tpmc_set_tuning(self._h, ctypes.byref(t)))
 
 
 class Mesh:
