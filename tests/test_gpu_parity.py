@@ -224,6 +224,42 @@ def test_batch_equals_plain_bitwise(ctx, T, flags):
     pr.close()
 
 
+def test_tuning_does_not_change_results(ctx, T):
+    """Every launch tuning (refill threshold, tile size, workgroups per CU) gives
+    bit-identical plain and batched results, on a deep and a 2-triangle mesh."""
+    import ctypes
+    base = ctx.tuning
+    try:
+        for V, Tr in (I.satellite(3000), I.plate()):
+            mesh = ctx.build_mesh(V, Tr)
+            qs = _batch_queries(4)
+            ref = None
+            for t in ({"refill_lanes": 1, "tile_particles": 64, "groups_per_cu": 1},
+                      {"refill_lanes": 64, "tile_particles": 4096, "groups_per_cu": 32},
+                      {"refill_lanes": 33, "tile_particles": 1 << 22, "groups_per_cu": 3}):
+                ctx.set_tuning(**t)
+                plain, pr = T.run(mesh, qs, A_ref=1.0)
+                b = T.Batch(mesh, qs)
+                batched = b.launch(use_graph=True).results(A_ref=1.0)
+                b.close()
+                pr.close()
+                for got in (plain, batched):
+                    if ref is None:
+                        ref = got
+                    for p, q in zip(ref, got):
+                        for k in p:
+                            assert np.array_equal(np.asarray(p[k]), np.asarray(q[k])), (t, k)
+        for bad in ({"refill_lanes": 0}, {"refill_lanes": 65}, {"tile_particles": 100}, {"tile_particles": 0},
+                    {"tile_particles": (1 << 22) + 64}, {"groups_per_cu": 0}, {"groups_per_cu": 33}):
+            with pytest.raises(T.TpmcError):
+                ctx.set_tuning(**bad)
+        t = T.Tuning(48, 16384, 8, 1)  # reserved must be 0
+        assert T._lib.tpmc_set_tuning(ctx._h, ctypes.byref(t)) == 1
+    finally:
+        ctx.set_tuning(**base)
+    assert ctx.tuning == base
+
+
 def test_batch_graph_replays(ctx, T):
     """Graph replays, with eager work in between, equal the eager launch."""
     import torch
