@@ -66,6 +66,13 @@ __device__ __forceinline__ float unif32(uint32_t k) { return ((float)(k >> 9) + 
 // G'' = S sqrt(pi) (1 + erf St), so the equation G(mu) = u Z is solved by
 // Halley's method inside a shrinking bracket.  Every evaluation costs one exp
 // and one erfc: the alternative forms below are selected values, not calls.
+//
+// Mixed precision: the iterations that only approach the root run in FP32
+// (cheap exp / erfc) until a step is below 1e-5; then FP64 Halley steps take
+// over from there and end after a step below 1e-5, which by the cubic
+// convergence leaves an error far below the FP64 resolution of the result
+// (usually one FP64 evaluation).  The result is an FP64 root either way; FP32
+// only chooses where the FP64 iteration starts.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG, double& d2G) {
   const double S = q.S;
@@ -80,40 +87,73 @@ __device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& 
   d2G = S * kSqrtPi * c;
 }
 
+// FP32 form of G for the approaching iterations (constants rounded to FP32).
+struct LatConst32 {
+  float S, erfS, erfcS, expmS2;
+  bool small;
+};
+
+__device__ __forceinline__ void latitude_G32(const LatConst32& c, float t, float& G, float& dG, float& d2G) {
+  const float St = c.S * t;
+  const float e = expf(-St * St);
+  const float cc = erfcf(-St);
+  const float E = c.small ? erff(St) + c.erfS : (St < -1.0f ? cc - c.erfcS : (cc - 1.0f) + c.erfS);
+  G = (float)kSqrtPi / (4.0f * c.S) * E + 0.5f * (float)kSqrtPi * c.S * (t * t * cc - c.erfcS) +
+      0.5f * (t * e + c.expmS2);
+  dG = e + (float)kSqrtPi * St * cc;
+  d2G = c.S * (float)kSqrtPi * cc;
+}
+
 // One Halley step inside the bracket [lo, hi], bisection when the step leaves
-// it.  Returns |step| of a Halley (or Newton) step, or +inf after a bisection,
-// so that only a genuine iteration step can end the solve.  The bounds are
-// inclusive: a step below one ulp leaves x unchanged and ends the solve.
-__device__ __forceinline__ double halley_step(double& x, double f, double df, double d2f, double& lo, double& hi) {
-  if (f < 0.0) lo = x;
+// it.  x_new = x - 2 f f' / (2 f'^2 - f f''), or the Newton step f / f' when
+// the Halley factor 1 - f f'' / (2 f'^2) leaves (1/2, 2); one division either
+// way.  Returns |step| of a Halley (or Newton) step, or +inf after a
+// bisection, so that only a genuine iteration step can end a solve.  The
+// bounds are inclusive: a step below one ulp leaves x unchanged.
+template <class T>
+__device__ __forceinline__ T halley_step(T& x, T f, T df, T d2f, T& lo, T& hi) {
+  if (f < T(0)) lo = x;
   else hi = x;
-  const double nt = f / df;
-  const double den = 1.0 - 0.5 * nt * d2f / df;
-  const double xn = x - (den > 0.5 && den < 2.0 ? nt / den : nt);
+  const T df2 = df * df;
+  const T D = T(2) * df2 - f * d2f;
+  const bool hal = D > df2 && D < T(4) * df2;
+  const T xn = x - (hal ? T(2) * f * df : f) / (hal ? D : df);
   if (xn >= lo && xn <= hi) {
-    const double dx = fabs(xn - x);
+    const T dx = fabs(xn - x);
     x = xn;
     return dx;
   }
-  x = 0.5 * (lo + hi);
-  return __builtin_inf();
+  x = T(0.5) * (lo + hi);
+  return (T)__builtin_inf();
 }
 
 __device__ inline double sample_latitude(const QueryDev& q, double u) {
   if (q.s_zero) return 2.0 * u - 1.0;  // S -> 0: g -> cos(phi)/2, mu uniform
   const double target = u * q.Z;
-  // starting point between the S -> 0 law (uniform) and the S -> inf law (density 2 mu)
-  const double wgt = q.S * q.S / (1.0 + q.S * q.S);
-  double x = (1.0 - wgt) * (2.0 * u - 1.0) + wgt * sqrt(u);
+  // FP32 approach from a point between the S -> 0 law (uniform) and the
+  // S -> inf law (density 2 mu)
+  const LatConst32 c{(float)q.S, (float)q.erfS, (float)q.erfcS, (float)q.expmS2, q.S < 0.25};
+  const float uf = (float)u, wgt = c.S * c.S / (1.0f + c.S * c.S);
+  float xf = (1.0f - wgt) * (2.0f * uf - 1.0f) + wgt * sqrtf(uf);
+  float lof = -1.0f, hif = 1.0f;
+  const float tf = (float)target;
+#pragma unroll 1
+  for (int it = 0; it < 5; ++it) {
+    float G, dG, d2G;
+    latitude_G32(c, xf, G, dG, d2G);
+    const float dx = halley_step(xf, G - tf, dG, d2G, lof, hif);
+    if (dx <= 1e-5f || hif - lof <= 1e-5f) break;
+  }
+  double x = (double)xf;
   double lo = -1.0, hi = 1.0;
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double G, dG, d2G;
     latitude_G(q, x, G, dG, d2G);
     const double dx = halley_step(x, G - target, dG, d2G, lo, hi);
-    // cubic convergence: after a step below 1e-7 the remaining error is far
+    // cubic convergence: after a step below 1e-5 the remaining error is far
     // below the FP64 resolution of mu
-    if (dx <= 1e-7 || hi - lo <= 1e-15) break;
+    if (dx <= 1e-5 || hi - lo <= 1e-15) break;
   }
   return x;
 }
@@ -149,23 +189,51 @@ __device__ __forceinline__ void normal_speed_F(const NormalSpeedConsts& k, doubl
   d2F = 2.0 * ea * (1.0 - 2.0 * x * a);
 }
 
+__device__ __forceinline__ void normal_speed_F32(float s, float es2, float erfs, float erfcs, float erfcms, float x,
+                                                 float& F, float& dF, float& d2F) {
+  const float a = x - s;
+  const float ea = expf(-a * a);
+  const float t = erfcf(fabsf(a));
+  const float esum = s < 0.0f ? erfcms - t : (a < 0.0f ? t - erfcs : (1.0f - t) + erfs);
+  F = es2 - ea + (float)kSqrtPi * s * esum;
+  dF = 2.0f * x * ea;
+  d2F = 2.0f * ea * (1.0f - 2.0f * x * a);
+}
+
 __device__ inline double sample_normal_speed(double s, double u) {
   const NormalSpeedConsts k = normal_speed_consts(s);
   const double target = u * k.chi;
-  // starting point: near-Gaussian about s for s > 1, Rayleigh law (exact at s = 0) otherwise
-  double x;
-  if (s > 1.0) x = s + 0.5 / s + erfinv(2.0 * u - 1.0);
-  else x = sqrt(-log1p(-u)) + (s > 0.0 ? 0.5 * s : 0.0);
   // The root lies below max(s, 0) + 7: the upper tail there is below e^{-49},
   // far under the smallest 1 - u the variates produce (2^-33).
-  double lo = 0.0, hi = (s > 0.0 ? s : 0.0) + 7.0;
+  const double hi0 = (s > 0.0 ? s : 0.0) + 7.0;
+  // FP32 approach from a near-Gaussian point about s for s > 1, the Rayleigh
+  // law (exact at s = 0) otherwise.  Below s = -9 the FP32 density underflows;
+  // such s are never drawn in practice, and FP64 then starts at the guess.
+  const float sf = (float)s, uf = (float)u;
+  float xf = sf > 1.0f ? sf + 0.5f / sf + erfinvf(2.0f * uf - 1.0f)
+                       : sqrtf(-log1pf(-uf)) + (sf > 0.0f ? 0.5f * sf : 0.0f);
+  float lof = 0.0f, hif = (float)hi0;
+  if (!(xf > lof && xf < hif)) xf = 0.5f * (lof + hif);
+  if (s > -9.0) {
+    const float es2 = (float)k.es2, erfs = (float)k.erfs, erfcs = (float)k.erfcs, erfcms = (float)k.erfcms;
+    const float tf = (float)target;
+#pragma unroll 1
+    for (int it = 0; it < 5; ++it) {
+      float F, dF, d2F;
+      normal_speed_F32(sf, es2, erfs, erfcs, erfcms, xf, F, dF, d2F);
+      const float dx = halley_step(xf, F - tf, dF, d2F, lof, hif);
+      if (dx <= 1e-5f * xf || hif - lof <= 1e-5f * xf) break;
+    }
+  }
+  double x = (double)xf;
+  double lo = 0.0, hi = hi0;
   if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double F, dF, d2F;
     normal_speed_F(k, x, F, dF, d2F);
     const double dx = halley_step(x, F - target, dF, d2F, lo, hi);
-    if (dx <= 1e-7 * x || hi - lo <= 1e-15 * x) break;
+    if (dx <= 1e-5 * x || hi - lo <= 1e-15 * x) break;
   }
   return x;
 }
