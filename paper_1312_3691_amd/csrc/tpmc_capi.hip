@@ -782,6 +782,7 @@ static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   a.n_entries = b->nq;
   a.refill = b->refill;
   a.tile = b->tile;
+  a.lds_tris = b->mode == kTallyLds ? (uint32_t)m->nt : 0u;
   launch_batch(a, m->stack_slots, b->mode, b->grid, st);
   if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, (uint32_t)m->nt, st);
 }
@@ -948,7 +949,8 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   s->h_tile0.assign(tile0, tile0 + n);
   s->h_tiles.assign(count, count + n);
   uint64_t acc = 0;
-  int stack = 8;
+  int stack = 4;
+  uint32_t lds_tris = 0;  // largest per-triangle tally kept in LDS by the auto mode
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t sl = slots[i];
     if (sl >= s->max_slots || !s->used[sl]) return fail(TPMC_E_INVALID, "entry %u names an empty slot %u", i, sl);
@@ -958,6 +960,8 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
                   (unsigned long long)tile0[i], (unsigned long long)count[i], (unsigned long long)tiles);
     acc += count[i];
     if (s->mesh_of[sl]->stack_slots > stack) stack = s->mesh_of[sl]->stack_slots;
+    const QueryDev& hq = s->hq[sl];
+    if (hq.per_tri && hq.nt <= (uint32_t)kLdsTallyMaxTris && hq.nt > lds_tris) lds_tris = hq.nt;
   }
   if (acc == 0) return TPMC_OK;
   HIP_TRY(hipSetDevice(s->ctx->device));
@@ -977,6 +981,7 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   a.n_entries = n;
   a.refill = s->ctx->tune.refill_lanes;
   a.tile = s->tile;
+  a.lds_tris = lds_tris;
   launch_batch(a, stack, kTallyAuto, s->ctx->n_cu * (int)s->ctx->tune.groups_per_cu, st);
   HIP_CHECK_LAUNCH("server step");
   return TPMC_OK;

@@ -358,7 +358,7 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
 template <int STACK, int MODE, bool COUNT>
 __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
   __shared__ int stk[STACK][kBlock];
-  __shared__ unsigned long long lt[MODE == kTallyLds ? kLdsTallyMaxTris * 7 : (MODE == kTallyLane ? 2 * 7 * kBlock : 1)];
+  extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
   const QueryDev& q = *a.q;
   if (MODE == kTallyLds) {
     for (uint32_t i = threadIdx.x; i < a.nt * 7u; i += kBlock) lt[i] = 0ull;
@@ -461,10 +461,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
-  __shared__ unsigned long long lt[kMayLds                ? kLdsTallyMaxTris * 7
-                                   : MODE == kTallyLane   ? 2 * 7 * kBlock
-                                   : MODE == kTallyTotals ? 7 * kBlock
-                                                          : 1];
+  extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -711,13 +708,27 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
   out[i] = r;
 }
 
+// Dynamic LDS of the tallies: the workgroup tally of lds_tris triangles, the
+// per-lane slots of <= 2-triangle meshes, or per-lane totals (persistent
+// kernel only; the plain kernel keeps totals in registers).
+size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent) {
+  switch (mode) {
+    case kTallyLds:
+    case kTallyAuto: return (size_t)lds_tris * 7 * sizeof(unsigned long long);
+    case kTallyLane: return (size_t)2 * 7 * kBlock * sizeof(unsigned long long);
+    case kTallyTotals: return persistent ? (size_t)7 * kBlock * sizeof(unsigned long long) : 0;
+    default: return 0;
+  }
+}
+
 template <int STACK, bool COUNT>
 void launch_trace_mode(const TraceArgs& a, TallyMode mode, int grid, hipStream_t st) {
+  const size_t lds = tally_lds_bytes(mode, a.nt, false);
   switch (mode) {
-    case kTallyGlobal: trace_kernel<STACK, kTallyGlobal, COUNT><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyLds: trace_kernel<STACK, kTallyLds, COUNT><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyLane: trace_kernel<STACK, kTallyLane, COUNT><<<grid, kBlock, 0, st>>>(a); break;
-    default: trace_kernel<STACK, kTallyTotals, COUNT><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyGlobal: trace_kernel<STACK, kTallyGlobal, COUNT><<<grid, kBlock, lds, st>>>(a); break;
+    case kTallyLds: trace_kernel<STACK, kTallyLds, COUNT><<<grid, kBlock, lds, st>>>(a); break;
+    case kTallyLane: trace_kernel<STACK, kTallyLane, COUNT><<<grid, kBlock, lds, st>>>(a); break;
+    default: trace_kernel<STACK, kTallyTotals, COUNT><<<grid, kBlock, lds, st>>>(a); break;
   }
 }
 
@@ -729,12 +740,13 @@ void launch_trace_stack(const TraceArgs& a, TallyMode mode, int grid, hipStream_
 
 template <int STACK>
 void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t st) {
+  const size_t lds = tally_lds_bytes(mode, a.lds_tris, true);
   switch (mode) {
-    case kTallyLane: batch_kernel<STACK, kTallyLane><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyLds: batch_kernel<STACK, kTallyLds><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyTotals: batch_kernel<STACK, kTallyTotals><<<grid, kBlock, 0, st>>>(a); break;
-    case kTallyAuto: batch_kernel<STACK, kTallyAuto><<<grid, kBlock, 0, st>>>(a); break;
-    default: batch_kernel<STACK, kTallyGlobal><<<grid, kBlock, 0, st>>>(a); break;
+    case kTallyLane: batch_kernel<STACK, kTallyLane><<<grid, kBlock, lds, st>>>(a); break;
+    case kTallyLds: batch_kernel<STACK, kTallyLds><<<grid, kBlock, lds, st>>>(a); break;
+    case kTallyTotals: batch_kernel<STACK, kTallyTotals><<<grid, kBlock, lds, st>>>(a); break;
+    case kTallyAuto: batch_kernel<STACK, kTallyAuto><<<grid, kBlock, lds, st>>>(a); break;
+    default: batch_kernel<STACK, kTallyGlobal><<<grid, kBlock, lds, st>>>(a); break;
   }
 }
 
@@ -749,6 +761,7 @@ void zero_u32(uint32_t* p, uint64_t n, hipStream_t st) {
 }
 
 int stack_slots_for_depth(uint32_t depth) {
+  if (depth <= 4) return 4;
   if (depth <= 8) return 8;
   if (depth <= 16) return 16;
   if (depth <= 32) return 32;
@@ -762,6 +775,7 @@ void launch_seed(const QueryDev* d_q, uint64_t n, float* const x[3], float* cons
 
 void launch_trace(const TraceArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st) {
   switch (stack_slots) {
+    case 4: launch_trace_stack<4>(a, mode, grid, st); break;
     case 8: launch_trace_stack<8>(a, mode, grid, st); break;
     case 16: launch_trace_stack<16>(a, mode, grid, st); break;
     case 32: launch_trace_stack<32>(a, mode, grid, st); break;
@@ -771,6 +785,7 @@ void launch_trace(const TraceArgs& a, int stack_slots, TallyMode mode, int grid,
 
 void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st) {
   switch (stack_slots) {
+    case 4: launch_batch_mode<4>(a, mode, grid, st); break;
     case 8: launch_batch_mode<8>(a, mode, grid, st); break;
     case 16: launch_batch_mode<16>(a, mode, grid, st); break;
     case 32: launch_batch_mode<32>(a, mode, grid, st); break;

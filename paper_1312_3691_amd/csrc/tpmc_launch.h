@@ -47,6 +47,7 @@ struct BatchArgs {
   uint32_t n_entries;
   uint32_t refill;                 // as TraceArgs::refill
   uint64_t tile;                   // particles per tile (multiple of 64)
+  uint32_t lds_tris;               // largest nt of an entry with an LDS tally (kTallyLds / kTallyAuto)
 };
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
