@@ -116,7 +116,7 @@ void tpmc_destroy_ctx(tpmc_ctx ctx);
  * tuning.  Set by the autotuner (paper_1312_3691_amd/autotune.py) or by hand;
  * a context starts with the defaults below. */
 typedef struct {
-  uint32_t refill_lanes;   /* 1..64, default 48: a wave serves the lanes whose ray segment has ended
+  uint32_t refill_lanes;   /* 1..64, default 32: a wave serves the lanes whose ray segment has ended
                               (re-emission, tallies, next segment or particle) once fewer than this
                               many of its 64 lanes are still traversing */
   uint32_t tile_particles; /* multiple of 64 in [64, 2^22], default 16384: particles per work tile

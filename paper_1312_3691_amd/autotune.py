@@ -21,10 +21,10 @@ import dataclasses
 from typing import Callable, Dict, Iterable, List, Sequence, Tuple
 
 # candidate values, searched in this order (one coordinate at a time)
-REFILL = (24, 32, 40, 48, 56)
+REFILL = (16, 24, 32, 40, 48)
 TILE = (4096, 16384, 65536)
 GROUPS = (4, 8, 16)
-DEFAULT = {"refill_lanes": 48, "tile_particles": 16384, "groups_per_cu": 8}
+DEFAULT = {"refill_lanes": 32, "tile_particles": 16384, "groups_per_cu": 8}
 AXES: Tuple[Tuple[str, Sequence[int]], ...] = (("refill_lanes", REFILL), ("tile_particles", TILE),
                                               ("groups_per_cu", GROUPS))
 

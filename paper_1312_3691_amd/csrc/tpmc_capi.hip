@@ -344,7 +344,7 @@ extern "C" tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out) 
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->capture_stream = nullptr;
   c->n_cu = prop.multiProcessorCount;
-  c->tune.refill_lanes = 48;
+  c->tune.refill_lanes = 32;
   c->tune.tile_particles = 16384;
   c->tune.groups_per_cu = 8;
   c->tune.reserved = 0;

@@ -105,9 +105,10 @@ struct Lane {
 constexpr int kDone = -0x7FFFFFFF - 1;  // Seg::cur once the traversal has ended
 
 struct Seg {
-  int cur;   // next node to visit, or kDone
-  int sp;    // stack depth
-  int best;  // closest triangle so far (Morton position), -1 if none
+  int cur;     // next node to visit, or kDone
+  int sp;      // stack depth
+  int best;    // closest triangle so far (Morton position), -1 if none
+  int p0, p1;  // leaves whose boxes were hit, waiting for a leaf phase (-1: none)
   float t_best, b0, b1, b2;
 };
 
@@ -115,8 +116,14 @@ __device__ __forceinline__ void seg_begin(Seg& s) {
   s.cur = 0;
   s.sp = 0;
   s.best = -1;
+  s.p0 = s.p1 = -1;
   s.t_best = __builtin_inff();
 }
+
+// Lane states: traversing (next node known, no leaf waiting), waiting for a
+// leaf phase, or finished (segment ready for its service pass).
+__device__ __forceinline__ bool seg_traversing(const Seg& s) { return s.cur != kDone && s.p0 < 0; }
+__device__ __forceinline__ bool seg_finished(const Seg& s) { return s.cur == kDone && s.p0 < 0; }
 
 // Candidate leaf k: two-sided test, the triangle just left excluded.
 template <bool COUNT>
@@ -137,8 +144,13 @@ __device__ __forceinline__ void test_leaf(const TriRec* tris, const uint32_t* or
   }
 }
 
-// One traversal step of a lane with s.cur != kDone.  Each node is entered at
-// most once per ray, so a segment takes at most nt - 1 steps.
+// One traversal step of a traversing lane.  Hit leaves are not tested here
+// but recorded in p0 / p1 (a node has two children), and the lane then waits
+// for a leaf phase: the costly triangle test runs for many lanes at once
+// instead of for the few lanes that happen to reach a leaf in a given step.
+// Each node is entered at most once per ray, so a segment takes at most nt - 1
+// steps and nt leaf tests.  Trees of depth <= 4 (a 4-slot stack: meshes of a
+// few triangles, where nearly every step ends at leaves) test them in place.
 template <int STACK, bool COUNT>
 __device__ __forceinline__ void trav_step(const Node* nodes, const TriRec* tris, const uint32_t* orig, const Ray& r,
                                           int prev, Seg& s, int (*stk)[kBlock], uint32_t& n_nodes,
@@ -151,14 +163,19 @@ __device__ __forceinline__ void trav_step(const Node* nodes, const TriRec* tris,
   float tn0, tn1;
   bool h0 = slab(r, A.x, A.y, A.z, A.w, B.x, B.y, s.t_best, tn0);
   bool h1 = slab(r, B.z, B.w, C.x, C.y, C.z, C.w, s.t_best, tn1);
-  if (h0 && L.x < 0) {
-    test_leaf<COUNT>(tris, orig, r, ~L.x, prev, s, n_tests);
-    h0 = false;
+  const bool leaf0 = h0 && L.x < 0, leaf1 = h1 && L.y < 0;
+  if (STACK <= 4) {
+    if (leaf0) test_leaf<COUNT>(tris, orig, r, ~L.x, prev, s, n_tests);
+    if (leaf1) test_leaf<COUNT>(tris, orig, r, ~L.y, prev, s, n_tests);
+  } else {
+    if (leaf0) s.p0 = ~L.x;
+    if (leaf1) {
+      if (leaf0) s.p1 = ~L.y;
+      else s.p0 = ~L.y;
+    }
   }
-  if (h1 && L.y < 0) {
-    test_leaf<COUNT>(tris, orig, r, ~L.y, prev, s, n_tests);
-    h1 = false;
-  }
+  h0 = h0 && !leaf0;
+  h1 = h1 && !leaf1;
   if (h0 && h1 && s.sp < STACK) {
     const bool first0 = tn0 <= tn1;
     stk[s.sp][lane] = first0 ? L.y : L.x;
@@ -170,6 +187,18 @@ __device__ __forceinline__ void trav_step(const Node* nodes, const TriRec* tris,
     s.cur = L.y;
   } else {
     s.cur = s.sp == 0 ? kDone : stk[--s.sp][lane];
+  }
+}
+
+// Leaf phase (convergent): every waiting lane tests its first pending leaf;
+// a second one moves up and waits for the next phase.
+template <bool COUNT>
+__device__ __forceinline__ void leaf_phase(const TriRec* tris, const uint32_t* orig, const Ray& r, int prev, Seg& s,
+                                           uint32_t& n_tests) {
+  if (s.p0 >= 0) {
+    test_leaf<COUNT>(tris, orig, r, s.p0, prev, s, n_tests);
+    s.p0 = s.p1;
+    s.p1 = -1;
   }
 }
 
@@ -369,10 +398,11 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
   Acc A;
   acc_zero(A);
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  const uint32_t max_steps = a.nt + 64u;
+  const uint32_t max_steps = 2u * a.nt + 64u;
   Lane L;
   Seg s;
   Ray r;
+  seg_begin(s);
   auto load = [&](Lane& l) {
     l.ox = a.x[0][l.pid]; l.oy = a.x[1][l.pid]; l.oz = a.x[2][l.pid];
     l.wx = a.w[0][l.pid]; l.wy = a.w[1][l.pid]; l.wz = a.w[2][l.pid];
@@ -390,8 +420,13 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
   make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
   uint32_t guard = 0;  // steps since the last service pass (wave-uniform)
   while (__ballot(L.live) != 0ull) {
-    if ((uint32_t)__popcll(__ballot(L.live && s.cur != kDone)) < a.refill) {
-      const bool fin = L.live && s.cur == kDone;
+    uint32_t ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
+    if (ntrav < a.refill && __ballot(L.live && s.p0 >= 0) != 0ull) {
+      leaf_phase<COUNT>(a.tris, a.orig, r, L.prev, s, A.tests);
+      ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
+    }
+    if (ntrav < a.refill) {
+      const bool fin = L.live && seg_finished(s);
       if (__ballot(fin) != 0ull) {
         Hit h;
         h.valid = false;
@@ -416,10 +451,12 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
       make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
       guard = 0;
     }
-    // Between service passes every traversing lane ends its segment within nt
-    // steps; the bound only keeps a damaged tree from spinning a wave.
+    // Between service passes every traversing lane ends its segment within
+    // nt - 1 steps and nt leaf phases; the bound only keeps a damaged tree
+    // from spinning a wave.
     if (++guard > max_steps) s.cur = kDone;
-    if (L.live && s.cur != kDone) trav_step<STACK, COUNT>(a.nodes, a.tris, a.orig, r, L.prev, s, stk, A.nodes, A.tests);
+    if (L.live && seg_traversing(s))
+      trav_step<STACK, COUNT>(a.nodes, a.tris, a.orig, r, L.prev, s, stk, A.nodes, A.tests);
   }
   flush_acc(A, a.scal, MODE == kTallyTotals);
   if (MODE == kTallyLane) flush_lane_tally(lt, a.tally, a.nt);
@@ -530,16 +567,23 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     Seg s;
     Ray r;
     L.live = false;
+    seg_begin(s);
     s.cur = kDone;
-    const uint32_t max_steps = q.nt + 64u;
+    const uint32_t max_steps = 2u * q.nt + 64u;
     uint32_t guard = 0;                // steps since the last service pass (wave-uniform)
     bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
     uint64_t q_pid0 = 0;               // particle id of queue slot 0
     for (;;) {
-      if ((uint32_t)__popcll(__ballot(L.live && s.cur != kDone)) < a.refill) {
+      uint32_t ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
+      if (ntrav < a.refill && __ballot(L.live && s.p0 >= 0) != 0ull) {
+        uint32_t n1 = 0;
+        leaf_phase<false>(tris, orig, r, L.prev, s, n1);
+        ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
+      }
+      if (ntrav < a.refill) {
         // serve every lane whose segment has ended
-        const bool fin = L.live && s.cur == kDone;
+        const bool fin = L.live && seg_finished(s);
         if (__ballot(fin) != 0ull) {
           Hit h;
           h.valid = false;
@@ -619,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       }
       // as in the plain path: a bound only against a damaged tree
       if (++guard > max_steps) s.cur = kDone;
-      if (L.live && s.cur != kDone) {
+      if (L.live && seg_traversing(s)) {
         uint32_t n0 = 0, n1 = 0;
         trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
       }
