@@ -299,7 +299,11 @@ def workload_sweep(args):
 
 def workload_served(args):
     """Served stream: Poisson arrivals over four resident satellite meshes (~1k, 20k, 100k,
-    500k triangles), random attitudes, S ~ U[2, 10], N log-uniform in [1e5, 1e7]."""
+    500k triangles), random attitudes, S ~ U[2, 10], N log-uniform in [1e5, 1e7], alpha = 0.9,
+    per-request per-triangle tallies admitted against an HBM budget.  Saturation throughput
+    first (everything submitted at once), then offered loads of 0.5 / 0.8 / 0.95 of it, each
+    with `--warm` warm-up requests left out of the latency figures; the same stream through a
+    FIFO plain path (one query at a time, host sync) for comparison."""
     import asyncio
 
     import torch
@@ -311,61 +315,98 @@ def workload_served(args):
     sizes = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
     meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i)) for i, (k, v) in enumerate(sizes.items())}
     rng = np.random.default_rng(7)
-    n_req = int(args.requests)
+    n_warm, n_meas = int(args.warm), int(args.requests)
+    n_req = n_warm + n_meas
     names = list(sizes)
     quats = I.random_quats(n_req, 3)
     reqs = []
     for i in range(n_req):
         n = int(10 ** rng.uniform(5, 7))
         reqs.append((names[rng.integers(0, 4)], I.query(q=tuple(quats[i]), S=float(rng.uniform(2, 10)), T_inf=T_INF,
-                                                         T_w=T_W, alpha=0.9, n=n, seed=10_000 + i, flags=1)))
-    max_slots = 64
+                                                         T_w=T_W, alpha=0.9, n=n, seed=10_000 + i)))
+    max_slots = int(args.slots)
+    pool_words = int(args.hbm_budget_gb * 2 ** 30) // 8
     tuning = tune_for(args, meshes["sat100k"], [q for m, q in reqs if m == "sat100k"][:64])
-    ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=1 << 20)
-    # saturation: everything submitted at once
+    ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=pool_words)
+
     def run(rate):
-        sched = Scheduler(ex, max_slots=max_slots, pool_words=1 << 20, tiles_per_step=int(args.tiles_per_step))
+        sched = Scheduler(ex, max_slots=max_slots, pool_words=pool_words, tiles_per_step=int(args.tiles_per_step))
         gaps = rng.exponential(1.0 / rate, n_req) if rate else np.zeros(n_req)
 
         async def main():
             stop = asyncio.Event()
             runner = asyncio.ensure_future(sched.run(stop))
             futs = []
-            for (mesh, q), g in zip(reqs, gaps):
-                if g > 0:
-                    await asyncio.sleep(float(g))
-                futs.append(sched.submit(mesh, q))
-            res = await asyncio.gather(*futs)
+            # absolute (Poisson) arrival times: every request whose time has come is
+            # submitted with that time, however long the scheduler held the loop
+            t0 = time.perf_counter()
+            arrive = t0 + np.cumsum(gaps)
+            t_meas = float(arrive[n_warm]) if rate else t0
+            k = 0
+            while k < n_req:
+                now = time.perf_counter()
+                while k < n_req and arrive[k] <= now:
+                    futs.append(sched.submit(reqs[k][0], reqs[k][1], t_arrival=float(arrive[k])))
+                    k += 1
+                if k < n_req:
+                    await asyncio.sleep(max(0.0, float(arrive[k]) - time.perf_counter()))
+            res = await asyncio.gather(*futs, return_exceptions=True)
+            t_end = time.perf_counter()
             stop.set()
             sched._wake.set()
             await runner
-            return res
-        t0 = time.perf_counter()
-        res = asyncio.run(main())
-        dt = time.perf_counter() - t0
-        p50, p99 = sched.percentiles()
-        return res, dt, p50, p99, sched.stats
-    res, dt, p50, p99, st = run(0)
-    hits = sum(r["hits"] for r in res)
-    sat_rate = n_req / dt
+            return res, t_end - t_meas
+
+        res, dt = asyncio.run(main())
+        ok = [r for r in res[n_warm:] if isinstance(r, dict)]
+        p50, p99 = sched.percentiles(skip=n_warm)
+        return res, {"req_per_s": len(ok) / dt, "hits_per_s": sum(r["hits"] for r in ok) / dt,
+                     "p50_ms": p50, "p99_ms": p99, "steps": sched.stats.steps,
+                     "max_active": sched.stats.max_active, "rejected": sched.stats.rejected,
+                     "failed": sched.stats.failed, "completed": len(ok)}
+
+    log("served: saturation")
+    res, sat = run(0)
+    sat_rate = sat["req_per_s"]
     loads = {}
-    for frac in (0.5, 0.8):
-        r2, dt2, a, b, st2 = run(frac * sat_rate)
-        loads[str(frac)] = {"offered_req_per_s": frac * sat_rate, "p50_ms": a, "p99_ms": b,
-                            "hits_per_s": sum(x["hits"] for x in r2) / dt2, "steps": st2.steps}
+    for frac in (0.5, 0.8, 0.95):
+        log(f"served: load {frac}")
+        _, st = run(frac * sat_rate)
+        loads[str(frac)] = dict(st, offered_req_per_s=frac * sat_rate)
+    # FIFO plain path: one request at a time (seed -> trace -> forces, host sync), service
+    # times measured; latencies for the 0.8 load's arrival process by a single-server queue
+    log("served: FIFO plain path")
+    service = []
+    for mesh, q in reqs[:n_warm + min(n_meas, int(args.fifo_requests))]:
+        t0 = time.perf_counter()
+        r, pr = tpmc.run(meshes[mesh], [q])
+        service.append(time.perf_counter() - t0)
+        pr.close()
+    service = np.array(service[n_warm:]) if len(service) > n_warm else np.array(service)
+    arrivals = np.cumsum(rng.exponential(1.0 / (0.8 * sat_rate), len(service)))
+    finish, lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        finish = max(finish, a) + sv
+        lat.append((finish - a) * 1e3)
+    fifo = {"service_ms_mean": float(service.mean() * 1e3), "capacity_req_per_s": float(1.0 / service.mean()),
+            "requests": int(len(service)),
+            "p50_ms_at_0.8_of_served_saturation": float(np.percentile(lat, 50)),
+            "p99_ms_at_0.8_of_served_saturation": float(np.percentile(lat, 99))}
     # every served result equals its solo run (first 8 requests)
     same = True
     for (mesh, q), r in list(zip(reqs, res))[:8]:
         solo, pr = tpmc.run(meshes[mesh], [q])
-        same = same and all(np.array_equal(np.asarray(solo[0][k]), np.asarray(r[k])) for k in solo[0])
+        same = same and isinstance(r, dict) and all(np.array_equal(np.asarray(solo[0][k]), np.asarray(r[k]))
+                                                    for k in solo[0])
         pr.close()
     torch.cuda.synchronize()
-    _line("particle-surface hits/sec on 1 MI355X (served stream); p50/p99 query ms", hits / dt, "hits/s", dt, 1, 0,
-          {"workload": f"{n_req} requests over satellites {list(sizes.values())} tris, N log-uniform 1e5-1e7, "
-                       f"S~U[2,10], alpha=0.9", "path": "continuous batching, one persistent launch per step"},
-          {"saturation": {"req_per_s": sat_rate, "p50_ms": p50, "p99_ms": p99, "steps": st.steps,
-                          "max_active": st.max_active},
-           "loads": loads, "query_ms_p50": p50, "query_ms_p99": p99, "served_equals_solo": bool(same),
+    _line("particle-surface hits/sec on 1 MI355X (served stream); p50/p99 query ms", sat["hits_per_s"], "hits/s",
+          n_meas / sat_rate, 1, n_warm,
+          {"workload": f"{n_warm} + {n_meas} requests over satellites {list(sizes.values())} tris, N log-uniform "
+                       f"1e5-1e7, S~U[2,10], alpha=0.9, per-triangle tallies", "slots": max_slots,
+           "hbm_budget_gb": args.hbm_budget_gb, "path": "continuous batching, one persistent launch per step"},
+          {"saturation": sat, "loads": loads, "query_ms_p50": loads["0.8"]["p50_ms"],
+           "query_ms_p99": loads["0.8"]["p99_ms"], "fifo_plain_path": fifo, "served_equals_solo": bool(same),
            "tuning": tuning})
 
 
@@ -384,7 +425,11 @@ def main():
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
-    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
+    ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
+    ap.add_argument("--slots", type=int, default=64, help="served: request slots")
+    ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="served: per-request tally budget")
+    ap.add_argument("--fifo-requests", type=int, default=600, help="served: requests timed on the plain path")
     ap.add_argument("--tiles-per-step", type=int, default=2048)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (library defaults)")
     ap.add_argument("--tune-particles", type=float, default=2e7, help="particles per autotuner trial")

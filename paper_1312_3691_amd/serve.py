@@ -75,6 +75,7 @@ class Request:
 @dataclass
 class Stats:
     latencies_ms: list = field(default_factory=list)
+    latency_ids: list = field(default_factory=list)  # request id of each latency
     admitted: int = 0
     rejected: int = 0
     failed: int = 0
@@ -147,10 +148,12 @@ class Scheduler:
         self._wake = None
 
     # -- client side -------------------------------------------------------
-    def submit(self, mesh: str, query: dict) -> asyncio.Future:
+    def submit(self, mesh: str, query: dict, t_arrival: float | None = None) -> asyncio.Future:
+        """Queue a request; its latency counts from t_arrival (default: now),
+        so a load generator can pass the scheduled arrival time."""
         loop = asyncio.get_event_loop()
         fut = loop.create_future()
-        req = Request(self._next_id, mesh, dict(query), self.clock(), fut)
+        req = Request(self._next_id, mesh, dict(query), self.clock() if t_arrival is None else t_arrival, fut)
         self._next_id += 1
         try:
             req.words = self.ex.tally_words(mesh, query)
@@ -253,6 +256,7 @@ class Scheduler:
                 if not r.future.done():
                     r.future.set_result(out)
                 self.stats.latencies_ms.append((now - r.t_arrival) * 1e3)
+                self.stats.latency_ids.append(r.rid)
                 self.stats.hits += int(out.get("hits", 0)) if isinstance(out, dict) else 0
                 self._retire(r)
         return True
@@ -275,9 +279,11 @@ class Scheduler:
                 if w is not None and not w.done():
                     w.cancel()
 
-    def percentiles(self):
+    def percentiles(self, skip: int = 0):
+        """p50 / p99 latency (ms) of the completed requests, leaving out the
+        first `skip` submitted (warm-up)."""
         import numpy as np
-        lat = self.stats.latencies_ms
+        lat = [ms for ms, rid in zip(self.stats.latencies_ms, self.stats.latency_ids) if rid >= skip]
         if not lat:
             return None, None
         return float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
