@@ -156,9 +156,12 @@ __device__ __forceinline__ void trav_step(const Node* nodes, const TriRec* tris,
                                           int prev, Seg& s, int (*stk)[kBlock], uint32_t& n_nodes,
                                           uint32_t& n_tests) {
   const int lane = threadIdx.x;
-  const gptr<vf4> np = (gptr<vf4>)(nodes + s.cur);
+  // 32-bit byte offset from the (scalar) base: one shift, no 64-bit address math
+  const gptr<char> base = (gptr<char>)nodes;
+  const uint32_t off = (uint32_t)s.cur * (uint32_t)sizeof(Node);
+  const gptr<vf4> np = (gptr<vf4>)(base + off);
   const vf4 A = np[0], B = np[1], C = np[2];
-  const vi4 L = ((gptr<vi4>)(nodes + s.cur))[3];
+  const vi4 L = ((gptr<vi4>)(base + off))[3];
   if (COUNT) ++n_nodes;
   float tn0, tn1;
   bool h0 = slab(r, A.x, A.y, A.z, A.w, B.x, B.y, s.t_best, tn0);
@@ -569,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     L.live = false;
     seg_begin(s);
     s.cur = kDone;
-    const uint32_t max_steps = 2u * q.nt + 64u;
+    const uint32_t max_steps = __builtin_amdgcn_readfirstlane(2u * q.nt + 64u);
     uint32_t guard = 0;                // steps since the last service pass (wave-uniform)
     bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
