@@ -135,6 +135,10 @@ tpmc_status tpmc_set_tuning(tpmc_ctx ctx, const tpmc_tuning* t);
  * the triangle centroids; closest-hit tracing on a triangulation, Sec. II.A).
  *   xyz: host float [nv][3], metres, body frame.  tri: host uint32 [nt][3].
  * Triangles are two-sided; zero-area triangles are accepted and never hit.
+ * Also marks, per triangle and side, whether the whole mesh lies on the other
+ * side of its plane, so that a particle leaving that side provably cannot hit
+ * again and escapes without being traced (exact; nt * nv FP64 distance
+ * evaluations at build).  nt < 2^30, nv < 2^32.
  * Builds on the device (synchronises); the handle owns its device memory. */
 tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
                             tpmc_mesh* out);

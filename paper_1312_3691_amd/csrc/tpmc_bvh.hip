@@ -207,6 +207,59 @@ __global__ void pack_tris_kernel(const float* __restrict__ xyz, const uint32_t* 
   orig[k] = id;
 }
 
+// Supporting-plane flags, used to resolve the segment that leaves a hit
+// without tracing it.  For triangle k (Morton order) with exact plane
+// through v0 and normal n = (v1 - v0) x (v2 - v0) / |...|: bit 30 of orig[k]
+// when no mesh vertex lies above the plane by more than tol, bit 31 when none
+// lies below it by more than tol, tol = 2^-22 max|coordinate of triangle k|.
+// A particle re-emitted from k leaves from a point 8 ulps of that scale (at
+// least 5 once the rounding of the hit point is counted) above the plane on
+// its emission side and moves away from the plane (or parallel to it), so
+// when the mesh lies within tol of the other side, the outgoing ray cannot hit
+// anything: every mesh point is below its starting height.  FP64 distances
+// over all vertices, tiled through LDS.
+__global__ __launch_bounds__(kBlock) void support_kernel(const float* __restrict__ xyz, uint32_t nv,
+                                                         const TriRec* __restrict__ tris, uint32_t nt,
+                                                         uint32_t* __restrict__ orig) {
+  __shared__ float vx[kBlock], vy[kBlock], vz[kBlock];
+  const uint32_t k = blockIdx.x * kBlock + threadIdx.x;
+  const TriRec t = tris[k < nt ? k : nt - 1];
+  const double ox = t.v0x, oy = t.v0y, oz = t.v0z;
+  const double e1x = (double)t.v1x - ox, e1y = (double)t.v1y - oy, e1z = (double)t.v1z - oz;
+  const double e2x = (double)t.v2x - ox, e2y = (double)t.v2y - oy, e2z = (double)t.v2z - oz;
+  double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  const double len = sqrt(nx * nx + ny * ny + nz * nz);
+  const double inv = len > 0.0 ? 1.0 / len : 0.0;
+  nx *= inv;
+  ny *= inv;
+  nz *= inv;
+  double hi = -__builtin_inf(), lo = __builtin_inf();
+  for (uint32_t base = 0; base < nv; base += kBlock) {
+    const uint32_t i = base + threadIdx.x;
+    __syncthreads();
+    if (i < nv) {
+      vx[threadIdx.x] = xyz[3ull * i];
+      vy[threadIdx.x] = xyz[3ull * i + 1];
+      vz[threadIdx.x] = xyz[3ull * i + 2];
+    }
+    __syncthreads();
+    const uint32_t m = nv - base < (uint32_t)kBlock ? nv - base : (uint32_t)kBlock;
+    for (uint32_t j = 0; j < m; ++j) {
+      const double d = nx * ((double)vx[j] - ox) + ny * ((double)vy[j] - oy) + nz * ((double)vz[j] - oz);
+      hi = fmax(hi, d);
+      lo = fmin(lo, d);
+    }
+  }
+  if (k >= nt || len == 0.0) return;  // zero-area triangles are never hit
+  const float sc = fmaxf(fmaxf(fmaxf(fabsf(t.v0x), fabsf(t.v0y)), fmaxf(fabsf(t.v0z), fabsf(t.v1x))),
+                         fmaxf(fmaxf(fabsf(t.v1y), fabsf(t.v1z)), fmaxf(fmaxf(fabsf(t.v2x), fabsf(t.v2y)), fabsf(t.v2z))));
+  const double tol = ldexp((double)sc, -22);
+  uint32_t w = orig[k];
+  if (hi <= tol) w |= 1u << 30;
+  if (lo >= -tol) w |= 1u << 31;
+  orig[k] = w;
+}
+
 __device__ __forceinline__ float ld_relaxed(const float* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -286,6 +339,12 @@ __global__ void single_node_kernel(Node* nodes, const TriRec* tris) {
 }
 
 }  // namespace
+
+void mark_support(const float* d_xyz, uint64_t nv, const TriRec* d_tris, uint64_t nt, uint32_t* d_orig,
+                  hipStream_t st) {
+  support_kernel<<<(unsigned)((nt + kBlock - 1) / kBlock), kBlock, 0, st>>>(d_xyz, (uint32_t)nv, d_tris,
+                                                                           (uint32_t)nt, d_orig);
+}
 
 size_t bvh_scratch_bytes(uint64_t nt) {
   const uint64_t nblocks = (nt + kSortTile - 1) / kSortTile;

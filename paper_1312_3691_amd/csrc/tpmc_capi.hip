@@ -117,6 +117,7 @@ extern "C" tpmc_status tpmc_check_mesh(const float* xyz, uint64_t nv, const uint
   if (!xyz || !tri) return fail(TPMC_E_INVALID, "mesh arrays must not be NULL");
   if (nt == 0) return fail(TPMC_E_MESH, "mesh has no triangles");
   if (nv == 0) return fail(TPMC_E_MESH, "mesh has no vertices");
+  if (nv > 0xFFFFFFFFull) return fail(TPMC_E_MESH, "mesh has too many vertices (%llu)", (unsigned long long)nv);
   if (nt >= (1ull << 30)) return fail(TPMC_E_MESH, "mesh has too many triangles (%llu)", (unsigned long long)nt);
   for (uint64_t i = 0; i < 3 * nv; ++i)
     if (!std::isfinite(xyz[i])) return fail(TPMC_E_MESH, "vertex %llu is not finite", (unsigned long long)(i / 3));
@@ -420,6 +421,11 @@ extern "C" tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t 
     const float lo[3] = {(float)m->lo[0], (float)m->lo[1], (float)m->lo[2]};
     const float hi[3] = {(float)m->hi[0], (float)m->hi[1], (float)m->hi[2]};
     e = build_bvh(d_xyz, d_tri, nt, lo, hi, scratch, m->nodes, m->tris, m->orig, &depth, ctx->stream);
+  }
+  if (e == hipSuccess) {
+    mark_support(d_xyz, nv, m->tris, nt, m->orig, ctx->stream);
+    e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipGetLastError();
   }
   if (d_xyz) (void)hipFree(d_xyz);
   if (d_tri) (void)hipFree(d_tri);

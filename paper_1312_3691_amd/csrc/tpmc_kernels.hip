@@ -68,7 +68,10 @@ __device__ __forceinline__ TriRec load_tri(const TriRec* p, int k) {
   return TriRec{a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
 }
 
-__device__ __forceinline__ uint32_t load_orig(const uint32_t* p, int k) { return ((gptr<uint32_t>)p)[k]; }
+// orig[] word of a triangle: original index in bits 0..29, supporting-plane
+// flags in bits 30 (nothing above the plane) and 31 (nothing below).
+__device__ __forceinline__ uint32_t load_orig_word(const uint32_t* p, int k) { return ((gptr<uint32_t>)p)[k]; }
+__device__ __forceinline__ uint32_t load_orig(const uint32_t* p, int k) { return load_orig_word(p, k) & kOrigIdMask; }
 
 // A pointer every lane holds the same value of, moved to scalar registers.
 template <class T>
@@ -227,9 +230,11 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
   A.nodes = A.tests = 0;
 }
 
-// Outcome of a finished segment.
+// Outcome of a finished segment.  kOutHitLeft: a hit whose outgoing segment
+// cannot hit anything (the mesh lies on the other side of the triangle's
+// plane), so that segment is counted and the particle escapes untraced.
 // (names distinct from the scalar-slot indices kMissed, kEscaped, kCapped)
-enum Outcome : int { kOutGoOn = 0, kOutMissed = 1, kOutEscaped = 2, kOutCapped = 3 };
+enum Outcome : int { kOutGoOn = 0, kOutMissed = 1, kOutEscaped = 2, kOutCapped = 3, kOutHitLeft = 4 };
 
 // a7-a9 for a lane whose traversal has ended: re-emission and bookkeeping of
 // the hit, or the particle's exit.  The particle retires unless kOutGoOn.
@@ -245,7 +250,8 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
     return kOutEscaped;
   }
   const TriRec tr = load_tri(tris, k);
-  const uint32_t id = load_orig(orig, k);
+  const uint32_t ow = load_orig_word(orig, k);
+  const uint32_t id = ow & kOrigIdMask;
   const float px = s.b0 * tr.v0x + s.b1 * tr.v1x + s.b2 * tr.v2x;
   const float py = s.b0 * tr.v0y + s.b1 * tr.v1y + s.b2 * tr.v2y;
   const float pz = s.b0 * tr.v0z + s.b1 * tr.v1z + s.b2 * tr.v2z;
@@ -274,15 +280,18 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
   L.ox = px + eps * tr.nx; L.oy = py + eps * tr.ny; L.oz = pz + eps * tr.nz;
   L.wx = nwx; L.wy = nwy; L.wz = nwz;
   L.prev = k;
-  return L.hits >= q.rmax ? kOutCapped : kOutGoOn;
+  if (L.hits >= q.rmax) return kOutCapped;
+  // the emission side is empty of mesh points (see support_kernel)
+  const bool clear = side > 0.0f ? (ow >> 30) & 1u : (ow >> 31) & 1u;
+  return clear ? kOutHitLeft : kOutGoOn;
 }
 
 // Event counts of a lane whose segment ended with outcome `out`.
 __device__ __forceinline__ void count_outcome(Acc& A, int out, bool hit) {
-  ++A.segs;
+  A.segs += out == kOutHitLeft ? 2u : 1u;
   A.hits += hit ? 1u : 0u;
   A.missed += out == kOutMissed ? 1u : 0u;
-  A.escaped += out == kOutEscaped ? 1u : 0u;
+  A.escaped += (out == kOutEscaped || out == kOutHitLeft) ? 1u : 0u;
   A.capped += out == kOutCapped ? 1u : 0u;
   A.rays += out != kOutGoOn ? 1u : 0u;
 }

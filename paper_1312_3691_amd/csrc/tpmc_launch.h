@@ -54,6 +54,10 @@ void zero_i64(long long* p, uint64_t n, hipStream_t st);
 void zero_u32(uint32_t* p, uint64_t n, hipStream_t st);
 
 size_t bvh_scratch_bytes(uint64_t nt);
+// Supporting-plane flags in bits 30 / 31 of orig[] (after build_bvh; see tpmc_bvh.hip).
+void mark_support(const float* d_xyz, uint64_t nv, const TriRec* d_tris, uint64_t nt, uint32_t* d_orig,
+                  hipStream_t st);
+constexpr uint32_t kOrigIdMask = 0x3FFFFFFFu;  // orig[] bits 0..29: original triangle index
 hipError_t build_bvh(const float* d_xyz, const uint32_t* d_tri, uint64_t nt, const float box_lo[3],
                      const float box_hi[3], void* scratch, Node* d_nodes, TriRec* d_tris, uint32_t* d_orig,
                      uint32_t* h_depth, hipStream_t st);

@@ -159,6 +159,22 @@ def test_concave_satellite_parity(ctx, T):
     assert abs(g["hits"] - o["hits"]) <= 0.001 * o["hits"] + 3
 
 
+@pytest.mark.parametrize("flow", [(0.0, 0.0, -1.0), (0.6, 0.0, 0.8)], ids=["into_cup", "onto_back"])
+def test_concave_cup_multibounce_parity(ctx, T, flow):
+    """Hemispherical cup, diffuse: particles entering the cup bounce many times
+    (its inner faces do not bound the mesh), particles meeting the convex back
+    leave at once (those faces do) -- both sides of the same triangles."""
+    V, Tr = I.hemisphere_cup(10, 24)
+    q = I.query(q=I.quat_for_flow(flow), S=5.0, alpha=1.0, n=20_011, seed=17, max_reflections=16)
+    g, o = _compare(ctx, T, V, Tr, q, cd_rel=3e-4, tri_tol=1e-3)
+    if flow[2] < 0:  # into the cup: about two hits per particle that hits (oracle: 1.98)
+        assert g["hits"] > 1.5 * (g["rays"] - g["missed"])
+    else:  # onto the back: every particle that hits leaves after one hit
+        assert g["hits"] == g["rays"] - g["missed"]
+    assert abs(g["hits"] - o["hits"]) <= 0.001 * o["hits"] + 3
+    assert abs(g["segments"] - o["segments"]) <= 0.001 * o["segments"] + 3
+
+
 def test_edge_cases(ctx, T):
     """N = 1, a single-triangle mesh, max_reflections = 1, S = 0."""
     V, Tr = I.plate()
