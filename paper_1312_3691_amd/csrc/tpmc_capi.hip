@@ -562,8 +562,10 @@ extern "C" tpmc_status tpmc_particles_planes(tpmc_particles p, float* dev_planes
   return TPMC_OK;
 }
 
+// Plain trace grid: at least four particles per lane (so that lanes whose
+// particle retires have another to take), at most groups_per_cu per CU.
 static int trace_grid(tpmc_ctx ctx, uint64_t n) {
-  const uint64_t g = (n + kBlock - 1) / kBlock;
+  const uint64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
   const uint64_t cap = (uint64_t)ctx->n_cu * ctx->tune.groups_per_cu;
   return (int)(g < cap ? (g ? g : 1) : cap);
 }
