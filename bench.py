@@ -197,7 +197,7 @@ def tune_for(args, mesh, queries, key="workload"):
         return mesh.ctx.tuning
     from paper_1312_3691_amd import autotune
     t0 = time.perf_counter()
-    best, trials = autotune.tune(mesh, queries, particles=int(args.tune_particles))
+    best, trials = autotune.tune(mesh, queries, particles=int(args.tune_particles) or None)
     log(f"autotune nt={mesh.info['nt']}: {best} ({len(trials)} trials, {time.perf_counter() - t0:.1f} s)")
     return best
 
@@ -432,7 +432,8 @@ def main():
     ap.add_argument("--fifo-requests", type=int, default=600, help="served: requests timed on the plain path")
     ap.add_argument("--tiles-per-step", type=int, default=2048)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (library defaults)")
-    ap.add_argument("--tune-particles", type=float, default=2e7, help="particles per autotuner trial")
+    ap.add_argument("--tune-particles", type=float, default=0,
+                    help="particles per autotuner trial (default 0: the whole workload)")
     ap.add_argument("--tuning", default=None, metavar="JSON",
                     help="fixed settings instead of the autotuner: a bench line's \"tuning\" object, "
                          "or a file holding a bench line")

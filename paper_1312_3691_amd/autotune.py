@@ -8,9 +8,11 @@ a workgroup claims) and groups_per_cu (persistent workgroups per compute unit)
 its own counter-based stream, and all sums are exact integers, so every
 setting returns bit-identical results.  The best setting depends on the mesh
 (tree depth, hit rate) and on the query mix, so it is measured: a coordinate
-search over the candidate values on a reduced sample of the caller's own
-workload (the same queries with fewer particles), each candidate timed with
-device events around replays of its launch.
+search over the candidate values on the caller's own workload, each candidate
+timed with device events around replays of its launch.  By default the whole
+workload is timed: in a shorter launch the tail (the last tiles finishing
+while most workgroups idle) weighs more and favours smaller tiles than a full
+launch does.
 
 The search logic (`coordinate_search`) is plain Python over a cost function,
 so it is tested without a GPU; `tune` supplies the cost from the device.
@@ -78,18 +80,19 @@ def sample_queries(queries: Sequence[dict], particles: int) -> List[dict]:
     return [dict(q, n=min(int(q["n"]), max(4096, int(q["n"] * f)))) for q in queries]
 
 
-def tune(mesh, queries: Sequence[dict], particles: int = 20_000_000, reps: int = 2,
+def tune(mesh, queries: Sequence[dict], particles: int = None, reps: int = 1,
          check_results: bool = True) -> Tuple[Dict[str, int], List[Trial]]:
-    """Measure the batched launch of `queries` (reduced to about `particles`)
-    on `mesh` under candidate tunings, set the fastest on the mesh's context
-    and return it with every trial.  With check_results, every candidate's
-    results must equal the first one's bit for bit (TpmcError otherwise)."""
+    """Measure the batched launch of `queries` (reduced to about `particles`
+    when given) on `mesh` under candidate tunings, set the fastest on the
+    mesh's context and return it with every trial.  With check_results, every
+    candidate's results must equal the first one's bit for bit (TpmcError
+    otherwise)."""
     import torch
 
     from . import tpmc
 
     ctx = mesh.ctx
-    sample = sample_queries(queries, particles)
+    sample = [dict(q) for q in queries] if particles is None else sample_queries(queries, particles)
     ref: List = []
 
     def cost(t: Dict[str, int]) -> float:
