@@ -68,10 +68,10 @@ __device__ __forceinline__ float unif32(uint32_t k) { return ((float)(k >> 9) + 
 // and one erfc: the alternative forms below are selected values, not calls.
 //
 // Mixed precision: the iterations that only approach the root run in FP32
-// (cheap exp / erfc) until a step is below 1e-5; then FP64 Halley steps take
-// over from there and end after a step below 1e-5, which by the cubic
-// convergence leaves an error far below the FP64 resolution of the result
-// (usually one FP64 evaluation).  The result is an FP64 root either way; FP32
+// (cheap exp / erfc) until a step is below 1e-3 (by the cubic convergence the
+// error after such a step is near 1e-9); then FP64 Halley steps take over and
+// end after a step below 1e-5, which leaves an error far below the FP64
+// resolution of the result (usually one FP64 evaluation).  The result is an FP64 root either way; FP32
 // only chooses where the FP64 iteration starts.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG, double& d2G) {
@@ -142,7 +142,7 @@ __device__ inline double sample_latitude(const QueryDev& q, double u) {
     float G, dG, d2G;
     latitude_G32(c, xf, G, dG, d2G);
     const float dx = halley_step(xf, G - tf, dG, d2G, lof, hif);
-    if (dx <= 1e-5f || hif - lof <= 1e-5f) break;
+    if (dx <= 1e-3f || hif - lof <= 1e-3f) break;
   }
   double x = (double)xf;
   double lo = -1.0, hi = 1.0;
@@ -222,7 +222,7 @@ __device__ inline double sample_normal_speed(double s, double u) {
       float F, dF, d2F;
       normal_speed_F32(sf, es2, erfs, erfcs, erfcms, xf, F, dF, d2F);
       const float dx = halley_step(xf, F - tf, dF, d2F, lof, hif);
-      if (dx <= 1e-5f * xf || hif - lof <= 1e-5f * xf) break;
+      if (dx <= 1e-3f * xf || hif - lof <= 1e-3f * xf) break;
     }
   }
   double x = (double)xf;
