@@ -105,7 +105,9 @@ const char* tpmc_last_error(void);
 int tpmc_abi_version(void);
 
 /* Context on HIP device `device` issuing work on `hip_stream` (a hipStream_t;
- * NULL = the null stream).  Reads device properties; allocates nothing. */
+ * NULL = the null stream).  Reads device properties; allocates nothing.  The
+ * first context on a device also fills a small table in the library's code
+ * object (starting points of the normal-speed solve, one kernel, synchronised). */
 tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out);
 tpmc_status tpmc_set_stream(tpmc_ctx ctx, void* hip_stream);
 void tpmc_destroy_ctx(tpmc_ctx ctx);

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/tpmc.h"
@@ -339,6 +340,18 @@ extern "C" tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out) 
   HIP_TRY(hipSetDevice(device));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, device));
+  {
+    // the seeding start table lives in the code object of each device; fill it once
+    static std::mutex mu;
+    static std::vector<char> ready;
+    std::lock_guard<std::mutex> lock(mu);
+    if (ready.size() < (size_t)count) ready.resize(count, 0);
+    if (!ready[device]) {
+      hipError_t e = init_seed_tables(static_cast<hipStream_t>(hip_stream));
+      if (e != hipSuccess) return fail(TPMC_E_DEVICE, "seeding tables: %s", hipGetErrorString(e));
+      ready[device] = 1;
+    }
+  }
   tpmc_ctx c = new (std::nothrow) tpmc_ctx_s;
   if (!c) return fail(TPMC_E_INVALID, "out of host memory");
   c->device = device;

@@ -200,18 +200,42 @@ __device__ __forceinline__ void normal_speed_F32(float s, float es2, float erfs,
   d2F = 2.0f * ea * (1.0f - 2.0f * x * a);
 }
 
-__device__ inline double sample_normal_speed(double s, double u) {
+// Starting points of the normal-speed solve: a table of the root x of
+// F(x | s) = u chi(s) over s in [kVnS0, kVnS0 + (kVnNS - 1) kVnDS] and the logit
+// t = ln(u / (1 - u)) in [kVnT0, kVnT0 + (kVnNT - 1) kVnDT], bilinear in (s, t).
+// The law depends on s alone, so one table serves every query; it is filled
+// once per device by FP64 bisection (vn_table_kernel).  It only chooses where
+// the iteration starts.
+constexpr int kVnNS = 41, kVnNT = 129;
+constexpr float kVnS0 = -4.0f, kVnDS = 0.25f, kVnT0 = -24.0f, kVnDT = 0.375f;
+
+__device__ __forceinline__ float normal_speed_start(const float* __restrict__ tab, double s, double u) {
+  const float sf = (float)s;
+  if (sf >= kVnS0 && sf <= kVnS0 + (kVnNS - 1) * kVnDS) {
+    const float t = logf((float)u) - logf((float)(1.0 - u));
+    const float fs = (sf - kVnS0) * (1.0f / kVnDS);
+    const float ft = fminf(fmaxf((t - kVnT0) * (1.0f / kVnDT), 0.0f), (float)(kVnNT - 1));
+    const int i = min((int)fs, kVnNS - 2), j = min((int)ft, kVnNT - 2);
+    const float a = fs - (float)i, b = ft - (float)j;
+    const float* r0 = tab + i * kVnNT + j;
+    const float* r1 = r0 + kVnNT;
+    return (1.0f - a) * ((1.0f - b) * r0[0] + b * r0[1]) + a * ((1.0f - b) * r1[0] + b * r1[1]);
+  }
+  // outside the table: near-Gaussian about s for large s, the Rayleigh law otherwise
+  const float uf = (float)u;
+  return sf > 1.0f ? sf + 0.5f / sf + erfinvf(2.0f * uf - 1.0f) : sqrtf(-log1pf(-uf));
+}
+
+__device__ inline double sample_normal_speed(const float* __restrict__ tab, double s, double u) {
   const NormalSpeedConsts k = normal_speed_consts(s);
   const double target = u * k.chi;
   // The root lies below max(s, 0) + 7: the upper tail there is below e^{-49},
   // far under the smallest 1 - u the variates produce (2^-33).
   const double hi0 = (s > 0.0 ? s : 0.0) + 7.0;
-  // FP32 approach from a near-Gaussian point about s for s > 1, the Rayleigh
-  // law (exact at s = 0) otherwise.  Below s = -9 the FP32 density underflows;
-  // such s are never drawn in practice, and FP64 then starts at the guess.
-  const float sf = (float)s, uf = (float)u;
-  float xf = sf > 1.0f ? sf + 0.5f / sf + erfinvf(2.0f * uf - 1.0f)
-                       : sqrtf(-log1pf(-uf)) + (sf > 0.0f ? 0.5f * sf : 0.0f);
+  // FP32 approach from the tabulated start.  Below s = -9 the FP32 density
+  // underflows; such s are never drawn in practice, and FP64 then starts there.
+  const float sf = (float)s;
+  float xf = normal_speed_start(tab, s, u);
   float lof = 0.0f, hif = (float)hi0;
   if (!(xf > lof && xf < hif)) xf = 0.5f * (lof + hif);
   if (s > -9.0) {
@@ -239,7 +263,8 @@ __device__ inline double sample_normal_speed(double s, double u) {
 }
 
 // One seeded particle (Sec. III.A.1-3): position on the CV and velocity, FP64.
-__device__ inline void seed_particle(const QueryDev& q, uint64_t pid, double x[3], double w[3]) {
+__device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ vn_tab, uint64_t pid, double x[3],
+                                     double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
   const double mu = sample_latitude(q, unif64(r0.a));
@@ -250,7 +275,7 @@ __device__ inline void seed_particle(const QueryDev& q, uint64_t pid, double x[3
   // t1 = cos(phi) U + mu c (unit, along the tangential part of U); t2 = t1 x n = -d,
   // d = -sin(th) e1 + cos(th) e2.  x = c0 - r n.
   const double s_n = q.S * mu;
-  const double wn = sample_normal_speed(s_n, unif64(r0.c));
+  const double wn = sample_normal_speed(vn_tab, s_n, unif64(r0.c));
   const double rad = sqrt(-2.0 * log(unif64(r0.d)));
   double sb, cb;
   sincospi(2.0 * unif64(r1.a), &sb, &cb);

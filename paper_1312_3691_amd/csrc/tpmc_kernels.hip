@@ -33,6 +33,29 @@ int grid_for(uint64_t n, int cap) {
 // ---------------------------------------------------------------------------
 // a2-a4: seeding
 // ---------------------------------------------------------------------------
+// Starting points of the normal-speed solve (normal_speed_start); part of the
+// code object, filled once per device by vn_table_kernel.
+__device__ float g_vn_start[kVnNS * kVnNT];
+
+__global__ void vn_table_kernel(float* __restrict__ tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kVnNS * kVnNT) return;
+  const double s = (double)kVnS0 + (double)(i / kVnNT) * (double)kVnDS;
+  const double t = (double)kVnT0 + (double)(i % kVnNT) * (double)kVnDT;
+  const double u = 1.0 / (1.0 + exp(-t));
+  const NormalSpeedConsts k = normal_speed_consts(s);
+  const double target = u * k.chi;
+  double lo = 0.0, hi = (s > 0.0 ? s : 0.0) + 8.0;
+  for (int it = 0; it < 80; ++it) {
+    const double m = 0.5 * (lo + hi);
+    double F, dF, d2F;
+    normal_speed_F(k, m, F, dF, d2F);
+    if (F < target) lo = m;
+    else hi = m;
+  }
+  tab[i] = (float)(0.5 * (lo + hi));
+}
+
 __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict__ qp, uint64_t n,
                                                       float* __restrict__ x0, float* __restrict__ x1,
                                                       float* __restrict__ x2, float* __restrict__ w0,
@@ -41,7 +64,7 @@ __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double x[3], w[3];
-    seed_particle(q, i, x, w);
+    seed_particle(q, g_vn_start, i, x, w);
     x0[i] = (float)x[0];
     x1[i] = (float)x[1];
     x2[i] = (float)x[2];
@@ -630,7 +653,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               const uint64_t pid = base + lane;
               if (pid < p_end) {
                 double x[3], w[3];
-                seed_particle(q, pid, x, w);
+                seed_particle(q, g_vn_start, pid, x, w);
                 qbuf[wave][0][lane] = (float)x[0];
                 qbuf[wave][1][lane] = (float)x[1];
                 qbuf[wave][2][lane] = (float)x[2];
@@ -807,6 +830,15 @@ void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t
 }
 
 }  // namespace
+
+hipError_t init_seed_tables(hipStream_t st) {
+  float* tab = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&tab, HIP_SYMBOL(g_vn_start));
+  if (e != hipSuccess) return e;
+  vn_table_kernel<<<(kVnNS * kVnNT + 255) / 256, 256, 0, st>>>(tab);
+  e = hipGetLastError();
+  return e != hipSuccess ? e : hipStreamSynchronize(st);
+}
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st) {
   if (n) zero_i64_kernel<<<grid_for(n, 4096), kBlock, 0, st>>>(p, n);

@@ -51,6 +51,8 @@ struct BatchArgs {
 };
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
+// Fills the seeding start table of the current device (once per device).
+hipError_t init_seed_tables(hipStream_t st);
 void zero_u32(uint32_t* p, uint64_t n, hipStream_t st);
 
 size_t bvh_scratch_bytes(uint64_t nt);
