@@ -96,6 +96,11 @@ __device__ __forceinline__ TriRec load_tri(const TriRec* p, int k) {
 __device__ __forceinline__ uint32_t load_orig_word(const uint32_t* p, int k) { return ((gptr<uint32_t>)p)[k]; }
 __device__ __forceinline__ uint32_t load_orig(const uint32_t* p, int k) { return load_orig_word(p, k) & kOrigIdMask; }
 
+// Mask of the lanes where p holds.  The builtin takes the comparison's lane
+// mask as it is; __ballot(int) first turns it into 0/1 values and compares
+// them again.
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 // A pointer every lane holds the same value of, moved to scalar registers.
 template <class T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
@@ -454,15 +459,15 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
   }
   make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
   uint32_t guard = 0;  // steps since the last service pass (wave-uniform)
-  while (__ballot(L.live) != 0ull) {
-    uint32_t ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
-    if (ntrav < a.refill && __ballot(L.live && s.p0 >= 0) != 0ull) {
+  while (ballot(L.live) != 0ull) {
+    uint32_t ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
+    if (ntrav < a.refill && ballot(L.live && s.p0 >= 0) != 0ull) {
       leaf_phase<COUNT>(a.tris, a.orig, r, L.prev, s, A.tests);
-      ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
+      ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
     }
     if (ntrav < a.refill) {
       const bool fin = L.live && seg_finished(s);
-      if (__ballot(fin) != 0ull) {
+      if (ballot(fin) != 0ull) {
         Hit h;
         h.valid = false;
         int out = kOutGoOn;
@@ -610,16 +615,16 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
     uint64_t q_pid0 = 0;               // particle id of queue slot 0
     for (;;) {
-      uint32_t ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
-      if (ntrav < a.refill && __ballot(L.live && s.p0 >= 0) != 0ull) {
+      uint32_t ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
+      if (ntrav < a.refill && ballot(L.live && s.p0 >= 0) != 0ull) {
         uint32_t n1 = 0;
         leaf_phase<false>(tris, orig, r, L.prev, s, n1);
-        ntrav = (uint32_t)__popcll(__ballot(L.live && seg_traversing(s)));
+        ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
       }
       if (ntrav < a.refill) {
         // serve every lane whose segment has ended
         const bool fin = L.live && seg_finished(s);
-        if (__ballot(fin) != 0ull) {
+        if (ballot(fin) != 0ull) {
           Hit h;
           h.valid = false;
           int out = kOutGoOn;
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             }
           }
         }
-        const uint64_t dead = __ballot(!L.live);
+        const uint64_t dead = ballot(!L.live);
         if (dead != 0ull) {
           if (q_count == 0 && !exhausted) {
             // claim and seed the next (up to) 64 particles, one per lane
@@ -689,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             __builtin_amdgcn_wave_barrier();
           }
         }
-        if (__ballot(L.live) == 0ull) {
+        if (ballot(L.live) == 0ull) {
           if (exhausted && q_count == 0) break;
           continue;  // nothing in flight: claim more next round
         }
