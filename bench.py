@@ -219,7 +219,7 @@ def workload_satellite(args):
     from paper_1312_3691_amd import tpmc
     ctx = tpmc.Context(0)
     V, T = I.satellite(50_000)
-    mesh = ctx.build_mesh(V, T)
+    mesh = ctx.build_mesh(V, T, builder=args.bvh)
     U = (-0.5, 0.0, -math.sqrt(3.0) / 2.0)
     n = int(args.particles_sat)
     q = I.query(q=I.quat_for_flow(U), S=7.0, T_inf=T_INF, T_w=T_W, alpha=0.9, n=n, seed=0, max_reflections=16)
@@ -239,7 +239,7 @@ def workload_satellite(args):
     pr.close()
     _line("particle-surface hits/sec on 1 MI355X (concave satellite)", r["hits"] / dt, "hits/s", dt, args.steps,
           args.warmup, {"workload": f"concave satellite {len(T)} tris, S=7, alpha=0.9, {n} particles, 16 reflections",
-                        "path": "batched persistent launch, graph replay"},
+                        "path": "batched persistent launch, graph replay", "bvh": args.bvh},
           {"CD": r["CD"], "CD_sigma": r["CD_sigma"], "hits_per_particle": r["hits"] / n,
            "segments_per_s": r["segments"] / dt, "capped": r["capped"], "bvh_depth": mesh.info["depth"],
            "tuning": tuning,
@@ -255,7 +255,7 @@ def workload_sweep(args):
     from paper_1312_3691_amd import tpmc
     ctx = tpmc.Context(0)
     V, T = I.satellite(50_000)
-    mesh = ctx.build_mesh(V, T)
+    mesh = ctx.build_mesh(V, T, builder=args.bvh)
     nq = 1024
     quats = I.random_quats(nq, 1)
     S = 2.0 + 8.0 * np.random.default_rng(1).random(nq)
@@ -290,7 +290,7 @@ def workload_sweep(args):
     _line("particle-surface hits/sec on 1 MI355X (batched attitude sweep)", hits / dt, "hits/s", dt, args.steps,
           args.warmup, {"workload": f"satellite {len(T)} tris, {nq} attitudes x S~U[2,10], "
                                     f"{int(args.particles_sweep)} particles each, per-query totals",
-                        "path": "one persistent graph-replayed launch"},
+                        "path": "one persistent graph-replayed launch", "bvh": args.bvh},
           {"plain_path": {"hits_per_s": p_hits / pdt, "queries_timed": k, "query_ms_p50": float(np.percentile(lat, 50)),
                           "query_ms_p99": float(np.percentile(lat, 99))},
            "batched_over_plain": (hits / dt) / (p_hits / pdt), "first_queries_equal_plain": bool(same),
@@ -313,7 +313,7 @@ def workload_served(args):
     from paper_1312_3691_amd.serve import GpuExecutor, Scheduler
     ctx = tpmc.Context(0)
     sizes = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
-    meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i)) for i, (k, v) in enumerate(sizes.items())}
+    meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i), builder=args.bvh) for i, (k, v) in enumerate(sizes.items())}
     rng = np.random.default_rng(7)
     n_warm, n_meas = int(args.warm), int(args.requests)
     n_req = n_warm + n_meas
@@ -404,7 +404,8 @@ def workload_served(args):
           n_meas / sat_rate, 1, n_warm,
           {"workload": f"{n_warm} + {n_meas} requests over satellites {list(sizes.values())} tris, N log-uniform "
                        f"1e5-1e7, S~U[2,10], alpha=0.9, per-triangle tallies", "slots": max_slots,
-           "hbm_budget_gb": args.hbm_budget_gb, "path": "continuous batching, one persistent launch per step"},
+           "hbm_budget_gb": args.hbm_budget_gb, "path": "continuous batching, one persistent launch per step",
+           "bvh": args.bvh},
           {"saturation": sat, "loads": loads, "query_ms_p50": loads["0.8"]["p50_ms"],
            "query_ms_p99": loads["0.8"]["p99_ms"], "fifo_plain_path": fifo, "served_equals_solo": bool(same),
            "tuning": tuning})
@@ -431,6 +432,7 @@ def main():
     ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="served: per-request tally budget")
     ap.add_argument("--fifo-requests", type=int, default=600, help="served: requests timed on the plain path")
     ap.add_argument("--tiles-per-step", type=int, default=2048)
+    ap.add_argument("--bvh", default="sah", choices=["sah", "lbvh"], help="BVH builder (results do not depend on it)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (library defaults)")
     ap.add_argument("--tune-particles", type=float, default=0,
                     help="particles per autotuner trial (default 0: the whole workload)")
@@ -459,7 +461,7 @@ def main():
     ctx = tpmc.Context(0)
     mm = meshes()
     cl = cases(args.particles)
-    dev_mesh = {k: ctx.build_mesh(*v) for k, v in mm.items()}
+    dev_mesh = {k: ctx.build_mesh(*v, builder=args.bvh) for k, v in mm.items()}
     batches, tunings = {}, {}
     for kind in ("plate", "cylinder"):
         qs = [c["query"] for c in cl if c["kind"] == kind]
@@ -525,6 +527,7 @@ def main():
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s",
                 "frac": achieved / ALU_PEAK, "traffic": traffic,
                 "kernel": "batch_kernel (seed + trace + tally fused)", "kernel_ms_per_step": launch_s * 1e3,
+                "launch_ms": kern_ms,
                 "work_per_step": {"particles": particles, "segments": segments, "hits": hits,
                                   "node_visits_per_segment": V_seg, "triangle_tests_per_segment": T_seg,
                                   "alg_lane_ops": ops}}
@@ -583,7 +586,7 @@ def main():
                        "meshes": "plate 2 tris, capped cylinder 256 tris", "S": [1, 3, 8],
                        "accommodation": [0.0, 1.0], "angles_deg": list(range(0, 91, 10)),
                        "T_inf_K": T_INF, "T_w_K": T_W, "particles_per_case": args.particles,
-                       "path": "batched persistent launch per mesh, HIP graph replay"},
+                       "path": "batched persistent launch per mesh, HIP graph replay", "bvh": args.bvh},
             "query_ms_p50": plain["query_ms_p50"] if plain else None,
             "query_ms_p99": plain["query_ms_p99"] if plain else None,
             "segments_per_s": segments / dt, "particles_per_s": particles / dt,

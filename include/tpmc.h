@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 2
+#define TPMC_ABI_VERSION 3
 
 typedef enum {
   TPMC_OK = 0,
@@ -99,6 +99,8 @@ typedef struct {
   double box_lo[3], box_hi[3];
   double sphere_center[3], sphere_radius; /* default control volume */
   uint64_t device_bytes; /* resident BVH + triangle records */
+  uint32_t builder;      /* tpmc_bvh_builder the hierarchy was built with */
+  uint32_t reserved;     /* 0 */
 } tpmc_mesh_info;
 
 const char* tpmc_last_error(void);
@@ -133,17 +135,31 @@ typedef struct {
 tpmc_status tpmc_get_tuning(tpmc_ctx ctx, tpmc_tuning* out);
 tpmc_status tpmc_set_tuning(tpmc_ctx ctx, const tpmc_tuning* t);
 
-/* Mesh and its linear BVH (Karras 2012 hierarchy over 30-bit Morton codes of
- * the triangle centroids; closest-hit tracing on a triangulation, Sec. II.A).
+/* Bounding-volume hierarchy builders (both on the device, same node format).
+ * The hierarchy changes only speed: the closest hit does not depend on it
+ * (ties between equal t go to the lower original triangle index), so both
+ * give bit-identical results. */
+typedef enum {
+  TPMC_BVH_SAH = 0,  /* default: top-down, binned surface-area heuristic (32 planes per axis
+                        over the triangle box centres), one workgroup per node and level */
+  TPMC_BVH_LBVH = 1  /* linear BVH: Karras 2012 hierarchy over 30-bit Morton codes of the
+                        triangle centroids (fastest build, more node visits per ray) */
+} tpmc_bvh_builder;
+
+/* Mesh and its BVH (closest-hit tracing on a triangulation, Sec. II.A).
  *   xyz: host float [nv][3], metres, body frame.  tri: host uint32 [nt][3].
  * Triangles are two-sided; zero-area triangles are accepted and never hit.
  * Also marks, per triangle and side, whether the whole mesh lies on the other
  * side of its plane, so that a particle leaving that side provably cannot hit
  * again and escapes without being traced (exact; nt * nv FP64 distance
  * evaluations at build).  nt < 2^30, nv < 2^32.
- * Builds on the device (synchronises); the handle owns its device memory. */
+ * Builds on the device (synchronises); the handle owns its device memory.
+ * tpmc_build_mesh uses TPMC_BVH_SAH; tpmc_build_mesh_ex takes the builder
+ * (TPMC_E_INVALID for any other value). */
 tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
                             tpmc_mesh* out);
+tpmc_status tpmc_build_mesh_ex(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
+                               uint32_t builder, tpmc_mesh* out);
 tpmc_status tpmc_get_mesh_info(tpmc_mesh mesh, tpmc_mesh_info* out);
 void tpmc_destroy_mesh(tpmc_mesh mesh);
 

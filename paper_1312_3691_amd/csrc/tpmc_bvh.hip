@@ -338,6 +338,310 @@ __global__ void single_node_kernel(Node* nodes, const TriRec* tris) {
   nodes[0] = nd;
 }
 
+
+// ---- top-down binned SAH build ----
+//
+// Alternative to the Morton/Karras hierarchy, same node and leaf format.  A
+// node's triangles (a contiguous range of an index array) are split where the
+// surface-area heuristic (cost of a child = its box area x its triangle count)
+// is lowest among kSahBins - 1 planes per axis, planes equally spaced over the
+// range of the triangle box centres; the range is then partitioned stably into
+// the other index array.  One workgroup per node, all nodes of one tree level
+// per launch.  Internal node ids follow Karras's rule, valid for any binary
+// tree over ordered leaves: the root is 0, an internal left child takes the
+// position of its last triangle and an internal right child that of its first,
+// so ids are known before the children are processed and the build is
+// deterministic.  Below level kSahMaxLevel (or when every centre coincides)
+// ranges are halved by position, so no leaf lies deeper than
+// kSahMaxLevel + 30 <= 64 for nt < 2^30.
+constexpr int kSahBins = 32;
+constexpr uint32_t kSahMaxLevel = 32;
+
+struct SahTask {
+  uint32_t a, b, id;  // triangle positions [a, b] (b > a), node id
+  int32_t parent;
+};
+
+// Order-preserving map of finite floats to int32 (for LDS integer min / max).
+__device__ __forceinline__ int f2o(float f) {
+  const int i = __float_as_int(f);
+  return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__device__ __forceinline__ float o2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7FFFFFFF); }
+
+__device__ __forceinline__ int sah_bin(float c, float cmin, float scale) {
+  return min(kSahBins - 1, (int)((c - cmin) * scale));
+}
+
+__device__ __forceinline__ float box_area(float lx, float ly, float lz, float hx, float hy, float hz) {
+  const float ex = hx - lx, ey = hy - ly, ez = hz - lz;
+  return ex * ey + ey * ez + ez * ex;
+}
+
+// Triangle boxes (exact min / max of the FP32 vertices); the box centre is the
+// binning key.
+__global__ void prim_box_kernel(const float* __restrict__ xyz, const uint32_t* __restrict__ tri, uint32_t nt,
+                                float4* __restrict__ plo, float4* __restrict__ phi, uint32_t* __restrict__ idx) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  const uint32_t a = tri[3 * i], b = tri[3 * i + 1], c = tri[3 * i + 2];
+  float lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float x = xyz[3 * a + k], y = xyz[3 * b + k], z = xyz[3 * c + k];
+    lo[k] = fminf(fminf(x, y), z);
+    hi[k] = fmaxf(fmaxf(x, y), z);
+  }
+  plo[i] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+  phi[i] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+  idx[i] = i;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void sah_level_kernel(const float4* __restrict__ plo,
+                                                          const float4* __restrict__ phi,
+                                                          const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                          uint32_t* __restrict__ order, const SahTask* __restrict__ tasks,
+                                                          uint32_t ntasks, SahTask* __restrict__ next,
+                                                          uint32_t* __restrict__ nnext, Node* __restrict__ nodes,
+                                                          uint32_t level, uint32_t* __restrict__ err) {
+  __shared__ int s_cb[6];  // centre bounds: lo xyz, hi xyz (ordered ints)
+  __shared__ uint32_t s_cnt[3][kSahBins];
+  __shared__ int s_lo[3][kSahBins][3], s_hi[3][kSahBins][3];
+  __shared__ unsigned long long s_best;
+  __shared__ int s_box[2][6];  // child boxes: lo xyz, hi xyz
+  __shared__ uint32_t s_wl[kBlock / 64], s_wv[kBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned long long lt_mask = (1ull << lane) - 1ull;
+  constexpr float kInf = __builtin_inff();
+
+  for (uint32_t ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+    const SahTask T = tasks[ti];
+    const uint32_t a = T.a, b = T.b, m = b - a + 1;
+
+    // 1. bounds of the box centres
+    if (tid < 6) s_cb[tid] = tid < 3 ? f2o(kInf) : f2o(-kInf);
+    if (tid < 12) s_box[tid / 6][tid % 6] = tid % 6 < 3 ? f2o(kInf) : f2o(-kInf);
+    for (int e = tid; e < 3 * kSahBins; e += kBlock) {
+      (&s_cnt[0][0])[e] = 0u;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        (&s_lo[0][0][0])[3 * e + q] = f2o(kInf);
+        (&s_hi[0][0][0])[3 * e + q] = f2o(-kInf);
+      }
+    }
+    if (tid == 0) s_best = ~0ull;
+    float cl[3] = {kInf, kInf, kInf}, ch[3] = {-kInf, -kInf, -kInf};
+    for (uint32_t i = a + tid; i <= b; i += kBlock) {
+      const uint32_t p = src[i];
+      const float4 lo = plo[p], hi = phi[p];
+      const float c[3] = {0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z)};
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        cl[k] = fminf(cl[k], c[k]);
+        ch[k] = fmaxf(ch[k], c[k]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cl[k] = wave_min(cl[k]);
+      ch[k] = wave_max(ch[k]);
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        atomicMin(&s_cb[k], f2o(cl[k]));
+        atomicMax(&s_cb[3 + k], f2o(ch[k]));
+      }
+    }
+    __syncthreads();
+    float cmin[3], scale[3];
+    bool use[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      cmin[k] = o2f(s_cb[k]);
+      const float ext = o2f(s_cb[3 + k]) - cmin[k];
+      scale[k] = (float)kSahBins / ext;
+      use[k] = level < kSahMaxLevel && ext > 0.0f && scale[k] < kInf;
+    }
+
+    // 2. bins of every usable axis: count and box union
+    if (use[0] || use[1] || use[2]) {
+      for (uint32_t i = a + tid; i <= b; i += kBlock) {
+        const uint32_t p = src[i];
+        const float4 lo = plo[p], hi = phi[p];
+        const float c[3] = {0.5f * (lo.x + hi.x), 0.5f * (lo.y + hi.y), 0.5f * (lo.z + hi.z)};
+        const int ilo[3] = {f2o(lo.x), f2o(lo.y), f2o(lo.z)}, ihi[3] = {f2o(hi.x), f2o(hi.y), f2o(hi.z)};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (!use[k]) continue;
+          const int bin = sah_bin(c[k], cmin[k], scale[k]);
+          atomicAdd(&s_cnt[k][bin], 1u);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            atomicMin(&s_lo[k][bin][q], ilo[q]);
+            atomicMax(&s_hi[k][bin][q], ihi[q]);
+          }
+        }
+      }
+      __syncthreads();
+      // 3. cost of every plane (axis k, left = bins below s); lowest (cost, k, s) wins
+      if (tid < 3 * kSahBins) {
+        const int k = tid / kSahBins, s = tid % kSahBins;
+        if (s > 0 && use[k]) {
+          uint32_t nl = 0, nr = 0;
+          int L[6] = {f2o(kInf), f2o(kInf), f2o(kInf), f2o(-kInf), f2o(-kInf), f2o(-kInf)};
+          int R[6] = {L[0], L[1], L[2], L[3], L[4], L[5]};
+          for (int j = 0; j < s; ++j) {
+            nl += s_cnt[k][j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              L[q] = min(L[q], s_lo[k][j][q]);
+              L[3 + q] = max(L[3 + q], s_hi[k][j][q]);
+            }
+          }
+          for (int j = s; j < kSahBins; ++j) {
+            nr += s_cnt[k][j];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              R[q] = min(R[q], s_lo[k][j][q]);
+              R[3 + q] = max(R[3 + q], s_hi[k][j][q]);
+            }
+          }
+          if (nl > 0 && nr > 0) {
+            const float cost =
+                box_area(o2f(L[0]), o2f(L[1]), o2f(L[2]), o2f(L[3]), o2f(L[4]), o2f(L[5])) * (float)nl +
+                box_area(o2f(R[0]), o2f(R[1]), o2f(R[2]), o2f(R[3]), o2f(R[4]), o2f(R[5])) * (float)nr;
+            atomicMin(&s_best, ((unsigned long long)__float_as_uint(cost) << 32) | (unsigned)tid);
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const unsigned long long best = s_best;
+    const bool halve = best == ~0ull;
+    int ax = 0, split = 0;
+    uint32_t nl = m / 2;
+    if (!halve) {
+      const int t = (int)(best & 0xFFFFFFFFull);
+      ax = t / kSahBins;
+      split = t % kSahBins;
+      nl = 0;
+      for (int j = 0; j < split; ++j) nl += s_cnt[ax][j];
+    }
+
+    // 4. stable partition into dst[a..b]: left part first; child boxes
+    float bl[2][3] = {{kInf, kInf, kInf}, {kInf, kInf, kInf}};
+    float bh[2][3] = {{-kInf, -kInf, -kInf}, {-kInf, -kInf, -kInf}};
+    uint32_t baseL = 0, baseR = 0;
+    for (uint32_t c0 = a; c0 <= b; c0 += kBlock) {
+      const uint32_t i = c0 + tid;
+      const bool valid = i <= b;
+      uint32_t p = 0;
+      bool left = false;
+      if (valid) {
+        p = src[i];
+        const float4 lo = plo[p], hi = phi[p];
+        if (halve) {
+          left = i - a < nl;
+        } else {
+          const float c = ax == 0 ? 0.5f * (lo.x + hi.x) : ax == 1 ? 0.5f * (lo.y + hi.y) : 0.5f * (lo.z + hi.z);
+          left = sah_bin(c, cmin[ax], scale[ax]) < split;
+        }
+        const int side = left ? 0 : 1;
+        bl[side][0] = fminf(bl[side][0], lo.x); bl[side][1] = fminf(bl[side][1], lo.y);
+        bl[side][2] = fminf(bl[side][2], lo.z);
+        bh[side][0] = fmaxf(bh[side][0], hi.x); bh[side][1] = fmaxf(bh[side][1], hi.y);
+        bh[side][2] = fmaxf(bh[side][2], hi.z);
+      }
+      const unsigned long long wl = __ballot(left), wv = __ballot(valid);
+      if (lane == 0) {
+        s_wl[wave] = (uint32_t)__popcll(wl);
+        s_wv[wave] = (uint32_t)__popcll(wv);
+      }
+      __syncthreads();
+      uint32_t offL = 0, offV = 0, totL = 0, totV = 0;
+#pragma unroll
+      for (int w = 0; w < kBlock / 64; ++w) {
+        if (w < wave) {
+          offL += s_wl[w];
+          offV += s_wv[w];
+        }
+        totL += s_wl[w];
+        totV += s_wv[w];
+      }
+      if (valid) {
+        const uint32_t pl = (uint32_t)__popcll(wl & lt_mask), pv = (uint32_t)__popcll(wv & lt_mask);
+        const uint32_t pos = left ? a + baseL + offL + pl : a + nl + baseR + (offV - offL) + (pv - pl);
+        if (pos >= a && pos <= b) {
+          dst[pos] = p;
+          if (left ? nl == 1 : m - nl == 1) order[pos] = p;  // a one-triangle child is a leaf
+        }
+      }
+      baseL += totL;
+      baseR += totV - totL;
+      __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        bl[s][q] = wave_min(bl[s][q]);
+        bh[s][q] = wave_max(bh[s][q]);
+      }
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          atomicMin(&s_box[s][q], f2o(bl[s][q]));
+          atomicMax(&s_box[s][3 + q], f2o(bh[s][q]));
+        }
+      }
+    }
+    __syncthreads();
+
+    // 5. the node, its internal children as tasks of the next level
+    if (tid == 0) {
+      if (baseL != nl) atomicOr(err, 1u);  // partition disagrees with the bin counts
+      const uint32_t nr = m - nl;
+      const int c0 = nl == 1 ? ~(int)a : (int)(a + nl - 1);
+      const int c1 = nr == 1 ? ~(int)b : (int)(a + nl);
+      Node nd;
+      nd.lo0x = o2f(s_box[0][0]); nd.lo0y = o2f(s_box[0][1]); nd.lo0z = o2f(s_box[0][2]);
+      nd.hi0x = o2f(s_box[0][3]); nd.hi0y = o2f(s_box[0][4]); nd.hi0z = o2f(s_box[0][5]);
+      nd.lo1x = o2f(s_box[1][0]); nd.lo1y = o2f(s_box[1][1]); nd.lo1z = o2f(s_box[1][2]);
+      nd.hi1x = o2f(s_box[1][3]); nd.hi1y = o2f(s_box[1][4]); nd.hi1z = o2f(s_box[1][5]);
+      nd.c0 = c0;
+      nd.c1 = c1;
+      nd.parent = T.parent;
+      nd.pad = 0;
+      nodes[T.id] = nd;
+      const uint32_t k = (nl > 1 ? 1u : 0u) + (nr > 1 ? 1u : 0u);
+      if (k) {
+        uint32_t slot = atomicAdd(nnext, k);
+        if (nl > 1) next[slot++] = SahTask{a, a + nl - 1, a + nl - 1, (int32_t)T.id};
+        if (nr > 1) next[slot] = SahTask{a + nl, b, a + nl, (int32_t)T.id};
+      }
+    }
+    __syncthreads();  // LDS is reused by the next task
+  }
+}
+
+__global__ void sah_root_kernel(SahTask* tasks, uint32_t nt) { tasks[0] = SahTask{0u, nt - 1u, 0u, -1}; }
+
 }  // namespace
 
 void mark_support(const float* d_xyz, uint64_t nv, const TriRec* d_tris, uint64_t nt, uint32_t* d_orig,
@@ -399,6 +703,63 @@ hipError_t build_bvh(const float* d_xyz, const uint32_t* d_tri, uint64_t nt64, c
   depth_kernel<<<g, kBlock, 0, st>>>(d_nodes, leaf_parent, nt, depth);
   e = hipMemcpyAsync(h_depth, depth, sizeof(uint32_t), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(st);
+  return e != hipSuccess ? e : hipGetLastError();
+}
+
+size_t sah_scratch_bytes(uint64_t nt) {
+  // prim boxes (2 x 16 B), two index arrays and the leaf order (3 x 4 B), two
+  // task lists of at most nt / 2 + 1 entries (16 B), two counters
+  return nt * (2 * sizeof(float4) + 3 * sizeof(uint32_t)) + 2 * (nt / 2 + 1) * sizeof(SahTask) + 4096;
+}
+
+hipError_t build_bvh_sah(const float* d_xyz, const uint32_t* d_tri, uint64_t nt64, void* scratch, Node* d_nodes,
+                         TriRec* d_tris, uint32_t* d_orig, uint32_t* h_depth, hipStream_t st) {
+  const uint32_t nt = (uint32_t)nt64;
+  char* p = static_cast<char*>(scratch);
+  auto take = [&p](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) & ~size_t(255);
+    return q;
+  };
+  float4* plo = reinterpret_cast<float4*>(take(nt * sizeof(float4)));
+  float4* phi = reinterpret_cast<float4*>(take(nt * sizeof(float4)));
+  uint32_t* idx[2] = {reinterpret_cast<uint32_t*>(take(nt * sizeof(uint32_t))),
+                      reinterpret_cast<uint32_t*>(take(nt * sizeof(uint32_t)))};
+  uint32_t* order = reinterpret_cast<uint32_t*>(take(nt * sizeof(uint32_t)));
+  const size_t ntask = nt / 2 + 1;
+  SahTask* tasks[2] = {reinterpret_cast<SahTask*>(take(ntask * sizeof(SahTask))),
+                       reinterpret_cast<SahTask*>(take(ntask * sizeof(SahTask)))};
+  uint32_t* cnt = reinterpret_cast<uint32_t*>(take(2 * sizeof(uint32_t)));  // next-level tasks, error flag
+  const uint32_t g = (nt + kBlock - 1) / kBlock;
+  hipError_t e;
+  prim_box_kernel<<<g, kBlock, 0, st>>>(d_xyz, d_tri, nt, plo, phi, idx[0]);
+  if (nt == 1) {
+    pack_tris_kernel<<<1, kBlock, 0, st>>>(d_xyz, d_tri, idx[0], 1u, d_tris, d_orig);
+    single_node_kernel<<<1, 1, 0, st>>>(d_nodes, d_tris);
+    *h_depth = 1;
+    e = hipStreamSynchronize(st);
+    return e != hipSuccess ? e : hipGetLastError();
+  }
+  zero_u32(cnt, 2, st);
+  sah_root_kernel<<<1, 1, 0, st>>>(tasks[0], nt);
+  uint32_t ntasks = 1, level = 0, h_cnt[2] = {0u, 0u};
+  while (ntasks > 0) {
+    if (level >= 64) return hipErrorUnknown;  // cannot happen: see kSahMaxLevel
+    zero_u32(cnt, 1, st);
+    const uint32_t grid = ntasks < 2048u ? ntasks : 2048u;
+    sah_level_kernel<<<grid, kBlock, 0, st>>>(plo, phi, idx[level & 1], idx[(level + 1) & 1], order, tasks[level & 1],
+                                              ntasks, tasks[(level + 1) & 1], cnt, d_nodes, level, cnt + 1);
+    e = hipMemcpyAsync(h_cnt, cnt, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (h_cnt[1] != 0u) return hipErrorUnknown;  // partition inconsistent with the bin counts
+    ntasks = h_cnt[0];
+    ++level;
+  }
+  *h_depth = level;  // internal nodes on the longest root-to-leaf path
+  pack_tris_kernel<<<g, kBlock, 0, st>>>(d_xyz, d_tri, order, nt, d_tris, d_orig);
   e = hipStreamSynchronize(st);
   return e != hipSuccess ? e : hipGetLastError();
 }

@@ -59,6 +59,7 @@ struct tpmc_mesh_s {
   tpmc_ctx ctx;
   uint64_t nv, nt;
   uint32_t depth;
+  uint32_t builder;  // tpmc_bvh_builder
   int stack_slots;
   Node* nodes;
   TriRec* tris;
@@ -402,8 +403,15 @@ extern "C" void tpmc_destroy_ctx(tpmc_ctx ctx) {
 
 extern "C" tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt,
                                        tpmc_mesh* out) {
+  return tpmc_build_mesh_ex(ctx, xyz, nv, tri, nt, TPMC_BVH_SAH, out);
+}
+
+extern "C" tpmc_status tpmc_build_mesh_ex(tpmc_ctx ctx, const float* xyz, uint64_t nv, const uint32_t* tri,
+                                          uint64_t nt, uint32_t builder, tpmc_mesh* out) {
   if (!ctx || !out) return fail(TPMC_E_INVALID, "ctx and out must not be NULL");
   *out = nullptr;
+  if (builder != TPMC_BVH_SAH && builder != TPMC_BVH_LBVH)
+    return fail(TPMC_E_INVALID, "unknown BVH builder %u", builder);
   tpmc_status s = tpmc_check_mesh(xyz, nv, tri, nt);
   if (s != TPMC_OK) return s;
   HIP_TRY(hipSetDevice(ctx->device));
@@ -423,7 +431,7 @@ extern "C" tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t 
   void* scratch = nullptr;
   hipError_t e = hipMalloc(&d_xyz, 3 * nv * sizeof(float));
   if (e == hipSuccess) e = hipMalloc(&d_tri, 3 * nt * sizeof(uint32_t));
-  if (e == hipSuccess) e = hipMalloc(&scratch, bvh_scratch_bytes(nt));
+  if (e == hipSuccess) e = hipMalloc(&scratch, builder == TPMC_BVH_SAH ? sah_scratch_bytes(nt) : bvh_scratch_bytes(nt));
   if (e == hipSuccess) e = hipMalloc(&m->nodes, nnodes * sizeof(Node));
   if (e == hipSuccess) e = hipMalloc(&m->tris, nt * sizeof(TriRec));
   if (e == hipSuccess) e = hipMalloc(&m->orig, nt * sizeof(uint32_t));
@@ -433,7 +441,9 @@ extern "C" tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t 
   if (e == hipSuccess) {
     const float lo[3] = {(float)m->lo[0], (float)m->lo[1], (float)m->lo[2]};
     const float hi[3] = {(float)m->hi[0], (float)m->hi[1], (float)m->hi[2]};
-    e = build_bvh(d_xyz, d_tri, nt, lo, hi, scratch, m->nodes, m->tris, m->orig, &depth, ctx->stream);
+    e = builder == TPMC_BVH_SAH
+            ? build_bvh_sah(d_xyz, d_tri, nt, scratch, m->nodes, m->tris, m->orig, &depth, ctx->stream)
+            : build_bvh(d_xyz, d_tri, nt, lo, hi, scratch, m->nodes, m->tris, m->orig, &depth, ctx->stream);
   }
   if (e == hipSuccess) {
     mark_support(d_xyz, nv, m->tris, nt, m->orig, ctx->stream);
@@ -448,6 +458,7 @@ extern "C" tpmc_status tpmc_build_mesh(tpmc_ctx ctx, const float* xyz, uint64_t 
     return fail(TPMC_E_DEVICE, "BVH build: %s", hipGetErrorString(e));
   }
   m->depth = depth;
+  m->builder = builder;
   m->stack_slots = stack_slots_for_depth(depth);
   if (m->stack_slots == 0) {
     tpmc_destroy_mesh(m);
@@ -471,6 +482,8 @@ extern "C" tpmc_status tpmc_get_mesh_info(tpmc_mesh m, tpmc_mesh_info* out) {
   }
   out->sphere_radius = m->r;
   out->device_bytes = m->device_bytes;
+  out->builder = m->builder;
+  out->reserved = 0;
   return TPMC_OK;
 }
 

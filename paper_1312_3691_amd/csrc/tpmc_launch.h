@@ -64,6 +64,11 @@ hipError_t build_bvh(const float* d_xyz, const uint32_t* d_tri, uint64_t nt, con
                      const float box_hi[3], void* scratch, Node* d_nodes, TriRec* d_tris, uint32_t* d_orig,
                      uint32_t* h_depth, hipStream_t st);
 
+// Top-down binned-SAH hierarchy in the same node / leaf format (default builder).
+size_t sah_scratch_bytes(uint64_t nt);
+hipError_t build_bvh_sah(const float* d_xyz, const uint32_t* d_tri, uint64_t nt, void* scratch, Node* d_nodes,
+                         TriRec* d_tris, uint32_t* d_orig, uint32_t* h_depth, hipStream_t st);
+
 int stack_slots_for_depth(uint32_t depth);  // 0 when too deep
 void launch_seed(const QueryDev* d_q, uint64_t n, float* const x[3], float* const w[3], int grid, hipStream_t st);
 void launch_trace(const TraceArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);

@@ -50,7 +50,10 @@ class MeshInfo(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_uint64), ("nt", ctypes.c_uint64), ("depth", ctypes.c_uint32),
                 ("stack_slots", ctypes.c_uint32), ("box_lo", ctypes.c_double * 3), ("box_hi", ctypes.c_double * 3),
                 ("sphere_center", ctypes.c_double * 3), ("sphere_radius", ctypes.c_double),
-                ("device_bytes", ctypes.c_uint64)]
+                ("device_bytes", ctypes.c_uint64), ("builder", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+# BVH builders (tpmc_bvh_builder); results do not depend on the choice
+BUILDERS = {"sah": 0, "lbvh": 1}
 
 
 _vp = ctypes.c_void_p
@@ -74,6 +77,7 @@ _SIGS = {
     "tpmc_set_stream": ([_vp, _vp], ctypes.c_int),
     "tpmc_destroy_ctx": ([_vp], None),
     "tpmc_build_mesh": ([_vp, _fp, _u64, ctypes.POINTER(_u32), _u64, ctypes.POINTER(_vp)], ctypes.c_int),
+    "tpmc_build_mesh_ex": ([_vp, _fp, _u64, ctypes.POINTER(_u32), _u64, _u32, ctypes.POINTER(_vp)], ctypes.c_int),
     "tpmc_get_mesh_info": ([_vp, ctypes.POINTER(MeshInfo)], ctypes.c_int),
     "tpmc_destroy_mesh": ([_vp], None),
     "tpmc_workspace_bytes": ([_vp, _vp, _QP, _u32, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -201,8 +205,8 @@ class Context:
         except Exception:
             pass
 
-    def build_mesh(self, V, T) -> "Mesh":
-        return Mesh(self, V, T)
+    def build_mesh(self, V, T, builder: str = "sah") -> "Mesh":
+        return Mesh(self, V, T, builder)
 
     @property
     def tuning(self) -> dict:
@@ -223,15 +227,18 @@ class Context:
 
 
 class Mesh:
-    """Triangle mesh with its device-resident LBVH."""
+    """Triangle mesh with its device-resident BVH (builder "sah" or "lbvh")."""
 
-    def __init__(self, ctx: Context, V, T):
+    def __init__(self, ctx: Context, V, T, builder: str = "sah"):
         V, T = _mesh_arrays(V, T)
+        if builder not in BUILDERS:
+            raise TpmcError(1, f"unknown BVH builder {builder!r} (one of {sorted(BUILDERS)})")
         self.ctx = ctx
         self.V, self.T = V, T
         h = _vp()
-        _check(_lib.tpmc_build_mesh(ctx._h, V.ctypes.data_as(_fp), V.shape[0],
-                                    T.ctypes.data_as(ctypes.POINTER(_u32)), T.shape[0], ctypes.byref(h)))
+        _check(_lib.tpmc_build_mesh_ex(ctx._h, V.ctypes.data_as(_fp), V.shape[0],
+                                       T.ctypes.data_as(ctypes.POINTER(_u32)), T.shape[0], BUILDERS[builder],
+                                       ctypes.byref(h)))
         self._h = h
         info = MeshInfo()
         _check(_lib.tpmc_get_mesh_info(h, ctypes.byref(info)))

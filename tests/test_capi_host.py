@@ -33,13 +33,15 @@ def test_every_declared_symbol_is_exported(T):
     lib = ctypes.CDLL(T.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.tpmc_abi_version() == 2
+    assert lib.tpmc_abi_version() == 3
 
 
 def test_struct_sizes_match_header(T):
     # tpmc_query: 4+1+2+1 doubles, 2 u64, 2 u32, 4 doubles = 112 bytes
     assert ctypes.sizeof(T.Query) == 8 * 8 + 16 + 8 + 32
     assert ctypes.sizeof(T.Result) == 12 * 8 + 6 * 8
+    # tpmc_mesh_info: 2 u64, 2 u32, 10 doubles, u64, 2 u32 = 120 bytes
+    assert ctypes.sizeof(T.MeshInfo) == 16 + 8 + 80 + 8 + 8
 
 
 def _status(fn):

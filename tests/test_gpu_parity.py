@@ -276,6 +276,56 @@ def test_tuning_does_not_change_results(ctx, T):
     assert ctx.tuning == base
 
 
+def _duplicates(n=64):
+    """n copies of one triangle: every box centre coincides (the SAH build
+    halves such ranges by position) and every hit is an n-way tie."""
+    V = np.array([[0.0, -0.3, -0.2], [0.0, 0.4, -0.1], [0.1, 0.0, 0.35]], np.float32)
+    return V, np.tile(np.arange(3, dtype=np.uint32), (n, 1))
+
+
+@pytest.mark.parametrize("name", ["triangle", "plate", "cylinder", "cup", "icosphere", "satellite", "duplicates"])
+def test_bvh_builders_agree(ctx, T, name):
+    """The SAH and Morton (LBVH) hierarchies give bit-identical results (the
+    closest hit, ties to the lower original index, does not depend on the
+    tree), plain and batched, per-triangle tallies included."""
+    V, Tr = {"triangle": lambda: (np.array([[0, -1, -1], [0, 1, -1], [0, 0, 1]], np.float32),
+                                  np.array([[0, 1, 2]], np.uint32)),
+             "plate": I.plate, "cylinder": I.capped_cylinder, "cup": lambda: I.hemisphere_cup(10, 24),
+             "icosphere": lambda: I.icosphere(2), "satellite": lambda: I.satellite(3000),
+             "duplicates": _duplicates}[name]()
+    qs = [I.query(q=I.quat_for_flow(f), S=S, alpha=a, n=150_001, seed=11 + i)
+          for i, (f, S, a) in enumerate((((1.0, 0.0, 0.0), 3.0, 1.0), ((0.3, -0.5, 0.8), 8.0, 0.0),
+                                         ((0.0, 0.6, -0.8), 1.0, 0.5)))]
+    out = {}
+    for b in ("lbvh", "sah"):
+        mesh = ctx.build_mesh(V, Tr, builder=b)
+        assert mesh.info["builder"] == T.BUILDERS[b]
+        assert mesh.info["depth"] <= mesh.info["stack_slots"]
+        plain, pr = T.run(mesh, qs, A_ref=1.0)
+        tallies = [pr.tally(i) for i in range(len(qs))]
+        pr.close()
+        bt = T.Batch(mesh, qs)
+        batched = bt.launch(use_graph=False).results(A_ref=1.0)
+        bt.close()
+        out[b] = (plain, batched, tallies)
+        mesh.close()
+    (p0, b0, t0), (p1, b1, t1) = out["lbvh"], out["sah"]
+    for ref, got in ((p0, p1), (b0, b1), (p0, b1)):
+        for r, g in zip(ref, got):
+            for k in r:
+                assert np.array_equal(np.asarray(r[k]), np.asarray(g[k])), (name, k)
+    for a, b in zip(t0, t1):
+        assert np.array_equal(a, b), name
+    assert sum(r["hits"] for r in p0) > 0
+    with pytest.raises(T.TpmcError):
+        ctx.build_mesh(V, Tr, builder="octree")
+    h = T._vp()
+    Vc, Tc = np.ascontiguousarray(V, np.float32), np.ascontiguousarray(Tr, np.uint32)
+    assert T._lib.tpmc_build_mesh_ex(ctx._h, Vc.ctypes.data_as(T._fp), Vc.shape[0],
+                                     Tc.ctypes.data_as(T.ctypes.POINTER(T._u32)), Tc.shape[0], 2,
+                                     T.ctypes.byref(h)) == 1
+
+
 def test_batch_graph_replays(ctx, T):
     """Graph replays, with eager work in between, equal the eager launch."""
     import torch
