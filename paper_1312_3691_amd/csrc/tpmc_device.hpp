@@ -127,14 +127,39 @@ __device__ __forceinline__ T halley_step(T& x, T f, T df, T d2f, T& lo, T& hi) {
   return (T)__builtin_inf();
 }
 
-__device__ inline double sample_latitude(const QueryDev& q, double u) {
+// Starting points of the latitude solve: a table of the root mu of
+// G(mu) = u Z(S) over ln S = ln kLatS0 + i kLatDL (S from 0.05 to 10.02) and
+// the logit t = ln(u / (1 - u)) = kLatT0 + j kLatDT, bilinear in (ln S, t).
+// The law depends on S alone, so one table serves every query; rows are
+// spaced in ln S because the root bends fastest in S below S ~ 1.  Filled once
+// per device by FP64 bisection (lat_table_kernel); a bilinear start is within
+// 1e-3 of the root, so one FP32 step usually ends the approach.  Outside the
+// table the start is a blend of the S -> 0 law (uniform mu) and the S -> inf
+// law (density 2 mu).  It only chooses where the iteration starts.
+constexpr int kLatNS = 107, kLatNT = 257;
+constexpr float kLatS0 = 0.05f, kLatDL = 0.05f, kLatT0 = -24.0f, kLatDT = 0.1875f;
+
+__device__ __forceinline__ float latitude_start(const float* __restrict__ tab, float S, double u) {
+  const float fs = logf(S * (1.0f / kLatS0)) * (1.0f / kLatDL);
+  const float uf = (float)u;
+  if (fs >= 0.0f && fs <= (float)(kLatNS - 1)) {
+    const float t = logf(uf) - logf((float)(1.0 - u));
+    const float ft = fminf(fmaxf((t - kLatT0) * (1.0f / kLatDT), 0.0f), (float)(kLatNT - 1));
+    const int i = min((int)fs, kLatNS - 2), j = min((int)ft, kLatNT - 2);
+    const float a = fs - (float)i, b = ft - (float)j;
+    const float* r0 = tab + i * kLatNT + j;
+    const float* r1 = r0 + kLatNT;
+    return (1.0f - a) * ((1.0f - b) * r0[0] + b * r0[1]) + a * ((1.0f - b) * r1[0] + b * r1[1]);
+  }
+  const float wgt = S * S / (1.0f + S * S);
+  return (1.0f - wgt) * (2.0f * uf - 1.0f) + wgt * sqrtf(uf);
+}
+
+__device__ inline double sample_latitude(const QueryDev& q, const float* __restrict__ lat_tab, double u) {
   if (q.s_zero) return 2.0 * u - 1.0;  // S -> 0: g -> cos(phi)/2, mu uniform
   const double target = u * q.Z;
-  // FP32 approach from a point between the S -> 0 law (uniform) and the
-  // S -> inf law (density 2 mu)
   const LatConst32 c{(float)q.S, (float)q.erfS, (float)q.erfcS, (float)q.expmS2, q.S < 0.25};
-  const float uf = (float)u, wgt = c.S * c.S / (1.0f + c.S * c.S);
-  float xf = (1.0f - wgt) * (2.0f * uf - 1.0f) + wgt * sqrtf(uf);
+  float xf = fminf(fmaxf(latitude_start(lat_tab, c.S, u), -1.0f), 1.0f);
   float lof = -1.0f, hif = 1.0f;
   const float tf = (float)target;
 #pragma unroll 1
@@ -263,11 +288,11 @@ __device__ inline double sample_normal_speed(const float* __restrict__ tab, doub
 }
 
 // One seeded particle (Sec. III.A.1-3): position on the CV and velocity, FP64.
-__device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ vn_tab, uint64_t pid, double x[3],
-                                     double w[3]) {
+__device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ lat_tab,
+                                     const float* __restrict__ vn_tab, uint64_t pid, double x[3], double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
-  const double mu = sample_latitude(q, unif64(r0.a));
+  const double mu = sample_latitude(q, lat_tab, unif64(r0.a));
   const double cphi = sqrt(fmax(0.0, 1.0 - mu * mu));
   double sth, cth;
   sincospi(2.0 * unif64(r0.b), &sth, &cth);

@@ -33,9 +33,33 @@ int grid_for(uint64_t n, int cap) {
 // ---------------------------------------------------------------------------
 // a2-a4: seeding
 // ---------------------------------------------------------------------------
-// Starting points of the normal-speed solve (normal_speed_start); part of the
-// code object, filled once per device by vn_table_kernel.
+// Starting points of the latitude and normal-speed solves (latitude_start,
+// normal_speed_start); part of the code object, filled once per device.
+__device__ float g_lat_start[kLatNS * kLatNT];
 __device__ float g_vn_start[kVnNS * kVnNT];
+
+__global__ void lat_table_kernel(float* __restrict__ tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kLatNS * kLatNT) return;
+  QueryDev q{};
+  q.S = (double)kLatS0 * exp((double)(i / kLatNT) * (double)kLatDL);
+  q.erfS = erf(q.S);
+  q.erfcS = erfc(q.S);
+  q.expmS2 = exp(-q.S * q.S);
+  const double t = (double)kLatT0 + (double)(i % kLatNT) * (double)kLatDT;
+  const double u = 1.0 / (1.0 + exp(-t));
+  double Z, G, dG, d2G;
+  latitude_G(q, 1.0, Z, dG, d2G);
+  const double target = u * Z;
+  double lo = -1.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (lo + hi);
+    latitude_G(q, m, G, dG, d2G);
+    if (G < target) lo = m;
+    else hi = m;
+  }
+  tab[i] = (float)(0.5 * (lo + hi));
+}
 
 __global__ void vn_table_kernel(float* __restrict__ tab) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -64,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double x[3], w[3];
-    seed_particle(q, g_vn_start, i, x, w);
+    seed_particle(q, g_lat_start, g_vn_start, i, x, w);
     x0[i] = (float)x[0];
     x1[i] = (float)x[1];
     x2[i] = (float)x[2];
@@ -658,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               const uint64_t pid = base + lane;
               if (pid < p_end) {
                 double x[3], w[3];
-                seed_particle(q, g_vn_start, pid, x, w);
+                seed_particle(q, g_lat_start, g_vn_start, pid, x, w);
                 qbuf[wave][0][lane] = (float)x[0];
                 qbuf[wave][1][lane] = (float)x[1];
                 qbuf[wave][2][lane] = (float)x[2];
@@ -838,9 +862,12 @@ void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t
 
 hipError_t init_seed_tables(hipStream_t st) {
   float* tab = nullptr;
+  float* lat = nullptr;
   hipError_t e = hipGetSymbolAddress((void**)&tab, HIP_SYMBOL(g_vn_start));
+  if (e == hipSuccess) e = hipGetSymbolAddress((void**)&lat, HIP_SYMBOL(g_lat_start));
   if (e != hipSuccess) return e;
   vn_table_kernel<<<(kVnNS * kVnNT + 255) / 256, 256, 0, st>>>(tab);
+  lat_table_kernel<<<(kLatNS * kLatNT + 255) / 256, 256, 0, st>>>(lat);
   e = hipGetLastError();
   return e != hipSuccess ? e : hipStreamSynchronize(st);
 }
