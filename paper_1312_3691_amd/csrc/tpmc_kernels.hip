@@ -260,6 +260,22 @@ __device__ __forceinline__ void leaf_phase(const TriRec* tris, const uint32_t* o
   }
 }
 
+// Whether a ray from (o, w) passes the slab test of either box of the root
+// node with no distance bound, i.e. whether its first traversal step can find
+// anything.  Same reciprocals and test as the traversal.
+__device__ __forceinline__ bool ray_enters_root(const Node* nodes, const float o[3], const float w[3]) {
+  Ray r;
+  r.ox = o[0]; r.oy = o[1]; r.oz = o[2];
+  r.idx = __builtin_amdgcn_rcpf(w[0]);
+  r.idy = __builtin_amdgcn_rcpf(w[1]);
+  r.idz = __builtin_amdgcn_rcpf(w[2]);
+  const gptr<vf4> np = (gptr<vf4>)nodes;
+  const vf4 A = np[0], B = np[1], C = np[2];
+  float tn;
+  const float inf = __builtin_inff();
+  return slab(r, A.x, A.y, A.z, A.w, B.x, B.y, inf, tn) || slab(r, B.z, B.w, C.x, C.y, C.z, C.w, inf, tn);
+}
+
 // Momentum and moment of one hit, ready for the tallies.
 struct Hit {
   bool valid;
@@ -562,6 +578,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   constexpr uint32_t kNone = 0xFFFFFFFFu;
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
+  __shared__ uint8_t qlane[kBlock / 64][64];  // queue slot -> particle offset in its seeding batch
   extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
@@ -670,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         }
         const uint64_t dead = ballot(!L.live);
         if (dead != 0ull) {
-          if (q_count == 0 && !exhausted) {
+          while (q_count == 0 && !exhausted) {  // wave-uniform
             // claim and seed the next (up to) 64 particles, one per lane
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(&next_sh, 64ull);
@@ -679,19 +696,37 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             if (base >= p_end) {
               exhausted = true;
             } else {
+              // Seed; a particle whose first ray misses both boxes of the root
+              // node would end its first traversal step with no hit, so it is
+              // counted as missed here and only the others are queued (trees
+              // deeper than a 4-slot stack: there it spares the lane its idle
+              // wait for the next service pass; in tiny trees every step ends
+              // at leaves and the test would only add work).
               const uint64_t pid = base + lane;
+              bool keep = false;
+              float xs[3], ws[3];
               if (pid < p_end) {
                 double x[3], w[3];
                 seed_particle(q, g_lat_start, g_vn_start, pid, x, w);
-                qbuf[wave][0][lane] = (float)x[0];
-                qbuf[wave][1][lane] = (float)x[1];
-                qbuf[wave][2][lane] = (float)x[2];
-                qbuf[wave][3][lane] = (float)w[0];
-                qbuf[wave][4][lane] = (float)w[1];
-                qbuf[wave][5][lane] = (float)w[2];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  xs[c] = (float)x[c];
+                  ws[c] = (float)w[c];
+                }
+                keep = STACK <= 4 || ray_enters_root(nodes, xs, ws);
+                if (!keep) count_outcome(A, kOutMissed, false);
               }
-              const uint64_t left = p_end - base;
-              q_count = left < 64 ? (uint32_t)left : 64u;
+              const uint64_t kb = ballot(keep);
+              if (keep) {
+                const uint32_t slot = (uint32_t)__popcll(kb & lt_mask);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  qbuf[wave][c][slot] = xs[c];
+                  qbuf[wave][3 + c][slot] = ws[c];
+                }
+                qlane[wave][slot] = (uint8_t)lane;
+              }
+              q_count = (uint32_t)__popcll(kb);
               q_head = 0;
               q_pid0 = base;
               __builtin_amdgcn_wave_barrier();
@@ -704,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               const uint32_t slot = q_head + rank;
               L.ox = qbuf[wave][0][slot]; L.oy = qbuf[wave][1][slot]; L.oz = qbuf[wave][2][slot];
               L.wx = qbuf[wave][3][slot]; L.wy = qbuf[wave][4][slot]; L.wz = qbuf[wave][5][slot];
-              L.pid = q_pid0 + slot;
+              L.pid = q_pid0 + qlane[wave][slot];
               L.D = 0.0f;
               L.prev = -1;
               L.hits = 0;
