@@ -74,12 +74,16 @@ __device__ __forceinline__ float unif32(uint32_t k) { return ((float)(k >> 9) + 
 // resolution of the result (usually one FP64 evaluation).  The result is an FP64 root either way; FP32
 // only chooses where the FP64 iteration starts.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG, double& d2G) {
+// Besides G and its derivatives, returns e = exp(-(S t)^2) and ta = erfc(|S t|),
+// which the normal-speed law at s = S mu reuses (normal_speed_consts_near).
+__device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG, double& d2G, double& e,
+                                           double& ta) {
   const double S = q.S;
   const double St = S * t;
-  const double e = exp(-St * St);
-  const double c = erfc(-St);  // 1 + erf(S t)
-  double E;                    // erf(S t) + erf(S)
+  e = exp(-St * St);
+  ta = erfc(fabs(St));
+  const double c = St >= 0.0 ? 2.0 - ta : ta;  // erfc(-S t) = 1 + erf(S t)
+  double E;                                     // erf(S t) + erf(S)
   if (S < 0.25) E = erf(St) + q.erfS;  // uniform branch: small S keeps erf(St) exact
   else E = St < -1.0 ? c - q.erfcS : (c - 1.0) + q.erfS;
   G = kSqrtPi / (4.0 * S) * E + 0.5 * kSqrtPi * S * (t * t * c - q.erfcS) + 0.5 * (t * e + q.expmS2);
@@ -155,7 +159,14 @@ __device__ __forceinline__ float latitude_start(const float* __restrict__ tab, f
   return (1.0f - wgt) * (2.0f * uf - 1.0f) + wgt * sqrtf(uf);
 }
 
-__device__ inline double sample_latitude(const QueryDev& q, const float* __restrict__ lat_tab, double u) {
+// The last FP64 evaluation of a latitude solve: point t, exp(-(S t)^2), erfc(|S t|).
+struct LatEval {
+  double t, e, ta;
+  bool valid;
+};
+
+__device__ inline double sample_latitude(const QueryDev& q, const float* __restrict__ lat_tab, double u, LatEval& le) {
+  le.valid = false;
   if (q.s_zero) return 2.0 * u - 1.0;  // S -> 0: g -> cos(phi)/2, mu uniform
   const double target = u * q.Z;
   const LatConst32 c{(float)q.S, (float)q.erfS, (float)q.erfcS, (float)q.expmS2, q.S < 0.25};
@@ -171,10 +182,12 @@ __device__ inline double sample_latitude(const QueryDev& q, const float* __restr
   }
   double x = (double)xf;
   double lo = -1.0, hi = 1.0;
+  le.valid = true;
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double G, dG, d2G;
-    latitude_G(q, x, G, dG, d2G);
+    le.t = x;
+    latitude_G(q, x, G, dG, d2G, le.e, le.ta);
     const double dx = halley_step(x, G - target, dG, d2G, lo, hi);
     // cubic convergence: after a step below 1e-5 the remaining error is far
     // below the FP64 resolution of mu
@@ -197,6 +210,45 @@ __device__ __forceinline__ NormalSpeedConsts normal_speed_consts(double s) {
   const double t = erfc(fabs(s));  // the small one of erfc(s), erfc(-s)
   k.erfcs = s >= 0.0 ? t : 2.0 - t;
   k.erfcms = s >= 0.0 ? 2.0 - t : t;  // 1 + erf(s)
+  k.erfs = s >= 0.0 ? 1.0 - t : t - 1.0;
+  k.chi = k.es2 + kSqrtPi * s * k.erfcms;
+  return k;
+}
+
+// The same constants at s from exp(-s0^2) and erfc(|s0|) at a nearby s0 of
+// the same sign (the latitude solve's last evaluation point, S times a point
+// within one Halley step of mu).  With y = |s0|, h = |s| - y:
+//   exp(-s^2)  = exp(-y^2) sum_n H_n(-y) h^n / n!,
+//   erfc(|s|)  = erfc(y) - 2/sqrt(pi) exp(-y^2) sum_n H_n(-y) h^(n+1) / (n+1)!,
+// H_n the physicists' Hermite polynomials (generating function
+// exp(2xh - h^2) = sum_n H_n(x) h^n / n!).  For |h| (y + 1) <= 1e-4 the terms
+// fall by at least ~2e-4 each, so six terms leave a relative error near 1e-21;
+// otherwise (or across s = 0) the constants are evaluated directly.
+__device__ __forceinline__ NormalSpeedConsts normal_speed_consts_near(double s, double s0, double e0, double ta0) {
+  const double y = fabs(s0);
+  const double h = fabs(s) - y;
+  if (!((s >= 0.0) == (s0 >= 0.0) && fabs(h) * (y + 1.0) <= 1e-4)) return normal_speed_consts(s);
+  constexpr double kInv[7] = {1.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6};
+  const double x = -y;
+  double Hm = 1.0, Hn = 2.0 * x;          // H_0, H_1
+  double hp = h;                          // h^n / n! at n = 1
+  double E = 1.0 + Hn * hp;               // sum_n H_n h^n / n!
+  double I = h + Hn * hp * h * kInv[2];  // sum_n H_n h^(n+1) / (n+1)!
+#pragma unroll
+  for (int n = 1; n < 5; ++n) {
+    const double Hp = 2.0 * x * Hn - 2.0 * n * Hm;  // H_{n+1}
+    Hm = Hn;
+    Hn = Hp;
+    hp *= h * kInv[n + 1];            // h^(n+1) / (n+1)!
+    E += Hn * hp;
+    I += Hn * hp * h * kInv[n + 2];  // h^(n+2) / (n+2)!
+  }
+  NormalSpeedConsts k;
+  k.s = s;
+  k.es2 = e0 * E;
+  const double t = ta0 - 2.0 / kSqrtPi * e0 * I;  // erfc(|s|)
+  k.erfcs = s >= 0.0 ? t : 2.0 - t;
+  k.erfcms = s >= 0.0 ? 2.0 - t : t;
   k.erfs = s >= 0.0 ? 1.0 - t : t - 1.0;
   k.chi = k.es2 + kSqrtPi * s * k.erfcms;
   return k;
@@ -251,8 +303,8 @@ __device__ __forceinline__ float normal_speed_start(const float* __restrict__ ta
   return sf > 1.0f ? sf + 0.5f / sf + erfinvf(2.0f * uf - 1.0f) : sqrtf(-log1pf(-uf));
 }
 
-__device__ inline double sample_normal_speed(const float* __restrict__ tab, double s, double u) {
-  const NormalSpeedConsts k = normal_speed_consts(s);
+__device__ inline double sample_normal_speed(const float* __restrict__ tab, const NormalSpeedConsts& k, double u) {
+  const double s = k.s;
   const double target = u * k.chi;
   // The root lies below max(s, 0) + 7: the upper tail there is below e^{-49},
   // far under the smallest 1 - u the variates produce (2^-33).
@@ -292,7 +344,8 @@ __device__ inline void seed_particle(const QueryDev& q, const float* __restrict_
                                      const float* __restrict__ vn_tab, uint64_t pid, double x[3], double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
-  const double mu = sample_latitude(q, lat_tab, unif64(r0.a));
+  LatEval le;
+  const double mu = sample_latitude(q, lat_tab, unif64(r0.a), le);
   const double cphi = sqrt(fmax(0.0, 1.0 - mu * mu));
   double sth, cth;
   sincospi(2.0 * unif64(r0.b), &sth, &cth);
@@ -300,7 +353,9 @@ __device__ inline void seed_particle(const QueryDev& q, const float* __restrict_
   // t1 = cos(phi) U + mu c (unit, along the tangential part of U); t2 = t1 x n = -d,
   // d = -sin(th) e1 + cos(th) e2.  x = c0 - r n.
   const double s_n = q.S * mu;
-  const double wn = sample_normal_speed(vn_tab, s_n, unif64(r0.c));
+  const NormalSpeedConsts k =
+      le.valid ? normal_speed_consts_near(s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(s_n);
+  const double wn = sample_normal_speed(vn_tab, k, unif64(r0.c));
   const double rad = sqrt(-2.0 * log(unif64(r0.d)));
   double sb, cb;
   sincospi(2.0 * unif64(r1.a), &sb, &cb);

@@ -48,13 +48,13 @@ __global__ void lat_table_kernel(float* __restrict__ tab) {
   q.expmS2 = exp(-q.S * q.S);
   const double t = (double)kLatT0 + (double)(i % kLatNT) * (double)kLatDT;
   const double u = 1.0 / (1.0 + exp(-t));
-  double Z, G, dG, d2G;
-  latitude_G(q, 1.0, Z, dG, d2G);
+  double Z, G, dG, d2G, e, ta;
+  latitude_G(q, 1.0, Z, dG, d2G, e, ta);
   const double target = u * Z;
   double lo = -1.0, hi = 1.0;
   for (int it = 0; it < 60; ++it) {
     const double m = 0.5 * (lo + hi);
-    latitude_G(q, m, G, dG, d2G);
+    latitude_G(q, m, G, dG, d2G, e, ta);
     if (G < target) lo = m;
     else hi = m;
   }
