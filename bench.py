@@ -39,7 +39,7 @@ OPS_SEED = 950.0   # per particle: 2 Philox blocks + FP64 inverse-CDF seeding + 
 OPS_NODE = 40.0    # per BVH node visit: two slab tests + stack
 OPS_TRI = 45.0     # per watertight triangle test
 OPS_HIT = 225.0    # per hit: Philox block + re-emission + tally
-KERNEL_SOURCES = ["tpmc_device.hpp", "tpmc_kernels.hip", "tpmc_internal.h"]
+KERNEL_SOURCES = ["tpmc_device.hpp", "tpmc_math.hpp", "tpmc_kernels.hip", "tpmc_internal.h"]
 
 
 def log(*a):

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "tpmc_internal.h"
+#include "tpmc_math.hpp"
 
 // Contraction into FMA only within one source expression, so every kernel that
 // inlines these functions rounds them identically (plain and batched paths
@@ -110,10 +111,21 @@ __device__ __forceinline__ void latitude_G32(const LatConst32& c, float t, float
 
 // One Halley step inside the bracket [lo, hi], bisection when the step leaves
 // it.  x_new = x - 2 f f' / (2 f'^2 - f f''), or the Newton step f / f' when
-// the Halley factor 1 - f f'' / (2 f'^2) leaves (1/2, 2); one division either
+// the Halley factor 1 - f f'' / (2 f'^2) leaves (1/2, 2); one reciprocal either
 // way.  Returns |step| of a Halley (or Newton) step, or +inf after a
 // bisection, so that only a genuine iteration step can end a solve.  The
 // bounds are inclusive: a step below one ulp leaves x unchanged.
+// The quotient uses the hardware reciprocal (plus one Newton step in FP64):
+// the step only corrects x, so its relative accuracy (1 ulp in FP32, ~2^-50
+// in FP64) is ample, and a zero or non-finite denominator still sends the
+// iterate out of the bracket into bisection.
+__device__ __forceinline__ float step_quotient(float n, float d) { return n * __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double step_quotient(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return n * r;
+}
+
 template <class T>
 __device__ __forceinline__ T halley_step(T& x, T f, T df, T d2f, T& lo, T& hi) {
   if (f < T(0)) lo = x;
@@ -121,7 +133,7 @@ __device__ __forceinline__ T halley_step(T& x, T f, T df, T d2f, T& lo, T& hi) {
   const T df2 = df * df;
   const T D = T(2) * df2 - f * d2f;
   const bool hal = D > df2 && D < T(4) * df2;
-  const T xn = x - (hal ? T(2) * f * df : f) / (hal ? D : df);
+  const T xn = x - step_quotient(hal ? T(2) * f * df : f, hal ? D : df);
   if (xn >= lo && xn <= hi) {
     const T dx = fabs(xn - x);
     x = xn;
@@ -356,7 +368,7 @@ __device__ inline void seed_particle(const QueryDev& q, const float* __restrict_
   const NormalSpeedConsts k =
       le.valid ? normal_speed_consts_near(s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(s_n);
   const double wn = sample_normal_speed(vn_tab, k, unif64(r0.c));
-  const double rad = sqrt(-2.0 * log(unif64(r0.d)));
+  const double rad = sqrt(-2.0 * log_draw(r0.d));  // ln unif64(r0.d)
   double sb, cb;
   sincospi(2.0 * unif64(r1.a), &sb, &cb);
   const double wt1 = q.S * cphi + rad * cb * kInvSqrt2;

@@ -1,0 +1,50 @@
+// tpmc_math.hpp -- FP64 logarithm of the seeding draws (Box-Muller radius).
+//
+// The seeding draws are u = (k + 1/2) 2^-32 for a 32-bit integer k (unif64 in
+// tpmc_device.hpp), so u = n 2^-33 with n = 2k + 1 odd, and the reduction is
+// exact in integer arithmetic: ln u = ln n - 33 ln 2 with n = m 2^e exactly,
+// m in [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),
+// s = (m - 1)/(m + 1), |s| <= 0.1716, series to s^21 (first omitted term
+// below 1e-18 relative); e ln 2 is split as e ln2_hi (exact: ln2_hi has 46
+// significant bits) plus e ln2_lo.  The result stays within 1.5 ulp of ln u
+// over every k (a CPU test compares it with 40-digit values; the largest
+// errors sit near u = 0.7, where -ln 2 and ln m partly cancel), with about
+// 30 % fewer instructions than a general-argument log.  The coefficients 2/(2j+1)
+// are rounded to the nearest double.
+#ifndef TPMC_MATH_HPP
+#define TPMC_MATH_HPP
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tpmc {
+
+// ln(u) for u = (k + 1/2) 2^-32.
+__host__ __device__ inline double log_draw(uint32_t k) {
+  const uint64_t n = 2ull * k + 1ull;  // u = n 2^-33
+  int e = 63 - __builtin_clzll(n);     // n = m 2^e, m in [1, 2)
+  double m = ldexp((double)n, -e);
+  if (m > 0x1.6a09e667f3bcdp+0) {      // sqrt(2)
+    m *= 0.5;
+    ++e;
+  }
+  const double s = (m - 1.0) / (m + 1.0);
+  const double w = s * s;
+  double p = 0x1.8618618618618p-4;  // 2/21
+  p = fma(p, w, 0x1.af286bca1af28p-4);
+  p = fma(p, w, 0x1.e1e1e1e1e1e1ep-4);
+  p = fma(p, w, 0x1.1111111111111p-3);
+  p = fma(p, w, 0x1.3b13b13b13b14p-3);
+  p = fma(p, w, 0x1.745d1745d1746p-3);
+  p = fma(p, w, 0x1.c71c71c71c71cp-3);
+  p = fma(p, w, 0x1.2492492492492p-2);
+  p = fma(p, w, 0x1.999999999999ap-2);
+  p = fma(p, w, 0x1.5555555555555p-1);  // 2/3
+  const double lm = fma(s * w, p, 2.0 * s);  // ln m = 2s + s w P(w)
+  const double E = (double)(e - 33);
+  return fma(E, 0x1.62e42fefa3980p-1, fma(E, 0x1.bcd5e4f1d9cc0p-47, lm));
+}
+
+}  // namespace tpmc
+
+#endif  // TPMC_MATH_HPP
