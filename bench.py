@@ -34,7 +34,7 @@ METRIC = "particle-surface hits/sec on 1 MI355X at C_D error ≤1e-3; p50/p99 qu
 T_INF, T_W = 1000.0, 300.0
 N_PER_CASE = 10_000_000
 ALU_PEAK = 256 * 64 * 2.4e9  # lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz (one VALU op per lane per clock)
-# Algorithmic lane-operations per unit of work ("Roofline").
+# Algorithmic lane-operations per unit of work (one VALU operation per lane = 1).
 OPS_SEED = 950.0   # per particle: 2 Philox blocks + FP64 inverse-CDF seeding + frame
 OPS_NODE = 40.0    # per BVH node visit: two slab tests + stack
 OPS_TRI = 45.0     # per watertight triangle test
@@ -62,12 +62,17 @@ def meshes():
     return {"plate": I.plate(), "cylinder": I.capped_cylinder()}
 
 
-def exact_cd(kind, V, T, q):
-    from oracle import closed_forms as CF
-    from paper_1312_3691_amd import inputs as I
-    U = I.flow_dir(q["q"])
-    F, _, _ = CF.mesh_force(V, T, U, q["S"], math.sqrt(T_W / T_INF), q["alpha"], two_sided=(kind == "plate"))
-    return float(F @ U)
+EXACT_PATH = os.path.join(ROOT, "tests", "golden", "bench_cases_exact.json")
+
+
+def exact_cd(kind, angle, S, alpha):
+    """Per-facet exact C_D of a benchmark case (drag area, A_ref = 1 m^2), from the
+    stored table tests/golden/bench_cases_exact.json (written from the closed
+    forms by tests/golden/make_bench_exact.py)."""
+    global _EXACT
+    if "_EXACT" not in globals():
+        _EXACT = {(e["kind"], e["angle"], e["S"], e["alpha"]): e["CD"] for e in json.load(open(EXACT_PATH))["cases"]}
+    return _EXACT[(kind, float(angle), float(S), float(alpha))]
 
 
 def kernel_hash():
@@ -219,7 +224,9 @@ def workload_satellite(args):
     from paper_1312_3691_amd import tpmc
     ctx = tpmc.Context(0)
     V, T = I.satellite(50_000)
+    t0 = time.perf_counter()
     mesh = ctx.build_mesh(V, T, builder=args.bvh)
+    build_ms = (time.perf_counter() - t0) * 1e3
     U = (-0.5, 0.0, -math.sqrt(3.0) / 2.0)
     n = int(args.particles_sat)
     q = I.query(q=I.quat_for_flow(U), S=7.0, T_inf=T_INF, T_w=T_W, alpha=0.9, n=n, seed=0, max_reflections=16)
@@ -242,8 +249,64 @@ def workload_satellite(args):
                         "path": "batched persistent launch, graph replay", "bvh": args.bvh},
           {"CD": r["CD"], "CD_sigma": r["CD_sigma"], "hits_per_particle": r["hits"] / n,
            "segments_per_s": r["segments"] / dt, "capped": r["capped"], "bvh_depth": mesh.info["depth"],
-           "tuning": tuning,
+           "bvh_build_ms": build_ms, "tuning": tuning,
            "plain_path": {"hits_per_s": rp[0]["hits"] / pdt, "s": pdt, "CD": rp[0]["CD"]}})
+
+
+PRATT_S = (0.5, 1.0, 2.0, 3.0, 5.0, 8.0, 12.0, 20.0, 30.0, 50.0)
+PRATT_EPS_D = 1.05349  # eps_D(90 deg) as printed with eq. hypersphere (Pratt's re-emission drag integral)
+
+
+def workload_pratt(args):
+    """Concave spherical shell: an open hemispherical cup (radius 1 m, 4512
+    triangles), flow into the cup, full diffuse accommodation, S from 0.5 to 50,
+    against Pratt's hyperthermal form C_D = 2 + eps_D sqrt(pi) tau / S (eq.
+    hypersphere; A_ref = pi r^2, the rim disk).  eps_D itself comes from the
+    tau-slope of C_D at S = 100 on equal seeds (C_D is linear in tau there)."""
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    ctx = tpmc.Context(0)
+    V, T = I.hemisphere_cup(24, 96)
+    t0 = time.perf_counter()
+    mesh = ctx.build_mesh(V, T, builder=args.bvh)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    n = int(args.particles_pratt)
+    flow = I.quat_for_flow((0.0, 0.0, -1.0))
+    cv = dict(cv_radius=1.0 + 1e-3, cv_center=(0.0, 0.0, 0.0))
+    qs = [I.query(q=flow, S=S, T_inf=T_INF, T_w=T_W, alpha=1.0, n=n, seed=i, max_reflections=16, **cv)
+          for i, S in enumerate(PRATT_S)]
+    taus = (0.5, 1.0)
+    qs += [I.query(q=flow, S=100.0, T_inf=1000.0, T_w=1000.0 * t * t, alpha=1.0, n=n, seed=100, max_reflections=16,
+                   **cv) for t in taus]
+    tuning = tune_for(args, mesh, qs)
+    b = tpmc.Batch(mesh, qs)
+    b.launch().results(A_ref=math.pi)
+    for _ in range(args.warmup):
+        b.launch(use_graph=True).results(A_ref=math.pi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = b.launch(use_graph=True).results(A_ref=math.pi)
+    dt = (time.perf_counter() - t0) / args.steps
+    b.close()
+    tau = math.sqrt(T_W / T_INF)
+    sweep = [{"S": S, "CD": r["CD"], "CD_sigma": r["CD_sigma"],
+              "pratt_CD": 2.0 + PRATT_EPS_D * math.sqrt(math.pi) * tau / S,
+              "hits_per_particle": r["hits"] / n, "capped": r["capped"]} for S, r in zip(PRATT_S, res)]
+    r0, r1 = res[len(PRATT_S):]
+    slope = (r1["CD"] - r0["CD"]) / (taus[1] - taus[0])
+    eps = slope * 100.0 / math.sqrt(math.pi)
+    # conservative: the two runs share seeds, so their errors are positively correlated
+    eps_sig = (r0["CD_sigma"] + r1["CD_sigma"]) / (taus[1] - taus[0]) * 100.0 / math.sqrt(math.pi)
+    hits = sum(r["hits"] for r in res)
+    _line("particle-surface hits/sec on 1 MI355X (concave shell vs Pratt)", hits / dt, "hits/s", dt, args.steps,
+          args.warmup, {"workload": f"hemispherical cup {len(T)} tris, flow into the cup, alpha=1, S in "
+                                    f"{list(PRATT_S)} + S=100 at tau in {list(taus)}, {n} particles each",
+                        "path": "one batched persistent launch, graph replay", "bvh": args.bvh},
+          {"sweep": sweep, "eps_D": {"value": eps, "sigma_bound": eps_sig, "paper": PRATT_EPS_D},
+           "segments_per_s": sum(r["segments"] for r in res) / dt, "bvh_build_ms": build_ms, "tuning": tuning})
 
 
 def workload_sweep(args):
@@ -422,10 +485,12 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true", help="run only the HBM-counter calibration copies")
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
-    ap.add_argument("--workload", default="plate-cylinder", choices=["plate-cylinder", "satellite", "sweep", "served"],
+    ap.add_argument("--workload", default="plate-cylinder",
+                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt"],
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
+    ap.add_argument("--particles-pratt", type=float, default=1e7)
     ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
     ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
     ap.add_argument("--slots", type=int, default=64, help="served: request slots")
@@ -448,10 +513,12 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the drag path shards by particle range, see DESIGN.md)", file=sys.stderr)
+              "(a query shards by particle range: every GPU traces its own id range on a BVH replica and "
+              "the int64 tallies are summed with one all-reduce)", file=sys.stderr)
         sys.exit(2)
     if args.workload != "plate-cylinder":
-        {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served}[args.workload](args)
+        {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served,
+         "pratt": workload_pratt}[args.workload](args)
         return
 
     import torch
@@ -461,7 +528,11 @@ def main():
     ctx = tpmc.Context(0)
     mm = meshes()
     cl = cases(args.particles)
-    dev_mesh = {k: ctx.build_mesh(*v, builder=args.bvh) for k, v in mm.items()}
+    dev_mesh, build_ms = {}, {}
+    for k, v in mm.items():
+        t0 = time.perf_counter()
+        dev_mesh[k] = ctx.build_mesh(*v, builder=args.bvh)
+        build_ms[k] = (time.perf_counter() - t0) * 1e3
     batches, tunings = {}, {}
     for kind in ("plate", "cylinder"):
         qs = [c["query"] for c in cl if c["kind"] == kind]
@@ -536,8 +607,7 @@ def main():
     # (relative error where the exact value is not ~0; error in units of the run's own sigma)
     errs, rels, zs = [], [], []
     for c, r in zip([c for k in ("plate", "cylinder") for c in cl if c["kind"] == k], res):
-        V, T = mm[c["kind"]]
-        ex = exact_cd(c["kind"], V, T, c["query"])
+        ex = exact_cd(c["kind"], c["angle"], c["query"]["S"], c["query"]["alpha"])
         e = abs(r["CD"] - ex)
         errs.append(e)
         if abs(ex) > 0.05:
@@ -590,7 +660,8 @@ def main():
             "query_ms_p50": plain["query_ms_p50"] if plain else None,
             "query_ms_p99": plain["query_ms_p99"] if plain else None,
             "segments_per_s": segments / dt, "particles_per_s": particles / dt,
-            "accuracy": accuracy, "plain_path": plain, "tuning": tunings, "roofline": roofline,
+            "accuracy": accuracy, "plain_path": plain, "tuning": tunings, "bvh_build_ms": build_ms,
+            "roofline": roofline,
             "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 

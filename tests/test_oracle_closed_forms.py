@@ -154,3 +154,26 @@ def test_fine_icosphere_approaches_eq_sphere():
     F, M, _ = CF.mesh_force(V.astype(np.float64), T, (1.0, 0, 0), 5.0, TAU, 1.0)
     assert F[0] / math.pi == pytest.approx(CF.sphere_cd(5.0, TAU), rel=5e-4)
     assert np.allclose(M, 0, atol=1e-9)
+
+
+def test_golden_bench_cases_regenerate():
+    """bench_cases_exact.json (written by tests/golden/make_bench_exact.py, read
+    by the benchmark's accuracy report) holds the per-facet closed forms of all
+    120 cases: the plate rows equal the corrected eq. plate values (diffuse) and
+    the specular plate form, and the cylinder rows match the survey's table of
+    drag areas at 0/30/60/90 degrees."""
+    d = json.load(open(os.path.join(GOLD, "bench_cases_exact.json")))["cases"]
+    assert len(d) == 120
+    for row in d:
+        if row["kind"] == "plate":
+            ref = (CF.plate_cd(row["S"], row["angle"], TAU) if row["alpha"] == 1.0
+                   else CF.plate_cd_specular(row["S"], row["angle"]))
+            assert row["CD"] == pytest.approx(ref, rel=1e-9, abs=1e-12)
+    cyl = {(r["S"], r["angle"], r["alpha"]): r["CD"] for r in d if r["kind"] == "cylinder"}
+    table = {1.0: ((4.8409, 4.6158), (4.9621, 4.2132), (5.0040, 4.0842), (4.9198, 4.3637)),
+             3.0: ((2.4997, 3.3108), (2.8549, 2.6252), (2.9739, 2.3985), (2.7124, 2.8845)),
+             8.0: ((1.8972, 3.1611), (2.4870, 2.4072), (2.6394, 2.1627), (2.2285, 2.6968))}
+    for S, row in table.items():
+        for a, (diffuse, specular) in zip((0.0, 30.0, 60.0, 90.0), row):
+            assert cyl[(S, a, 1.0)] == pytest.approx(diffuse, abs=6e-5)
+            assert cyl[(S, a, 0.0)] == pytest.approx(specular, abs=6e-5)

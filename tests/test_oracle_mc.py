@@ -342,6 +342,6 @@ def test_pratt_concave_hemisphere(orc):
     K = 2 * res[0]["Gamma_hat"] / (n * S * S) / math.pi
     dD = (res[1]["D"] - res[0]["D"]) / (t1 - t0)
     sig = K * math.sqrt(n) * np.std(dD) * S / math.sqrt(math.pi)
-    # faceting of the 4608-triangle cup biases eps_D by a few 1e-3
+    # faceting of the 4512-triangle cup biases eps_D by a few 1e-3
     assert abs(eps - paper["pratt_eps_D_90deg"]["value"]) < 4 * sig + 6e-3
     assert res[0]["CD"] == pytest.approx(2.0, abs=0.01)
