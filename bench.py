@@ -309,6 +309,55 @@ def workload_pratt(args):
            "segments_per_s": sum(r["segments"] for r in res) / dt, "bvh_build_ms": build_ms, "tuning": tuning})
 
 
+MOMENT_PITCH = tuple(range(-40, 41, 10))
+MOMENT_YAW = (-20, 0, 20)
+
+
+def workload_moments(args):
+    """Aerodynamic moment and static stability over an attitude grid: the
+    concave satellite (~50k triangles), S = 7, alpha = 0.9, pitch -40..40 deg x
+    yaw -20/0/20 deg about the nominal flow -z, all 27 attitudes in one batched
+    launch.  C_m = M / (q A_ref c) about the bus centre (origin) with A_ref = 1
+    m^2 and c = 1 m; the pitch stiffness dC_m,y / d(pitch) at zero yaw by
+    central differences."""
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    ctx = tpmc.Context(0)
+    V, T = I.satellite(50_000)
+    t0 = time.perf_counter()
+    mesh = ctx.build_mesh(V, T, builder=args.bvh)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    n = int(args.particles_moments)
+    grid = [(p, y) for y in MOMENT_YAW for p in MOMENT_PITCH]
+    qs = [I.query(q=I.quat_for_flow(I.flow_pitch_yaw(p, y)), S=7.0, T_inf=T_INF, T_w=T_W, alpha=0.9, n=n, seed=i,
+                  max_reflections=16) for i, (p, y) in enumerate(grid)]
+    tuning = tune_for(args, mesh, qs)
+    b = tpmc.Batch(mesh, qs)
+    b.launch().results()
+    for _ in range(args.warmup):
+        b.launch(use_graph=True).results()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = b.launch(use_graph=True).results(x_ref=(0.0, 0.0, 0.0), A_ref=1.0)
+    dt = (time.perf_counter() - t0) / args.steps
+    b.close()
+    rows = [{"pitch_deg": p, "yaw_deg": y, "CD": r["CD"], "CD_sigma": r["CD_sigma"], "Cm": list(r["M_over_q"]),
+             "CF": list(r["F_over_q"])} for (p, y), r in zip(grid, res)]
+    cm_y = {p: r["Cm"][1] for p, r in zip([g[0] for g in grid], rows) if r["yaw_deg"] == 0}
+    stiff = (cm_y[10] - cm_y[-10]) / math.radians(20.0)
+    hits = sum(r["hits"] for r in res)
+    _line("particle-surface hits/sec on 1 MI355X (moment and stability sweep)", hits / dt, "hits/s", dt,
+          args.steps, args.warmup,
+          {"workload": f"concave satellite {len(T)} tris, S=7, alpha=0.9, pitch {list(MOMENT_PITCH)} x yaw "
+                       f"{list(MOMENT_YAW)} deg, {n} particles each, moments about the origin",
+           "path": "one batched persistent launch, graph replay", "bvh": args.bvh},
+          {"grid": rows, "dCmy_dpitch_per_rad": stiff, "segments_per_s": sum(r["segments"] for r in res) / dt,
+           "bvh_build_ms": build_ms, "tuning": tuning})
+
+
 def workload_sweep(args):
     """1024 uniform-random attitudes x S ~ U[2, 10], 1e6 particles each, on the ~50k-triangle
     satellite: one persistent graph-replayed launch against 1024 plain calls (host sync each)."""
@@ -486,11 +535,12 @@ def main():
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
     ap.add_argument("--workload", default="plate-cylinder",
-                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt"],
+                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments"],
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
     ap.add_argument("--particles-pratt", type=float, default=1e7)
+    ap.add_argument("--particles-moments", type=float, default=4e6)
     ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
     ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
     ap.add_argument("--slots", type=int, default=64, help="served: request slots")
@@ -518,7 +568,7 @@ def main():
         sys.exit(2)
     if args.workload != "plate-cylinder":
         {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served,
-         "pratt": workload_pratt}[args.workload](args)
+         "pratt": workload_pratt, "moments": workload_moments}[args.workload](args)
         return
 
     import torch

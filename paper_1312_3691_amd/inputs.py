@@ -78,6 +78,14 @@ def flow_dir(q) -> np.ndarray:
     return matrix_from_quat(q)[0]
 
 
+def flow_pitch_yaw(pitch_deg: float, yaw_deg: float) -> tuple:
+    """Free-stream direction in the body frame for an attitude grid about the
+    nominal flow -z (into the satellite's dish): pitch about y, then yaw about
+    x, U = (sin p, cos p sin y, -cos p cos y)."""
+    p, y = math.radians(pitch_deg), math.radians(yaw_deg)
+    return (math.sin(p), math.cos(p) * math.sin(y), -math.cos(p) * math.cos(y))
+
+
 def random_quats(n: int, seed: int) -> np.ndarray:
     """Uniform random rotations (Shoemake, Graphics Gems III, 1992)."""
     rng = np.random.default_rng(seed)

@@ -233,6 +233,37 @@ def test_pratt_tau_linearity_and_eps_D(ctx, T):
     assert cd[0] == pytest.approx(2.0, abs=0.01)
 
 
+@pytest.mark.parametrize("pitch,yaw", [(0.0, 0.0), (25.0, 0.0), (-15.0, 20.0)])
+def test_moment_sweep_parity(ctx, T, pitch, yaw):
+    """Moment and stability sweeps (next row): the aerodynamic moment about an
+    off-centre reference point on the concave satellite at grid attitudes,
+    plain and batched paths against the oracle; the batched results at a
+    second reference point obey M(x2) = M(x1) + (x1 - x2) x F."""
+    V, Tr = I.satellite(4000)
+    x_ref = (0.2, -0.1, 0.4)
+    q = I.query(q=I.quat_for_flow(I.flow_pitch_yaw(pitch, yaw)), S=7.0, alpha=0.9, n=40_009, seed=5)
+    mesh = ctx.build_mesh(V, Tr)
+    res, pr = T.run(mesh, [q], x_ref=x_ref, A_ref=1.0)
+    pr.close()
+    g = res[0]
+    o = O.run(V, Tr, q, x_ref=x_ref, A_ref=1.0)
+    Fo, Mo = np.asarray(o["F_over_q"]), np.asarray(o["M_over_q"])
+    scale = np.linalg.norm(Mo) + np.linalg.norm(Fo) * 1.0  # 1 m lever
+    assert np.abs(np.asarray(g["M_over_q"]) - Mo).max() <= 1e-3 * scale, (g["M_over_q"], Mo)
+    assert np.abs(np.asarray(g["F_over_q"]) - Fo).max() <= 1e-3 * np.linalg.norm(Fo)
+    b = T.Batch(mesh, [q])
+    b.launch(use_graph=False)
+    r1 = b.results(x_ref=x_ref)[0]
+    x2 = (-0.7, 0.3, 1.1)
+    r2 = b.results(x_ref=x2)[0]
+    b.close()
+    for k in ("F_over_q", "M_over_q", "CD"):
+        assert np.array_equal(np.asarray(r1[k]), np.asarray(g[k])), k
+    F = np.asarray(r1["F_over_q"])
+    M2 = np.asarray(r1["M_over_q"]) + np.cross(np.asarray(x_ref) - np.asarray(x2), F)
+    assert np.allclose(np.asarray(r2["M_over_q"]), M2, rtol=1e-12, atol=1e-12 * scale)
+
+
 def test_edge_cases(ctx, T):
     """N = 1, a single-triangle mesh, max_reflections = 1, S = 0."""
     V, Tr = I.plate()
