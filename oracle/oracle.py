@@ -26,13 +26,15 @@ _lock = threading.Lock()
 _lib = None
 
 N_CHUNKS = 64
+BOX_CV_FLAG = 2  # query flag: box control volume
 
 
 class OrcQuery(ctypes.Structure):
     _fields_ = [("q_wxyz", ctypes.c_double * 4), ("S", ctypes.c_double), ("T_inf", ctypes.c_double),
                 ("T_w", ctypes.c_double), ("alpha", ctypes.c_double), ("n_particles", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("max_reflections", ctypes.c_uint32), ("round_fp32", ctypes.c_int32),
-                ("cv_center", ctypes.c_double * 3), ("cv_radius", ctypes.c_double)]
+                ("cv_center", ctypes.c_double * 3), ("cv_radius", ctypes.c_double), ("cv_box", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 class OrcConsts(ctypes.Structure):
@@ -40,7 +42,9 @@ class OrcConsts(ctypes.Structure):
                 ("S", ctypes.c_double), ("tau", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("Z", ctypes.c_double), ("Gamma_hat", ctypes.c_double), ("c0", ctypes.c_double * 3),
                 ("r", ctypes.c_double), ("N", ctypes.c_uint64), ("seed", ctypes.c_uint64),
-                ("rmax", ctypes.c_uint32), ("round_fp32", ctypes.c_int32), ("s_zero", ctypes.c_int32)]
+                ("rmax", ctypes.c_uint32), ("round_fp32", ctypes.c_int32), ("s_zero", ctypes.c_int32),
+                ("box", ctypes.c_int32), ("h", ctypes.c_double * 3), ("face_s", ctypes.c_double * 6),
+                ("face_cum", ctypes.c_double * 6)]
 
 
 class OrcScalars(ctypes.Structure):
@@ -120,6 +124,7 @@ def make_query(qd: dict, round_fp32: bool = True) -> OrcQuery:
     q.round_fp32 = 1 if round_fp32 else 0
     q.cv_center[:] = [float(v) for v in qd.get("cv_center", (0.0, 0.0, 0.0))]
     q.cv_radius = float(qd.get("cv_radius", 0.0))
+    q.cv_box = 1 if int(qd.get("flags", 0)) & BOX_CV_FLAG else 0
     return q
 
 

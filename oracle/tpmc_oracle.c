@@ -190,6 +190,50 @@ int orc_setup(const orc_query* q, const double* V, uint64_t nv, orc_consts* c) {
   c->rmax = q->max_reflections;
   c->round_fp32 = q->round_fp32;
 
+  if (q->cv_box) {
+    /* Box control volume (the rectangular CV of Sec. III.A, seeded correctly):
+     * the cube of half-side cv_radius about cv_center, or with cv_radius <= 0
+     * the vertex box widened on every axis by 1e-3 of its half-diagonal.  The
+     * inflow through face f (area A_f, inward normal n_f) is the one-sided
+     * flux of the drifting Maxwellian, A_f chi(s_f) / (2 sqrt(pi)) per n c_mp
+     * with s_f = S U.n_f (the sphere's flux density at latitude sin(phi) =
+     * U.n), so Gamma_hat = sum_f A_f chi(s_f) / (2 sqrt(pi)). */
+    c->box = 1;
+    if (q->cv_radius > 0.0) {
+      for (int k = 0; k < 3; ++k) {
+        c->c0[k] = q->cv_center[k];
+        c->h[k] = q->cv_radius;
+      }
+    } else {
+      double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+      for (uint64_t i = 0; i < nv; ++i)
+        for (int k = 0; k < 3; ++k) {
+          if (V[3 * i + k] < lo[k]) lo[k] = V[3 * i + k];
+          if (V[3 * i + k] > hi[k]) hi[k] = V[3 * i + k];
+        }
+      double hd = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        c->c0[k] = 0.5 * (lo[k] + hi[k]);
+        c->h[k] = 0.5 * (hi[k] - lo[k]);
+        hd += c->h[k] * c->h[k];
+      }
+      hd = sqrt(hd);
+      for (int k = 0; k < 3; ++k) c->h[k] += 1e-3 * hd;
+    }
+    c->r = sqrt(c->h[0] * c->h[0] + c->h[1] * c->h[1] + c->h[2] * c->h[2]);
+    double cum = 0.0;
+    for (int f = 0; f < 6; ++f) {
+      int k = f / 2, j = (k + 1) % 3, l = (k + 2) % 3;
+      double n_k = (f % 2 == 0) ? 1.0 : -1.0; /* inward normal of the face at c0[k] -/+ h[k] */
+      double s_f = c->s_zero ? 0.0 : q->S * c->U[k] * n_k;
+      c->face_s[f] = s_f;
+      cum += 4.0 * c->h[j] * c->h[l] * orc_chi(s_f);
+      c->face_cum[f] = cum;
+    }
+    c->Z = orc_Z(c->S);
+    c->Gamma_hat = cum / (2.0 * ORC_SQRTPI);
+    return 0;
+  }
   if (q->cv_radius > 0.0) {
     for (int k = 0; k < 3; ++k) c->c0[k] = q->cv_center[k];
     c->r = q->cv_radius;
@@ -217,10 +261,46 @@ int orc_setup(const orc_query* q, const double* V, uint64_t nv, orc_consts* c) {
 /* ------------------------------------------------------------------------- */
 /* Seeding one particle, Sec. III.A.1-3.                                       */
 /* ------------------------------------------------------------------------- */
+/* Box CV: the face by its share of the inflow, the point uniform on the face,
+ * the velocity from the same flux-weighted drifting distribution as on the
+ * sphere with s_n = s_f, tangential components Gaussian about the tangential
+ * drift S U_j, S U_l (face axes j, l). */
+static void orc_seed_box(const orc_consts* c, const uint32_t r0[4], const uint32_t r1[4], double x[3],
+                         double wv[3], double* mu_out) {
+  double u0 = u64_of(r0[0]), u1 = u64_of(r0[1]), u2 = u64_of(r0[2]), u3 = u64_of(r0[3]);
+  double u4 = u64_of(r1[0]), u5 = u64_of(r1[1]);
+  double t = u0 * c->face_cum[5];
+  int f = 0;
+  while (f < 5 && !(t < c->face_cum[f])) ++f;
+  int k = f / 2, j = (k + 1) % 3, l = (k + 2) % 3;
+  double n_k = (f % 2 == 0) ? 1.0 : -1.0;
+  x[k] = c->c0[k] - n_k * c->h[k];
+  x[j] = c->c0[j] + (2.0 * u1 - 1.0) * c->h[j];
+  x[l] = c->c0[l] + (2.0 * u5 - 1.0) * c->h[l];
+  double wn = orc_inv_F_n(u2, c->face_s[f]);
+  double rad = sqrt(-2.0 * log(u3));
+  double g1 = rad * cos(2.0 * ORC_PI * u4);
+  double g2 = rad * sin(2.0 * ORC_PI * u4);
+  wv[k] = wn * n_k;
+  wv[j] = c->S * c->U[j] + g1 / sqrt(2.0);
+  wv[l] = c->S * c->U[l] + g2 / sqrt(2.0);
+  if (c->round_fp32) {
+    for (int m = 0; m < 3; ++m) {
+      x[m] = (double)(float)x[m];
+      wv[m] = (double)(float)wv[m];
+    }
+  }
+  if (mu_out) *mu_out = c->U[k] * n_k;
+}
+
 static void orc_seed_one(const orc_consts* c, uint64_t pid, double x[3], double wv[3], double* mu_out) {
   uint32_t r0[4], r1[4];
   orc_stream(c->seed, pid, 0u, r0);
   orc_stream(c->seed, pid, 1u, r1);
+  if (c->box) {
+    orc_seed_box(c, r0, r1, x, wv, mu_out);
+    return;
+  }
   double u0 = u64_of(r0[0]), u1 = u64_of(r0[1]), u2 = u64_of(r0[2]), u3 = u64_of(r0[3]);
   double u4 = u64_of(r1[0]);
 

@@ -33,6 +33,8 @@ typedef struct {
   int32_t round_fp32;        /* 1: round seeded x, w to FP32 before tracing */
   double cv_center[3];       /* control-volume centre (used when cv_radius > 0) */
   double cv_radius;          /* <= 0: bounding sphere of the vertices times (1 + 1e-3) */
+  int32_t cv_box;            /* 1: the CV is an axis-aligned box of the body frame (see orc_setup) */
+  int32_t pad_;
 } orc_query;
 
 /* Per-query constants derived in FP64 (Sec. III.A.1, III.A.3). */
@@ -46,6 +48,10 @@ typedef struct {
   uint32_t rmax;
   int32_t round_fp32;
   int32_t s_zero;            /* 1 when S is treated as exactly zero */
+  int32_t box;               /* box CV: faces f = 2k (outward -e_k) and 2k + 1 (outward +e_k) */
+  double h[3];               /* box half-extents */
+  double face_s[6];          /* s_f = S U.n_f, n_f the inward normal of face f */
+  double face_cum[6];        /* cumulative A_f chi(s_f), f = 0..5 */
 } orc_consts;
 
 /* Running sums over a particle range.  D is the per-particle momentum given to

@@ -345,3 +345,110 @@ def test_pratt_concave_hemisphere(orc):
     # faceting of the 4512-triangle cup biases eps_D by a few 1e-3
     assert abs(eps - paper["pratt_eps_D_90deg"]["value"]) < 4 * sig + 6e-3
     assert res[0]["CD"] == pytest.approx(2.0, abs=0.01)
+
+
+# ---------------------------------------------------------------------------
+# box control volume
+# ---------------------------------------------------------------------------
+
+
+def _box_rejection_seeds(S, U, c0, h, n, rng):
+    """Independent sampler of the inflow through a box: w from the drifting
+    Maxwellian, a face with probability proportional to its area, accepted
+    with probability (w . n_in)+ / M, then a uniform point on that face."""
+    xs, ws, fs = [], [], []
+    M = S + 7.0
+    area = np.array([4 * h[(k + 1) % 3] * h[(k + 2) % 3] for k in range(3) for _ in (0, 1)])
+    while sum(len(a) for a in ws) < n:
+        m = 8 * n
+        w = S * U + rng.normal(0.0, math.sqrt(0.5), size=(m, 3))
+        f = rng.choice(6, size=m, p=area / area.sum())
+        k = f // 2
+        n_k = np.where(f % 2 == 0, 1.0, -1.0)
+        wn = w[np.arange(m), k] * n_k
+        keep = rng.random(m) * M < wn
+        w, f, k, n_k = w[keep], f[keep], k[keep], n_k[keep]
+        x = c0 + (2 * rng.random((len(w), 3)) - 1) * h
+        x[np.arange(len(w)), k] = c0[k] - n_k * h[k]
+        xs.append(x)
+        ws.append(w)
+        fs.append(f)
+    return np.concatenate(xs)[:n], np.concatenate(ws)[:n], np.concatenate(fs)[:n]
+
+
+def _box_faces(x, c0, h):
+    d = np.abs(x - c0) / h
+    k = np.argmax(d, axis=1)
+    side = x[np.arange(len(x)), k] > c0[k]
+    return 2 * k + side.astype(int), d
+
+
+@pytest.mark.parametrize("S", [0.7, 5.0])
+def test_box_seeds_match_rejection_sampler(orc, S):
+    """Box CV: every seed lies on the box surface and enters it; the face
+    shares, the normal and tangential velocity components, the speed and the
+    position on the face agree with an independent rejection sampler of the
+    same inflow (two-sample KS, chi-square on the faces)."""
+    V, T = I.icosphere(1)
+    q = I.query(q=tuple(I.random_quats(1, 8)[0]), S=S, n=40000, seed=9, cv_radius=1.3,
+                cv_center=(0.1, 0.0, -0.2), cv_box=True)
+    x, w, _ = orc.seed(V, q, round_fp32=False)
+    c0, h = np.array([0.1, 0.0, -0.2]), np.full(3, 1.3)
+    f, d = _box_faces(x, c0, h)
+    assert np.allclose(d.max(axis=1), 1.0, atol=1e-12) and (d <= 1.0 + 1e-12).all()
+    k = f // 2
+    n_k = np.where(f % 2 == 0, 1.0, -1.0)
+    assert (w[np.arange(len(w)), k] * n_k > 0).all()
+    U = I.flow_dir(q["q"])
+    xr, wr, fr = _box_rejection_seeds(S, U, c0, h, 40000, np.random.default_rng(4))
+    cnt = np.bincount(f, minlength=6).astype(float)
+    cnt_r = np.bincount(fr, minlength=6).astype(float)
+    use = (cnt + cnt_r) > 20
+    assert stats.chi2_contingency(np.stack([cnt[use], cnt_r[use]])).pvalue > 1e-3
+    for a, b in ((w @ U, wr @ U), (np.linalg.norm(w, axis=1), np.linalg.norm(wr, axis=1)),
+                 (w[np.arange(len(w)), k] * n_k, wr[np.arange(len(wr)), fr // 2] * np.where(fr % 2 == 0, 1.0, -1.0)),
+                 (x[:, 0], xr[:, 0]), (x[:, 2], xr[:, 2])):
+        assert stats.ks_2samp(a, b).pvalue > 1e-3
+
+
+def test_box_gamma_hat_is_the_face_flux_integral(orc):
+    """Gamma_hat of a box = sum over faces of area x the one-sided flux of the
+    drifting Maxwellian, integrated here numerically from the normal-velocity
+    marginal exp(-(x - s)^2)/sqrt(pi); at S = 0 it is the surface area over
+    2 sqrt(pi)."""
+    V, T = I.capped_cylinder()
+    for S in (0.0, 0.8, 4.0):
+        q = I.query(q=tuple(I.random_quats(1, 12)[0]), S=S, n=10, cv_box=True)
+        c = orc.consts_dict(orc.setup(V, q))
+        h = np.array(c["h"])
+        U = np.array(c["U"])
+        tot = 0.0
+        for f in range(6):
+            kk = f // 2
+            n_k = 1.0 if f % 2 == 0 else -1.0
+            s = S * U[kk] * n_k
+            flux = integrate.quad(lambda x: x * math.exp(-(x - s) ** 2) / math.sqrt(math.pi), 0, s + 40 if s > 0 else 40)[0]
+            tot += 4 * h[(kk + 1) % 3] * h[(kk + 2) % 3] * flux
+        assert c["Gamma_hat"] == pytest.approx(tot, rel=1e-9)
+        if S == 0.0:
+            area = 8 * (h[0] * h[1] + h[1] * h[2] + h[2] * h[0])
+            assert c["Gamma_hat"] == pytest.approx(area / (2 * math.sqrt(math.pi)), rel=1e-12)
+        # the widened vertex box: vertex half-extents plus 1e-3 of the half-diagonal
+        assert np.allclose(h, np.array([0.5, 0.5, 0.5]) + 1e-3 * math.sqrt(0.75), rtol=1e-6)
+
+
+def test_box_cv_invariance(orc):
+    """CV-shape invariance, the paper's central claim: with a correct flux
+    sampler on a box (fitted to the body, or an offset cube) the drag equals
+    the sphere-CV drag and the per-facet exact value within the run's sigma."""
+    V, T = I.icosphere(2)
+    exact = CF.mesh_force(V, T, (1.0, 0.0, 0.0), 3.0, TAU, 1.0)[0][0] / math.pi
+    for kw in (dict(cv_box=True), dict(cv_box=True, cv_radius=1.6, cv_center=(0.2, -0.3, 0.1)), dict()):
+        q = I.query(S=3.0, n=80000, seed=41, **kw)
+        r = orc.run(V, T, q, A_ref=math.pi)
+        assert abs(r["CD"] - exact) < 3.5 * r["CD_sigma"], (kw, r["CD"], exact, r["CD_sigma"])
+    Vp, Tp = I.plate()
+    a = math.radians(30.0)
+    qp = I.query(q=I.quat_for_flow((math.sin(a), 0, -math.cos(a))), S=3.0, n=80000, seed=43, cv_box=True)
+    rp = orc.run(Vp, Tp, qp)
+    assert abs(rp["CD"] - CF.plate_cd(3.0, 30.0, TAU)) < 3.5 * rp["CD_sigma"]
