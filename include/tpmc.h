@@ -72,10 +72,22 @@ typedef struct {
   uint32_t flags;            /* TPMC_Q_* bits */
   double cv_center[3];       /* control-volume centre, used when cv_radius > 0 */
   double cv_radius;          /* CV radius (m); <= 0: centre = vertex-box centre, radius = largest
-                                vertex distance times (1 + 1e-3) */
+                                vertex distance times (1 + 1e-3).  With TPMC_Q_BOX_CV: the half-side
+                                of a cube about cv_center; <= 0: the vertex box widened on every
+                                axis by 1e-3 of its half-diagonal */
 } tpmc_query;
 
 #define TPMC_Q_NO_TRIANGLE_TALLY 1u /* batched path: keep only per-query totals */
+/* Seed on an axis-aligned box of the body frame instead of a sphere (the
+ * rectangular control volume of Sec. III.A, with the correct inflow): a face
+ * is chosen by its share A_f chi(s_f) of the inflow (s_f = S U.n_f, n_f its
+ * inward normal, chi(s) = e^{-s^2} + sqrt(pi) s (1 + erf s)), the point is
+ * uniform on it, the normal speed follows eq. vel_dist1 with S_n = s_f and the
+ * two tangential components are Gaussian (eqs. vel_dist2-3) about the
+ * tangential drift; Gamma_hat = sum_f A_f chi(s_f) / (2 sqrt(pi)).  Draws:
+ * face r0.a, position r0.b and r1.b, normal speed r0.c, Box-Muller r0.d and
+ * r1.a. */
+#define TPMC_Q_BOX_CV 2u
 
 /* Result of one query.  Force and moment are divided by the dynamic pressure
  * q = rho U^2 / 2 (so they are areas, m^2, and m^3); Fhat = F / (rho c_mp^2) is

@@ -165,7 +165,8 @@ static tpmc_status check_query_fields(const tpmc_query* q) {
     return fail(TPMC_E_INVALID, "n_particles = %llu outside [1, 2^40]", (unsigned long long)q->n_particles);
   if (q->max_reflections == 0 || q->max_reflections > (uint32_t)kMaxReflections)
     return fail(TPMC_E_INVALID, "max_reflections = %u outside [1, %d]", q->max_reflections, kMaxReflections);
-  if (q->flags & ~TPMC_Q_NO_TRIANGLE_TALLY) return fail(TPMC_E_INVALID, "unknown query flags 0x%x", q->flags);
+  if (q->flags & ~(TPMC_Q_NO_TRIANGLE_TALLY | TPMC_Q_BOX_CV))
+    return fail(TPMC_E_INVALID, "unknown query flags 0x%x", q->flags);
   if (!finite3(q->cv_center) || !std::isfinite(q->cv_radius))
     return fail(TPMC_E_INVALID, "control volume must be finite");
   return TPMC_OK;
@@ -173,6 +174,15 @@ static tpmc_status check_query_fields(const tpmc_query* q) {
 
 static tpmc_status check_cv(const tpmc_query* q, const float* xyz, uint64_t nv) {
   if (!(q->cv_radius > 0.0)) return TPMC_OK;
+  if (q->flags & TPMC_Q_BOX_CV) {
+    double worst = 0.0;  // largest |v_k - c_k| over vertices and axes
+    for (uint64_t i = 0; i < nv; ++i)
+      for (int k = 0; k < 3; ++k) worst = std::fmax(worst, std::fabs(xyz[3 * i + k] - q->cv_center[k]));
+    if (worst > q->cv_radius)
+      return fail(TPMC_E_CV, "control box (half-side %g) does not enclose the mesh (a vertex at %g on one axis)",
+                  q->cv_radius, worst);
+    return TPMC_OK;
+  }
   double worst = 0.0;
   for (uint64_t i = 0; i < nv; ++i) {
     const double a = xyz[3 * i] - q->cv_center[0], b = xyz[3 * i + 1] - q->cv_center[1],
@@ -217,7 +227,6 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
     for (int k = 0; k < 3; ++k) q->c0[k] = m->c0[k];
     q->r = m->r;
   }
-  for (int k = 0; k < 3; ++k) q->c0f[k] = (float)q->c0[k];
   const double S = in->S;
   q->S = S;
   q->s_zero = S < 1e-8 ? 1u : 0u;
@@ -229,6 +238,34 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   q->Z = q->s_zero ? 2.0 : q->expmS2 + sqrtpi * (S + 0.5 / S) * q->erfS;
   q->Gamma_hat = q->s_zero ? 2.0 * sqrtpi * q->r * q->r
                            : (sqrtpi * q->expmS2 + (pi / (2.0 * S) + pi * S) * q->erfS) * q->r * q->r;
+  if (in->flags & TPMC_Q_BOX_CV) {
+    // Box CV: the cube of half-side cv_radius, or the vertex box widened by 1e-3
+    // of its half-diagonal; inflow through face f = A_f chi(s_f) / (2 sqrt(pi)).
+    q->box = 1u;
+    if (in->cv_radius > 0.0) {
+      for (int k = 0; k < 3; ++k) q->h[k] = in->cv_radius;
+    } else {
+      double hd = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        q->h[k] = 0.5 * (m->hi[k] - m->lo[k]);
+        hd += q->h[k] * q->h[k];
+      }
+      hd = std::sqrt(hd);
+      for (int k = 0; k < 3; ++k) q->h[k] += 1e-3 * hd;
+    }
+    q->r = std::sqrt(q->h[0] * q->h[0] + q->h[1] * q->h[1] + q->h[2] * q->h[2]);  // lever bound
+    double cum = 0.0;
+    for (int f = 0; f < 6; ++f) {
+      const int k = f / 2, j = (k + 1) % 3, l = (k + 2) % 3;
+      const double n_k = f % 2 == 0 ? 1.0 : -1.0;
+      const double s_f = q->s_zero ? 0.0 : S * U[k] * n_k;
+      q->face_s[f] = s_f;
+      cum += 4.0 * q->h[j] * q->h[l] * (std::exp(-s_f * s_f) + sqrtpi * s_f * std::erfc(-s_f));
+      q->face_cum[f] = cum;
+    }
+    q->Gamma_hat = cum / (2.0 * sqrtpi);
+  }
+  for (int k = 0; k < 3; ++k) q->c0f[k] = (float)q->c0[k];
   const double tau = std::sqrt(in->T_w / in->T_inf);
   q->tau = (float)tau;
   q->alpha = (float)in->alpha;

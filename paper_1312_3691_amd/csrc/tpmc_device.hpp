@@ -352,35 +352,70 @@ __device__ inline double sample_normal_speed(const float* __restrict__ tab, cons
 }
 
 // One seeded particle (Sec. III.A.1-3): position on the CV and velocity, FP64.
+// Both control volumes give a point x, an inward unit normal n, unit tangents
+// t1, t2, a tangential drift (d1, d2) and the normal drift s_n; the normal
+// speed (eq. vel_dist1) and the Gaussian tangentials (eqs. vel_dist2-3) are
+// drawn the same way, w = w_n n + (d1 + g1/sqrt2) t1 + (d2 + g2/sqrt2) t2.
+//  * Sphere: mu = sin(phi) from g(phi|S), theta uniform; n = mu U - cos(phi) c
+//    with c = cos(th) e1 + sin(th) e2, t1 = cos(phi) U + mu c (along the
+//    tangential part of U), t2 = t1 x n = sin(th) e1 - cos(th) e2;
+//    x = c0 - r n; d1 = S cos(phi), d2 = 0; s_n = S mu.
+//  * Box (query flag): face f by its share A_f chi(s_f) of the inflow, a
+//    uniform point on it; n = n_a e_a (a = f/2, n_a = +1 on the low face),
+//    t1 = e_j, t2 = e_l (j = a+1, l = a+2 mod 3); d1 = S U_j, d2 = S U_l;
+//    s_n = s_f.
+// Only the few scalars that fix the frame stay live across the normal-speed
+// solve (the frame is expanded afterwards), which keeps the persistent kernel
+// inside its register budget.
 __device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ lat_tab,
                                      const float* __restrict__ vn_tab, uint64_t pid, double x[3], double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
-  LatEval le;
-  const double mu = sample_latitude(q, lat_tab, unif64(r0.a), le);
-  const double cphi = sqrt(fmax(0.0, 1.0 - mu * mu));
-  double sth, cth;
-  sincospi(2.0 * unif64(r0.b), &sth, &cth);
-  // inward normal n = mu U - cos(phi) c with c = cos(th) e1 + sin(th) e2; tangent
-  // t1 = cos(phi) U + mu c (unit, along the tangential part of U); t2 = t1 x n = -d,
-  // d = -sin(th) e1 + cos(th) e2.  x = c0 - r n.
-  const double s_n = q.S * mu;
-  const NormalSpeedConsts k =
-      le.valid ? normal_speed_consts_near(s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(s_n);
+  double p0, p1, p2, p3;  // sphere: mu, cos(phi), sin(th), cos(th); box: n_a, position on the face (2)
+  int fa = 0;             // box: the face's normal axis
+  NormalSpeedConsts k;
+  if (q.box) {
+    const double t = unif64(r0.a) * q.face_cum[5];
+    int f = 0;
+    while (f < 5 && !(t < q.face_cum[f])) ++f;
+    fa = f >> 1;
+    p0 = (f & 1) ? -1.0 : 1.0;
+    p1 = 2.0 * unif64(r0.b) - 1.0;
+    p2 = 2.0 * unif64(r1.b) - 1.0;
+    p3 = 0.0;
+    k = normal_speed_consts(q.face_s[f]);
+  } else {
+    LatEval le;
+    p0 = sample_latitude(q, lat_tab, unif64(r0.a), le);
+    p1 = sqrt(fmax(0.0, 1.0 - p0 * p0));
+    sincospi(2.0 * unif64(r0.b), &p2, &p3);
+    const double s_n = q.S * p0;
+    k = le.valid ? normal_speed_consts_near(s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(s_n);
+  }
   const double wn = sample_normal_speed(vn_tab, k, unif64(r0.c));
   const double rad = sqrt(-2.0 * log_draw(r0.d));  // ln unif64(r0.d)
   double sb, cb;
   sincospi(2.0 * unif64(r1.a), &sb, &cb);
-  const double wt1 = q.S * cphi + rad * cb * kInvSqrt2;
-  const double wt2 = rad * sb * kInvSqrt2;
+  const double g1 = rad * cb * kInvSqrt2, g2 = rad * sb * kInvSqrt2;
+  if (q.box) {
+    const int j = fa == 2 ? 0 : fa + 1;  // t1 axis; the remaining axis is t2's
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const double ck = cth * q.e1[k] + sth * q.e2[k];
-    const double dk = -sth * q.e1[k] + cth * q.e2[k];
-    const double nk = mu * q.U[k] - cphi * ck;
-    const double t1k = cphi * q.U[k] + mu * ck;
-    x[k] = q.c0[k] - q.r * nk;
-    w[k] = wn * nk + wt1 * t1k - wt2 * dk;
+    for (int i = 0; i < 3; ++i) {
+      x[i] = i == fa ? q.c0[i] - p0 * q.h[i] : q.c0[i] + (i == j ? p1 : p2) * q.h[i];
+      w[i] = i == fa ? wn * p0 : q.S * q.U[i] + (i == j ? g1 : g2);
+    }
+  } else {
+    const double mu = p0, cphi = p1, sth = p2, cth = p3;
+    const double wt1 = q.S * cphi + g1;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const double ci = cth * q.e1[i] + sth * q.e2[i];
+      const double di = -sth * q.e1[i] + cth * q.e2[i];
+      const double ni = mu * q.U[i] - cphi * ci;
+      const double t1i = cphi * q.U[i] + mu * ci;
+      x[i] = q.c0[i] - q.r * ni;
+      w[i] = wn * ni + wt1 * t1i - g2 * di;
+    }
   }
 }
 

@@ -46,7 +46,11 @@ struct alignas(16) QueryDev {
   uint32_t s_zero;                   // S treated as exactly 0
   uint32_t per_tri;                  // per-triangle tallies kept
   uint32_t nt;                       // triangles of the query's mesh
-  uint32_t pad_[2];
+  uint32_t box;                      // box control volume (faces f = 2k: outward -e_k, 2k + 1: +e_k)
+  uint32_t pad_;
+  double h[3];                       // box half-extents
+  double face_s[6];                  // s_f = S U.n_f, n_f the inward normal of face f
+  double face_cum[6];                // cumulative A_f chi(s_f)
 };
 
 // Device result of the finalisation kernel (mirrors tpmc_result).

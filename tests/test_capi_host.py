@@ -91,6 +91,14 @@ def test_query_attitude_and_cv(T):
     assert _status(lambda: T.check_query(I.query(cv_radius=1.01), V)) == 0
     assert _status(lambda: T.check_query(I.query(cv_radius=1.01, cv_center=(0.2, 0, 0)), V)) == 3
     assert _status(lambda: T.check_query(I.query(cv_radius=1.01, cv_center=(0, float("nan"), 0)), V)) == 1
+    # box control volume: a cube of half-side cv_radius must contain every vertex
+    # (the unit icosphere fits a cube of half-side 1, not one offset by 0.2)
+    assert _status(lambda: T.check_query(I.query(cv_box=True), V)) == 0
+    assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=1.0), V)) == 0
+    assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=0.99), V)) == 3
+    assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=1.1, cv_center=(0.2, 0, 0)), V)) == 3
+    assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=0.9, cv_center=(0.0, 0, 0)), V)) == 3
+    assert _status(lambda: T.check_query(I.query(flags=6), V)) == 1  # unknown bit next to the box flag
 
 
 def test_no_device_is_a_clean_error(T):

@@ -264,6 +264,63 @@ def test_moment_sweep_parity(ctx, T, pitch, yaw):
     assert np.allclose(np.asarray(r2["M_over_q"]), M2, rtol=1e-12, atol=1e-12 * scale)
 
 
+BOX_SEED_CASES = [
+    dict(S=3.0, q=tuple(I.random_quats(1, 21)[0]), n=20011),
+    dict(S=0.4, q=tuple(I.random_quats(1, 22)[0]), cv_radius=1.6, cv_center=(0.2, -0.3, 0.1), n=10007),
+    dict(S=0.0, q=(1.0, 0.0, 0.0, 0.0), n=5003),
+    dict(S=12.0, q=I.quat_for_flow((0.3, -0.4, 0.866)), n=10007),
+]
+
+
+@pytest.mark.parametrize("case", BOX_SEED_CASES, ids=[f"S{c['S']}" for c in BOX_SEED_CASES])
+def test_box_cv_seed_parity(ctx, T, case):
+    """Box control volume (rectangular CV row): seeds against the oracle's, as
+    for the sphere -- face choice, point and velocity."""
+    V, Tr = I.icosphere(2)
+    mesh = ctx.build_mesh(V, Tr)
+    q = I.query(seed=4321, cv_box=True, **case)
+    pr = T.PlainRun(mesh, [q]).seed()
+    planes = pr.planes()
+    _sync()
+    xg = np.stack([_np(p) for p in planes[:3]], axis=1)
+    wg = np.stack([_np(p) for p in planes[3:]], axis=1)
+    xo, wo, _ = O.seed(V, q, round_fp32=True)
+    xo, wo = xo.astype(np.float32), wo.astype(np.float32)
+    for g, o in ((xg, xo), (wg, wo)):
+        assert np.isfinite(g).all()
+        assert np.mean(g == o) >= 0.999, np.mean(g == o)
+        assert _ulp_ok(g, o).all(), np.argwhere(~_ulp_ok(g, o))[:5]
+    pr.close()
+
+
+def test_box_cv_trace_parity(ctx, T):
+    """Whole path with a box CV: icosphere (C1 conditions) and the plate,
+    against the oracle on the same seeds and against the closed forms (CV-shape
+    invariance); batched results equal the plain ones bit for bit."""
+    V, Tr = I.icosphere(3)
+    q = I.query(S=5.0, n=100_000, seed=0, cv_box=True)
+    g, o = _compare(ctx, T, V, Tr, q, A_ref=math.pi)
+    F, _, _ = CF.mesh_force(V, Tr, (1.0, 0, 0), 5.0, TAU, 1.0)
+    assert abs(g["CD"] - F[0] / math.pi) < 3.5 * g["CD_sigma"]
+    Vp, Tp = I.plate()
+    a = math.radians(30.0)
+    qp = I.query(q=I.quat_for_flow((math.sin(a), 0, -math.cos(a))), S=3.0, alpha=1.0, n=60_007, seed=8,
+                 cv_box=True)
+    gp, _ = _compare(ctx, T, Vp, Tp, qp)
+    assert abs(gp["CD"] - CF.plate_cd(3.0, 30.0, TAU)) < 3.5 * gp["CD_sigma"]
+    mesh = ctx.build_mesh(*I.capped_cylinder())
+    qs = [I.query(q=tuple(I.random_quats(1, 30 + i)[0]), S=S, alpha=0.5, n=50_003, seed=i, cv_box=box)
+          for i, (S, box) in enumerate(((2.0, True), (7.0, True), (7.0, False), (0.5, True)))]
+    plain, pr = T.run(mesh, qs, A_ref=1.0)
+    pr.close()
+    b = T.Batch(mesh, qs)
+    batched = b.launch(use_graph=True).results(A_ref=1.0)
+    b.close()
+    for p_, b_ in zip(plain, batched):
+        for k in p_:
+            assert np.array_equal(np.asarray(p_[k]), np.asarray(b_[k])), k
+
+
 def test_edge_cases(ctx, T):
     """N = 1, a single-triangle mesh, max_reflections = 1, S = 0."""
     V, Tr = I.plate()
