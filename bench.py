@@ -309,6 +309,46 @@ def workload_pratt(args):
            "segments_per_s": sum(r["segments"] for r in res) / dt, "bvh_build_ms": build_ms, "tuning": tuning})
 
 
+def workload_boxcv(args):
+    """Control-volume shape invariance (Sec. III.A): the 1280-triangle
+    icosphere at S = 5, diffuse, seeded on the sphere CV, on the vertex box
+    widened by 1e-3 and on an offset cube, 1e8 particles each in one batched
+    launch; each C_D against the per-facet exact value (stored from the closed
+    forms in tests/golden/closed_forms.json)."""
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    ctx = tpmc.Context(0)
+    V, T = I.icosphere(3)
+    mesh = ctx.build_mesh(V, T, builder=args.bvh)
+    n = int(args.particles_boxcv)
+    cvs = (("sphere r=1.001", dict(cv_radius=1.001)), ("fitted box", dict(cv_box=True)),
+           ("cube half-side 1.6, offset (0.2,-0.3,0.1)", dict(cv_box=True, cv_radius=1.6, cv_center=(0.2, -0.3, 0.1))))
+    qs = [I.query(S=5.0, T_inf=T_INF, T_w=T_W, alpha=1.0, n=n, seed=i, **kw) for i, (_, kw) in enumerate(cvs)]
+    tuning = tune_for(args, mesh, qs)
+    b = tpmc.Batch(mesh, qs)
+    b.launch().results(A_ref=math.pi)
+    for _ in range(args.warmup):
+        b.launch(use_graph=True).results(A_ref=math.pi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = b.launch(use_graph=True).results(A_ref=math.pi)
+    dt = (time.perf_counter() - t0) / args.steps
+    b.close()
+    exact = json.load(open(os.path.join(ROOT, "tests", "golden", "closed_forms.json")))["icosphere3_S5"]["cd_facet"]
+    rows = [{"cv": name, "CD": r["CD"], "CD_sigma": r["CD_sigma"], "err_over_sigma": (r["CD"] - exact) / r["CD_sigma"],
+             "Gamma_hat": r["Gamma_hat"], "hits_per_particle": r["hits"] / n} for (name, _), r in zip(cvs, res)]
+    hits = sum(r["hits"] for r in res)
+    _line("particle-surface hits/sec on 1 MI355X (control-volume shape invariance)", hits / dt, "hits/s", dt,
+          args.steps, args.warmup,
+          {"workload": f"icosphere {len(T)} tris, S=5, alpha=1, sphere / fitted box / offset cube CV, {n} particles each",
+           "path": "one batched persistent launch, graph replay", "bvh": args.bvh},
+          {"cases": rows, "CD_exact_per_facet": exact, "segments_per_s": sum(r["segments"] for r in res) / dt,
+           "tuning": tuning})
+
+
 MOMENT_PITCH = tuple(range(-40, 41, 10))
 MOMENT_YAW = (-20, 0, 20)
 
@@ -535,12 +575,13 @@ def main():
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
     ap.add_argument("--workload", default="plate-cylinder",
-                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments"],
+                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv"],
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
     ap.add_argument("--particles-pratt", type=float, default=1e7)
     ap.add_argument("--particles-moments", type=float, default=4e6)
+    ap.add_argument("--particles-boxcv", type=float, default=1e8)
     ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
     ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
     ap.add_argument("--slots", type=int, default=64, help="served: request slots")
@@ -568,7 +609,7 @@ def main():
         sys.exit(2)
     if args.workload != "plate-cylinder":
         {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served,
-         "pratt": workload_pratt, "moments": workload_moments}[args.workload](args)
+         "pratt": workload_pratt, "moments": workload_moments, "boxcv": workload_boxcv}[args.workload](args)
         return
 
     import torch
