@@ -27,6 +27,7 @@ _lib = None
 
 N_CHUNKS = 64
 BOX_CV_FLAG = 2  # query flag: box control volume
+ENERGY_ACC_FLAG = 4  # query flag: diffuse re-emission with energy accommodation alpha_E
 
 
 class OrcQuery(ctypes.Structure):
@@ -34,7 +35,7 @@ class OrcQuery(ctypes.Structure):
                 ("T_w", ctypes.c_double), ("alpha", ctypes.c_double), ("n_particles", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("max_reflections", ctypes.c_uint32), ("round_fp32", ctypes.c_int32),
                 ("cv_center", ctypes.c_double * 3), ("cv_radius", ctypes.c_double), ("cv_box", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("energy_acc", ctypes.c_int32), ("alpha_E", ctypes.c_double)]
 
 
 class OrcConsts(ctypes.Structure):
@@ -44,14 +45,16 @@ class OrcConsts(ctypes.Structure):
                 ("r", ctypes.c_double), ("N", ctypes.c_uint64), ("seed", ctypes.c_uint64),
                 ("rmax", ctypes.c_uint32), ("round_fp32", ctypes.c_int32), ("s_zero", ctypes.c_int32),
                 ("box", ctypes.c_int32), ("h", ctypes.c_double * 3), ("face_s", ctypes.c_double * 6),
-                ("face_cum", ctypes.c_double * 6)]
+                ("face_cum", ctypes.c_double * 6), ("eacc", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("alpha_E", ctypes.c_double)]
 
 
 class OrcScalars(ctypes.Structure):
     _fields_ = [("D", ctypes.c_double), ("D_c", ctypes.c_double), ("D2", ctypes.c_double),
                 ("D2_c", ctypes.c_double), ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64),
                 ("segments", ctypes.c_uint64), ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64),
-                ("capped", ctypes.c_uint64)]
+                ("capped", ctypes.c_uint64), ("E", ctypes.c_double), ("E_c", ctypes.c_double),
+                ("E2", ctypes.c_double), ("E2_c", ctypes.c_double)]
 
 
 class OrcResult(ctypes.Structure):
@@ -59,7 +62,8 @@ class OrcResult(ctypes.Structure):
                 ("Fhat", ctypes.c_double * 3), ("CD", ctypes.c_double), ("CD_sigma", ctypes.c_double),
                 ("Gamma_hat", ctypes.c_double), ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64),
                 ("segments", ctypes.c_uint64), ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64),
-                ("capped", ctypes.c_uint64)]
+                ("capped", ctypes.c_uint64), ("Qhat", ctypes.c_double), ("CH", ctypes.c_double),
+                ("CH_sigma", ctypes.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -95,7 +99,7 @@ def lib():
             ip = ctypes.POINTER(ctypes.c_int32)
             L.orc_trace_range.argtypes = [dp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64,
                                           ctypes.POINTER(OrcConsts), ctypes.c_uint64, ctypes.c_uint64, dp, dp,
-                                          ctypes.POINTER(OrcScalars), ip, ip, dp]
+                                          ctypes.POINTER(OrcScalars), ip, ip, dp, dp]
             L.orc_trace_range.restype = ctypes.c_int
             L.orc_finalize.argtypes = [ctypes.POINTER(OrcConsts), dp, ctypes.c_uint64, ctypes.POINTER(OrcScalars),
                                        dp, ctypes.c_double, ctypes.POINTER(OrcResult)]
@@ -125,6 +129,8 @@ def make_query(qd: dict, round_fp32: bool = True) -> OrcQuery:
     q.cv_center[:] = [float(v) for v in qd.get("cv_center", (0.0, 0.0, 0.0))]
     q.cv_radius = float(qd.get("cv_radius", 0.0))
     q.cv_box = 1 if int(qd.get("flags", 0)) & BOX_CV_FLAG else 0
+    q.energy_acc = 1 if int(qd.get("flags", 0)) & ENERGY_ACC_FLAG else 0
+    q.alpha_E = float(qd.get("alpha_E", 1.0))
     return q
 
 
@@ -203,6 +209,7 @@ def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int 
     first = np.full(n, -1, np.int32) if per_particle else None
     nh = np.zeros(n, np.int32) if per_particle else None
     Dp = np.zeros(n) if per_particle else None
+    Ep = np.zeros(n) if per_particle else None
 
     def work(i):
         a, b = bounds[i], bounds[i + 1]
@@ -213,8 +220,9 @@ def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int 
         fptr = first[a - p0:].ctypes.data_as(ip) if per_particle else None
         hptr = nh[a - p0:].ctypes.data_as(ip) if per_particle else None
         dptr = _dp(Dp[a - p0:]) if per_particle else None
+        eptr = _dp(Ep[a - p0:]) if per_particle else None
         L.orc_trace_range(_dp(Vd), Vd.shape[0], Ti.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), nt,
-                          ctypes.byref(c), a, b, _dp(ts), _dp(tc), ctypes.byref(sc), fptr, hptr, dptr)
+                          ctypes.byref(c), a, b, _dp(ts), _dp(tc), ctypes.byref(sc), fptr, hptr, dptr, eptr)
         return ts + tc, sc
 
     nthreads = threads or min(os.cpu_count() or 1, 16)
@@ -222,8 +230,9 @@ def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int 
         parts = list(ex.map(work, range(k)))
     tri = _neumaier_merge([p[0] for p in parts])
     tot = OrcScalars()
-    Ds = _neumaier_merge([np.array([p[1].D + p[1].D_c, p[1].D2 + p[1].D2_c]) for p in parts])
-    tot.D, tot.D2 = float(Ds[0]), float(Ds[1])
+    Ds = _neumaier_merge([np.array([p[1].D + p[1].D_c, p[1].D2 + p[1].D2_c, p[1].E + p[1].E_c, p[1].E2 + p[1].E2_c])
+                          for p in parts])
+    tot.D, tot.D2, tot.E, tot.E2 = float(Ds[0]), float(Ds[1]), float(Ds[2]), float(Ds[3])
     for f in ("rays", "hits", "segments", "missed", "escaped", "capped"):
         setattr(tot, f, sum(getattr(p[1], f) for p in parts))
     res = OrcResult()
@@ -234,5 +243,5 @@ def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int 
     out.update(tri=tri.reshape(nt, 7), D_sum=tot.D, D2_sum=tot.D2, consts=consts_dict(c),
                threads=nthreads)
     if per_particle:
-        out.update(first_tri=first, nhits=nh, D=Dp)
+        out.update(first_tri=first, nhits=nh, D=Dp, E=Ep)
     return out

@@ -189,6 +189,8 @@ int orc_setup(const orc_query* q, const double* V, uint64_t nv, orc_consts* c) {
   c->seed = q->seed;
   c->rmax = q->max_reflections;
   c->round_fp32 = q->round_fp32;
+  c->eacc = q->energy_acc ? 1 : 0;
+  c->alpha_E = q->energy_acc ? q->alpha_E : 1.0;
 
   if (q->cv_box) {
     /* Box control volume (the rectangular CV of Sec. III.A, seeded correctly):
@@ -379,10 +381,20 @@ void orc_reflect(const orc_consts* c, uint64_t pid, uint32_t b, const double w_i
     double bb = ns[0] * ns[1] * aa;
     double b1[3] = {1.0 + sign * ns[0] * ns[0] * aa, sign * bb, -sign * ns[0]};
     double b2[3] = {bb, sign + ns[1] * ns[1] * aa, -ns[1]};
-    double vn = c->tau * sqrt(-log(ub));
+    /* With energy accommodation alpha_E (the "momentum and energy" exchange of
+     * Sec. I; Sentman's definition alpha_E = (E_i - E_r)/(E_i - E_w)), the
+     * molecule leaves diffusely at the temperature whose flux-weighted mean
+     * energy 2kT_r is E_r = (1 - alpha_E) E_i + alpha_E 2kT_w, i.e.
+     * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 per molecule. */
+    double tr = c->tau;
+    if (c->eacc) {
+      double e_in = w_in[0] * w_in[0] + w_in[1] * w_in[1] + w_in[2] * w_in[2];
+      tr = sqrt(c->alpha_E * c->tau * c->tau + (1.0 - c->alpha_E) * 0.5 * e_in);
+    }
+    double vn = tr * sqrt(-log(ub));
     double rad = sqrt(-2.0 * log(uc));
     double g1 = rad * cos(2.0 * ORC_PI * ud), g2 = rad * sin(2.0 * ORC_PI * ud);
-    double v1 = c->tau * g1 / sqrt(2.0), v2 = c->tau * g2 / sqrt(2.0);
+    double v1 = tr * g1 / sqrt(2.0), v2 = tr * g2 / sqrt(2.0);
     for (int k = 0; k < 3; ++k) w_out[k] = vn * ns[k] + v1 * b1[k] + v2 * b2[k];
   } else {
     /* Specular: mirror the normal component. */
@@ -436,14 +448,14 @@ static void tri_verts(const double* V, const uint32_t* T, uint64_t k, double v0[
 int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt,
                     const orc_consts* c, uint64_t p0, uint64_t p1,
                     double* tri_sum, double* tri_comp, orc_scalars* sc,
-                    int32_t* first_tri, int32_t* nhits, double* Dp) {
+                    int32_t* first_tri, int32_t* nhits, double* Dp, double* Ep) {
   (void)nv;
   for (uint64_t pid = p0; pid < p1; ++pid) {
     double o[3], w[3];
     orc_seed_one(c, pid, o, w, 0);
     int64_t prev = -1;
     uint32_t hits = 0;
-    double D = 0.0;
+    double D = 0.0, E = 0.0;
     int32_t first = -1;
     sc->rays += 1;
     for (;;) {
@@ -490,6 +502,8 @@ int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt
       for (int k = 0; k < 3; ++k) { nsum(s + k, cc + k, dw[k]); nsum(s + 3 + k, cc + 3 + k, L[k]); }
       s[6] += 1.0;
       D += dw[0] * c->U[0] + dw[1] * c->U[1] + dw[2] * c->U[2];
+      /* energy given to the body by this hit, in units of m c_mp^2 / 2 */
+      E += (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) - (wout[0] * wout[0] + wout[1] * wout[1] + wout[2] * wout[2]);
       if (hits == 0) first = (int32_t)best;
       hits += 1;
       sc->hits += 1;
@@ -499,10 +513,13 @@ int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt
     }
     nsum(&sc->D, &sc->D_c, D);
     nsum(&sc->D2, &sc->D2_c, D * D);
+    nsum(&sc->E, &sc->E_c, E);
+    nsum(&sc->E2, &sc->E2_c, E * E);
     uint64_t i = pid - p0;
     if (first_tri) first_tri[i] = first;
     if (nhits) nhits[i] = (int32_t)hits;
     if (Dp) Dp[i] = D;
+    if (Ep) Ep[i] = E;
   }
   return 0;
 }
@@ -539,6 +556,16 @@ void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt, con
   if (varD < 0.0) varD = 0.0;
   out->CD_sigma = c->s_zero ? NAN : 2.0 * c->Gamma_hat / (c->S * c->S * A_ref) * sqrt(varD / N);
   out->Gamma_hat = c->Gamma_hat;
+  /* Energy: each particle carries the rate Gamma / N, so the power to the body
+   * is Q = n c_mp (m c_mp^2 / 2) (Gamma_hat / N) sum E; C_H = Q / (rho U^3 A_ref / 2)
+   * = Gamma_hat sum E / (N S^3 A_ref). */
+  double sumE = sc->E + sc->E_c;
+  double meanE = sumE / N;
+  double varE = (sc->E2 + sc->E2_c) / N - meanE * meanE;
+  if (varE < 0.0) varE = 0.0;
+  out->Qhat = c->Gamma_hat * meanE;
+  out->CH = c->s_zero ? NAN : c->Gamma_hat * meanE / (c->S * c->S * c->S * A_ref);
+  out->CH_sigma = c->s_zero ? NAN : c->Gamma_hat / (c->S * c->S * c->S * A_ref) * sqrt(varE / N);
   out->rays = sc->rays; out->hits = sc->hits; out->segments = sc->segments;
   out->missed = sc->missed; out->escaped = sc->escaped; out->capped = sc->capped;
 }

@@ -34,7 +34,8 @@ typedef struct {
   double cv_center[3];       /* control-volume centre (used when cv_radius > 0) */
   double cv_radius;          /* <= 0: bounding sphere of the vertices times (1 + 1e-3) */
   int32_t cv_box;            /* 1: the CV is an axis-aligned box of the body frame (see orc_setup) */
-  int32_t pad_;
+  int32_t energy_acc;        /* 1: diffuse re-emission with energy accommodation alpha_E (orc_reflect) */
+  double alpha_E;            /* energy accommodation coefficient, [0, 1], used when energy_acc */
 } orc_query;
 
 /* Per-query constants derived in FP64 (Sec. III.A.1, III.A.3). */
@@ -52,6 +53,9 @@ typedef struct {
   double h[3];               /* box half-extents */
   double face_s[6];          /* s_f = S U.n_f, n_f the inward normal of face f */
   double face_cum[6];        /* cumulative A_f chi(s_f), f = 0..5 */
+  int32_t eacc;              /* energy accommodation on */
+  int32_t pad_;
+  double alpha_E;
 } orc_consts;
 
 /* Running sums over a particle range.  D is the per-particle momentum given to
@@ -59,12 +63,15 @@ typedef struct {
 typedef struct {
   double D, D_c, D2, D2_c;   /* Neumaier sums of D and D^2 */
   uint64_t rays, hits, segments, missed, escaped, capped;
+  double E, E_c, E2, E2_c;   /* Neumaier sums of the per-particle energy E = sum (|w|^2 - |w'|^2) and E^2 */
 } orc_scalars;
 
 typedef struct {
   double F_over_q[3], M_over_q[3], Fhat[3];
   double CD, CD_sigma, Gamma_hat;
   uint64_t rays, hits, segments, missed, escaped, capped;
+  double Qhat;               /* energy to the body per unit time / (n c_mp m c_mp^2 / 2) */
+  double CH, CH_sigma;       /* heat-transfer coefficient Q / (rho U^3 A_ref / 2) and its sigma */
 } orc_result;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11). */
@@ -102,7 +109,7 @@ int orc_intersect(const double o[3], const double d[3], const double v0[3],
 int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt,
                     const orc_consts* c, uint64_t p0, uint64_t p1,
                     double* tri_sum, double* tri_comp, orc_scalars* sc,
-                    int32_t* first_tri, int32_t* nhits, double* Dp);
+                    int32_t* first_tri, int32_t* nhits, double* Dp, double* Ep);
 
 /* Convert merged sums to force, moment and drag coefficient. */
 void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt,

@@ -303,18 +303,23 @@ def satellite(target_tris: int = 50_000, jitter_sigma: float = 1e-3, seed: int =
 
 
 BOX_CV = 2  # query flag: box control volume
+ENERGY_ACC = 4  # query flag: diffuse re-emission with energy accommodation alpha_E
 
 
 def query(q=(1.0, 0.0, 0.0, 0.0), S=5.0, T_inf=1000.0, T_w=300.0, alpha=1.0, n=100_000, seed=0,
-          max_reflections=16, cv_center=(0.0, 0.0, 0.0), cv_radius=0.0, flags=0, cv_box=False) -> dict:
+          max_reflections=16, cv_center=(0.0, 0.0, 0.0), cv_radius=0.0, flags=0, cv_box=False,
+          alpha_E=None) -> dict:
     """A drag query as a plain dict (both the GPU binding and the oracle wrapper
     accept it).  ``cv_radius <= 0`` asks for the automatic bounding sphere;
     ``cv_box`` seeds on an axis-aligned box instead (the cube of half-side
-    ``cv_radius`` about ``cv_center``, or the widened vertex box)."""
+    ``cv_radius`` about ``cv_center``, or the widened vertex box); ``alpha_E``
+    (when given) is the energy accommodation of diffuse re-emission (full, 1,
+    otherwise)."""
     return dict(q=tuple(float(v) for v in q), S=float(S), T_inf=float(T_inf), T_w=float(T_w),
                 alpha=float(alpha), n=int(n), seed=int(seed), max_reflections=int(max_reflections),
                 cv_center=tuple(float(v) for v in cv_center), cv_radius=float(cv_radius),
-                flags=int(flags) | (BOX_CV if cv_box else 0))
+                flags=int(flags) | (BOX_CV if cv_box else 0) | (ENERGY_ACC if alpha_E is not None else 0),
+                alpha_E=float(1.0 if alpha_E is None else alpha_E))
 
 
 def plate_cases(angles_deg=range(0, 91, 10), S_values=(1.0, 3.0, 8.0), n=10_000_000):
