@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 3
+#define TPMC_ABI_VERSION 4
 
 typedef enum {
   TPMC_OK = 0,
@@ -75,6 +75,7 @@ typedef struct {
                                 vertex distance times (1 + 1e-3).  With TPMC_Q_BOX_CV: the half-side
                                 of a cube about cv_center; <= 0: the vertex box widened on every
                                 axis by 1e-3 of its half-diagonal */
+  double energy_accommodation; /* alpha_E in [0, 1], read only with TPMC_Q_ENERGY_ACC (else 1) */
 } tpmc_query;
 
 #define TPMC_Q_NO_TRIANGLE_TALLY 1u /* batched path: keep only per-query totals */
@@ -88,6 +89,15 @@ typedef struct {
  * face r0.a, position r0.b and r1.b, normal speed r0.c, Box-Muller r0.d and
  * r1.a. */
 #define TPMC_Q_BOX_CV 2u
+/* Diffuse re-emission with incomplete energy accommodation ("momentum and
+ * energy" exchange, Sec. I): with alpha_E = (E_i - E_r) / (E_i - E_w) (Sentman)
+ * and E = 2kT the flux-weighted mean energy of a re-emitted Maxwellian, a
+ * molecule of incident velocity w leaves diffusely at the temperature
+ * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 (units of T_inf),
+ * capped at max(tau^2, (S + 15)^2 / 2) so that every speed stays bounded (the
+ * cap binds only after an extreme re-emission variate).  alpha_E = 1 is the
+ * default model. */
+#define TPMC_Q_ENERGY_ACC 4u
 
 /* Result of one query.  Force and moment are divided by the dynamic pressure
  * q = rho U^2 / 2 (so they are areas, m^2, and m^3); Fhat = F / (rho c_mp^2) is
@@ -102,6 +112,8 @@ typedef struct {
   uint64_t missed;   /* particles that never hit */
   uint64_t escaped;  /* particles that hit at least once and then left */
   uint64_t capped;   /* particles retired at max_reflections */
+  double Qhat;       /* energy given to the body per unit time / (n c_mp m c_mp^2 / 2) */
+  double CH, CH_sigma; /* heat-transfer coefficient Q / (rho U^3 A_ref / 2) and its sigma (NaN at S = 0) */
 } tpmc_result;
 
 typedef struct {

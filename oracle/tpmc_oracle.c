@@ -385,11 +385,15 @@ void orc_reflect(const orc_consts* c, uint64_t pid, uint32_t b, const double w_i
      * Sec. I; Sentman's definition alpha_E = (E_i - E_r)/(E_i - E_w)), the
      * molecule leaves diffusely at the temperature whose flux-weighted mean
      * energy 2kT_r is E_r = (1 - alpha_E) E_i + alpha_E 2kT_w, i.e.
-     * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 per molecule. */
+     * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 per molecule, capped at
+     * max(tau^2, (S + 15)^2 / 2) so that speeds stay bounded over repeated
+     * re-emissions (the cap binds only after an extreme variate). */
     double tr = c->tau;
     if (c->eacc) {
       double e_in = w_in[0] * w_in[0] + w_in[1] * w_in[1] + w_in[2] * w_in[2];
-      tr = sqrt(c->alpha_E * c->tau * c->tau + (1.0 - c->alpha_E) * 0.5 * e_in);
+      double tr2 = c->alpha_E * c->tau * c->tau + (1.0 - c->alpha_E) * 0.5 * e_in;
+      double cap2 = fmax(c->tau * c->tau, 0.5 * (c->S + 15.0) * (c->S + 15.0));
+      tr = sqrt(tr2 < cap2 ? tr2 : cap2);
     }
     double vn = tr * sqrt(-log(ub));
     double rad = sqrt(-2.0 * log(uc));

@@ -165,8 +165,11 @@ static tpmc_status check_query_fields(const tpmc_query* q) {
     return fail(TPMC_E_INVALID, "n_particles = %llu outside [1, 2^40]", (unsigned long long)q->n_particles);
   if (q->max_reflections == 0 || q->max_reflections > (uint32_t)kMaxReflections)
     return fail(TPMC_E_INVALID, "max_reflections = %u outside [1, %d]", q->max_reflections, kMaxReflections);
-  if (q->flags & ~(TPMC_Q_NO_TRIANGLE_TALLY | TPMC_Q_BOX_CV))
+  if (q->flags & ~(TPMC_Q_NO_TRIANGLE_TALLY | TPMC_Q_BOX_CV | TPMC_Q_ENERGY_ACC))
     return fail(TPMC_E_INVALID, "unknown query flags 0x%x", q->flags);
+  if ((q->flags & TPMC_Q_ENERGY_ACC) &&
+      (!std::isfinite(q->energy_accommodation) || q->energy_accommodation < 0.0 || q->energy_accommodation > 1.0))
+    return fail(TPMC_E_INVALID, "energy accommodation %g outside [0, 1]", q->energy_accommodation);
   if (!finite3(q->cv_center) || !std::isfinite(q->cv_radius))
     return fail(TPMC_E_INVALID, "control volume must be finite");
   return TPMC_OK;
@@ -282,7 +285,13 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   // |w| <= S + 15 for seeded and specular velocities and |w| <= 8 tau after a
   // diffuse re-emission, so one hit moves at most Dmax; scales are the largest
   // powers of two keeping N * rmax hits of Dmax inside 2^62.
-  const double Dmax = 2.0 * std::fmax(S + 15.0, 8.0 * tau);
+  // With energy accommodation a re-emitted speed is at most ~7.1 tau_r, and
+  // tau_r^2 <= max(tau^2, (S + 15)^2 / 2) (the cap), so every |w| stays below
+  // B = max(8 tau, 5 (S + 15)).
+  q->eacc = (in->flags & TPMC_Q_ENERGY_ACC) ? 1u : 0u;
+  q->alpha_E = q->eacc ? (float)in->energy_accommodation : 1.0f;
+  q->tr_cap2 = (float)std::fmax(tau * tau, 0.5 * (S + 15.0) * (S + 15.0));
+  const double Dmax = q->eacc ? 2.0 * std::fmax(8.0 * tau, 5.0 * (S + 15.0)) : 2.0 * std::fmax(S + 15.0, 8.0 * tau);
   const double hits_max = (double)in->n_particles * (double)in->max_reflections;
   const double sF = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax)), std::ldexp(1.0, 50));
   const double sL = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax * q->r * 1.01)), std::ldexp(1.0, 50));
@@ -297,6 +306,16 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   q->inv_scaleL = 1.0 / sL;
   q->inv_scaleD = 1.0 / sF;
   q->inv_scaleD2 = 1.0 / sD2;
+  // energy per hit |w|^2 - |w'|^2 is at most (Dmax / 2)^2 in magnitude
+  const double Emax = 0.25 * Dmax * Dmax;
+  const double sE = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Emax)), std::ldexp(1.0, 50));
+  const double pE = (double)in->max_reflections * Emax;
+  const double sE2 = std::fmin(pow2_floor(std::ldexp(1.0, 62) / ((double)in->n_particles * pE * pE)),
+                               std::ldexp(1.0, 50));
+  q->scaleE = (float)sE;
+  q->scaleE2 = (float)sE2;
+  q->inv_scaleE = 1.0 / sE;
+  q->inv_scaleE2 = 1.0 / sE2;
 }
 
 static tpmc_status make_queries(tpmc_mesh m, const tpmc_query* q, uint32_t nq, std::vector<QueryDev>& out) {
@@ -686,6 +705,9 @@ static void copy_result(const ResultDev& r, tpmc_result* o) {
   o->missed = r.missed;
   o->escaped = r.escaped;
   o->capped = r.capped;
+  o->Qhat = r.Qhat;
+  o->CH = r.CH;
+  o->CH_sigma = r.CH_sigma;
 }
 
 // Clears the per-query totals the reduction writes (slots kFx..kCount).

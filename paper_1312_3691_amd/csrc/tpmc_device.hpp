@@ -524,6 +524,13 @@ __device__ __forceinline__ void reemit(const QueryDev& q, uint64_t pid, uint32_t
   const U4 r = stream(q, pid, 2u + bounce);
   const float wn = wx * nx + wy * ny + wz * nz;
   if (unif32(r.a) < q.alpha) {
+    // temperature of the re-emitted Maxwellian: tau, or with energy
+    // accommodation tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 (capped)
+    float tr = q.tau;
+    if (q.eacc) {
+      const float e_in = wx * wx + wy * wy + wz * wz;
+      tr = sqrtf(fminf(q.alpha_E * q.tau * q.tau + (1.0f - q.alpha_E) * 0.5f * e_in, q.tr_cap2));
+    }
     const float sg = wn < 0.0f ? 1.0f : -1.0f;
     const float sx = sg * nx, sy = sg * ny, sz = sg * nz;
     // orthonormal tangents of (sx, sy, sz) (Duff et al., JCGT 2017)
@@ -532,8 +539,8 @@ __device__ __forceinline__ void reemit(const QueryDev& q, uint64_t pid, uint32_t
     const float b = sx * sy * a;
     const float b1x = 1.0f + sign * sx * sx * a, b1y = sign * b, b1z = -sign * sx;
     const float b2x = b, b2y = sign + sy * sy * a, b2z = -sy;
-    const float vn = q.tau * sqrtf(-logf(unif32(r.b)));
-    const float rad = q.tau * sqrtf(-2.0f * logf(unif32(r.c))) * (float)kInvSqrt2;
+    const float vn = tr * sqrtf(-logf(unif32(r.b)));
+    const float rad = tr * sqrtf(-2.0f * logf(unif32(r.c))) * (float)kInvSqrt2;
     float sn, cs;
     sincospif(2.0f * unif32(r.d), &sn, &cs);
     const float v1 = rad * cs, v2 = rad * sn;

@@ -9,14 +9,15 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
 constexpr int kMaxReflections = 64;
 constexpr int kLdsTallyMaxTris = 512;  // per-workgroup LDS tallies up to this mesh size
 constexpr int kLaneTallyMaxTris = 2;   // per-lane LDS tallies for tiny meshes
-constexpr int kScalarSlots = 16;       // int64 per query, see ScalarSlot
+constexpr int kScalarSlots = 18;       // int64 per query, see ScalarSlot
 
 // Per-query int64 block.  D is the momentum one particle gives the body along
 // the free stream (sum over its hits of (w - w').U); D and D^2 are quantised
 // per particle, so every sum is an exact integer sum and independent of order.
 enum ScalarSlot {
   kSD = 0, kSD2 = 1, kRays = 2, kHits = 3, kSegments = 4, kMissed = 5, kEscaped = 6, kCapped = 7,
-  kFx = 8, kFy = 9, kFz = 10, kLx = 11, kLy = 12, kLz = 13, kCount = 14
+  kFx = 8, kFy = 9, kFz = 10, kLx = 11, kLy = 12, kLz = 13, kCount = 14,
+  kSE = 15, kSE2 = 16  // per-particle energy E = sum over hits of |w|^2 - |w'|^2, and E^2
 };
 
 struct Node;
@@ -51,6 +52,12 @@ struct alignas(16) QueryDev {
   double h[3];                       // box half-extents
   double face_s[6];                  // s_f = S U.n_f, n_f the inward normal of face f
   double face_cum[6];                // cumulative A_f chi(s_f)
+  double inv_scaleE, inv_scaleE2;
+  float alpha_E;                     // energy accommodation of diffuse re-emission
+  float tr_cap2;                     // cap of the re-emission temperature tau_r^2
+  float scaleE, scaleE2;             // fixed-point scales of E and E^2
+  uint32_t eacc;                     // energy accommodation on (else tau_r = tau)
+  uint32_t pad2_[3];
 };
 
 // Device result of the finalisation kernel (mirrors tpmc_result).
@@ -58,6 +65,7 @@ struct ResultDev {
   double F_over_q[3], M_over_q[3], Fhat[3];
   double CD, CD_sigma, Gamma_hat;
   uint64_t rays, hits, segments, missed, escaped, capped;
+  double Qhat, CH, CH_sigma;
 };
 
 // BVH node: the boxes of both children and the two child links (64 bytes).

@@ -138,6 +138,7 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 struct Lane {
   float ox = 0.0f, oy = 0.0f, oz = 0.0f, wx = 0.0f, wy = 0.0f, wz = 0.0f;
   float D;        // momentum given along U so far (this particle)
+  float E;        // energy given to the body so far, sum of |w|^2 - |w'|^2
   int prev;       // Morton position of the triangle just left
   uint32_t hits;
   uint64_t pid;   // particle index within its query
@@ -285,13 +286,13 @@ struct Hit {
 
 // Per-lane exact integer accumulators.
 struct Acc {
-  long long sD, sD2, tot[7];
+  long long sD, sD2, sE, sE2, tot[7];
   uint32_t rays, hits, segs, missed, escaped, capped;
   uint32_t nodes, tests;  // traversal work (counting kernels only)
 };
 
 __device__ __forceinline__ void acc_zero(Acc& A) {
-  A.sD = A.sD2 = 0;
+  A.sD = A.sD2 = A.sE = A.sE2 = 0;
 #pragma unroll
   for (int c = 0; c < 7; ++c) A.tot[c] = 0;
   A.rays = A.hits = A.segs = A.missed = A.escaped = A.capped = 0;
@@ -325,6 +326,7 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
   const float pz = s.b0 * tr.v0z + s.b1 * tr.v1z + s.b2 * tr.v2z;
   float nwx = L.wx, nwy = L.wy, nwz = L.wz;
   reemit(q, L.pid, L.hits, tr.nx, tr.ny, tr.nz, nwx, nwy, nwz);
+  L.E += (L.wx * L.wx + L.wy * L.wy + L.wz * L.wz) - (nwx * nwx + nwy * nwy + nwz * nwz);
   const float dx = L.wx - nwx, dy = L.wy - nwy, dz = L.wz - nwz;
   const float rx = px - q.c0f[0], ry = py - q.c0f[1], rz = pz - q.c0f[2];
   h.valid = true;
@@ -367,6 +369,8 @@ __device__ __forceinline__ void count_outcome(Acc& A, int out, bool hit) {
 __device__ __forceinline__ void retire(const QueryDev& q, const Lane& L, Acc& A) {
   A.sD += fx(L.D, q.scaleD);
   A.sD2 += fx(L.D * L.D, q.scaleD2);
+  A.sE += fx(L.E, q.scaleE);
+  A.sE2 += fx(L.E * L.E, q.scaleE2);
 }
 
 // Tally of one hit per lane.  Called by every lane of the wave (convergent).
@@ -430,7 +434,7 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
       lane_tot[c * kBlock + threadIdx.x] = 0ull;
     }
   }
-  long long s[8 + 7];
+  long long s[8 + 7 + 2];
   s[0] = wave_sum(A.sD);
   s[1] = wave_sum(A.sD2);
   s[2] = wave_sum((long long)A.rays);
@@ -439,6 +443,8 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
   s[5] = wave_sum((long long)A.missed);
   s[6] = wave_sum((long long)A.escaped);
   s[7] = wave_sum((long long)A.capped);
+  s[15] = wave_sum(A.sE);
+  s[16] = wave_sum(A.sE2);
   if (TOTALS) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) s[8 + c] = wave_sum(A.tot[c]);
@@ -447,6 +453,8 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
 #pragma unroll
     for (int c = 0; c < 8; ++c)
       if (s[c]) atomic_add_i64(scal + c, s[c]);
+    if (s[15]) atomic_add_i64(scal + kSE, s[15]);
+    if (s[16]) atomic_add_i64(scal + kSE2, s[16]);
     if (TOTALS) {
 #pragma unroll
       for (int c = 0; c < 7; ++c)
@@ -487,6 +495,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
     l.ox = a.x[0][l.pid]; l.oy = a.x[1][l.pid]; l.oz = a.x[2][l.pid];
     l.wx = a.w[0][l.pid]; l.wy = a.w[1][l.pid]; l.wz = a.w[2][l.pid];
     l.D = 0.0f;
+    l.E = 0.0f;
     l.prev = -1;
     l.hits = 0;
   };
@@ -741,6 +750,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               L.wx = qbuf[wave][3][slot]; L.wy = qbuf[wave][4][slot]; L.wz = qbuf[wave][5][slot];
               L.pid = q_pid0 + qlane[wave][slot];
               L.D = 0.0f;
+              L.E = 0.0f;
               L.prev = -1;
               L.hits = 0;
               L.live = true;
@@ -842,6 +852,15 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
   if (varD < 0.0) varD = 0.0;
   r.CD_sigma = q.s_zero ? nan : 2.0 * q.Gamma_hat / (q.S * q.S * A_ref) * sqrt(varD / N);
   r.Gamma_hat = q.Gamma_hat;
+  // energy: power Q = n c_mp (m c_mp^2 / 2) (Gamma_hat / N) sum E, and
+  // C_H = Q / (rho U^3 A_ref / 2) = Gamma_hat sum E / (N S^3 A_ref)
+  const double meanE = (double)s[kSE] * q.inv_scaleE / N;
+  double varE = (double)s[kSE2] * q.inv_scaleE2 / N - meanE * meanE;
+  if (varE < 0.0) varE = 0.0;
+  const double S3 = q.S * q.S * q.S;
+  r.Qhat = q.Gamma_hat * meanE;
+  r.CH = q.s_zero ? nan : q.Gamma_hat * meanE / (S3 * A_ref);
+  r.CH_sigma = q.s_zero ? nan : q.Gamma_hat / (S3 * A_ref) * sqrt(varE / N);
   r.rays = (uint64_t)s[kRays];
   r.hits = (uint64_t)s[kHits];
   r.segments = (uint64_t)s[kSegments];

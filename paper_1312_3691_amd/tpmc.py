@@ -36,14 +36,16 @@ class Query(ctypes.Structure):
     _fields_ = [("q_wxyz", ctypes.c_double * 4), ("S", ctypes.c_double), ("T_inf", ctypes.c_double),
                 ("T_w", ctypes.c_double), ("alpha", ctypes.c_double), ("n_particles", ctypes.c_uint64),
                 ("seed", ctypes.c_uint64), ("max_reflections", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("cv_center", ctypes.c_double * 3), ("cv_radius", ctypes.c_double)]
+                ("cv_center", ctypes.c_double * 3), ("cv_radius", ctypes.c_double),
+                ("energy_accommodation", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("F_over_q", ctypes.c_double * 3), ("M_over_q", ctypes.c_double * 3), ("Fhat", ctypes.c_double * 3),
                 ("CD", ctypes.c_double), ("CD_sigma", ctypes.c_double), ("Gamma_hat", ctypes.c_double),
                 ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64), ("segments", ctypes.c_uint64),
-                ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64), ("capped", ctypes.c_uint64)]
+                ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64), ("capped", ctypes.c_uint64),
+                ("Qhat", ctypes.c_double), ("CH", ctypes.c_double), ("CH_sigma", ctypes.c_double)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -124,6 +126,7 @@ def make_query(qd: dict) -> Query:
     q.flags = int(qd.get("flags", 0))
     q.cv_center[:] = [float(v) for v in qd.get("cv_center", (0.0, 0.0, 0.0))]
     q.cv_radius = float(qd.get("cv_radius", 0.0))
+    q.energy_accommodation = float(qd.get("alpha_E", 1.0))
     return q
 
 

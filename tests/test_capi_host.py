@@ -33,13 +33,14 @@ def test_every_declared_symbol_is_exported(T):
     lib = ctypes.CDLL(T.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.tpmc_abi_version() == 3
+    assert lib.tpmc_abi_version() == 4
 
 
 def test_struct_sizes_match_header(T):
-    # tpmc_query: 4+1+2+1 doubles, 2 u64, 2 u32, 4 doubles = 112 bytes
-    assert ctypes.sizeof(T.Query) == 8 * 8 + 16 + 8 + 32
-    assert ctypes.sizeof(T.Result) == 12 * 8 + 6 * 8
+    # tpmc_query: 4+1+2+1 doubles, 2 u64, 2 u32, 4 doubles, 1 double = 120 bytes
+    assert ctypes.sizeof(T.Query) == 8 * 8 + 16 + 8 + 32 + 8
+    # tpmc_result: 12 doubles, 6 u64, 3 doubles
+    assert ctypes.sizeof(T.Result) == 12 * 8 + 6 * 8 + 3 * 8
     # tpmc_mesh_info: 2 u64, 2 u32, 10 doubles, u64, 2 u32 = 120 bytes
     assert ctypes.sizeof(T.MeshInfo) == 16 + 8 + 80 + 8 + 8
 
@@ -74,7 +75,7 @@ def test_mesh_validation(T):
 
 @pytest.mark.parametrize("field,value", [("S", -1.0), ("S", float("nan")), ("S", 101.0), ("T_inf", 0.0),
                                          ("T_w", -3.0), ("alpha", 1.5), ("alpha", -0.1), ("n", 0),
-                                         ("max_reflections", 0), ("max_reflections", 65), ("flags", 4)])
+                                         ("max_reflections", 0), ("max_reflections", 65), ("flags", 8)])
 def test_query_validation(T, field, value):
     q = I.query()
     q[field] = value
@@ -98,7 +99,12 @@ def test_query_attitude_and_cv(T):
     assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=0.99), V)) == 3
     assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=1.1, cv_center=(0.2, 0, 0)), V)) == 3
     assert _status(lambda: T.check_query(I.query(cv_box=True, cv_radius=0.9, cv_center=(0.0, 0, 0)), V)) == 3
-    assert _status(lambda: T.check_query(I.query(flags=6), V)) == 1  # unknown bit next to the box flag
+    assert _status(lambda: T.check_query(I.query(flags=8), V)) == 1  # unknown bit above the known flags
+    # energy accommodation in [0, 1] when its flag is set
+    assert _status(lambda: T.check_query(I.query(alpha_E=0.0), V)) == 0
+    assert _status(lambda: T.check_query(I.query(alpha_E=1.0), V)) == 0
+    assert _status(lambda: T.check_query(I.query(alpha_E=1.2), V)) == 1
+    assert _status(lambda: T.check_query(I.query(alpha_E=float("nan")), V)) == 1
 
 
 def test_no_device_is_a_clean_error(T):
