@@ -349,6 +349,74 @@ def workload_boxcv(args):
            "tuning": tuning})
 
 
+ENERGY_ACC = (0.0, 0.25, 0.5, 0.75, 1.0)
+
+
+def plate_ch(S, angle_deg, tau, alpha_E):
+    """Heat-transfer coefficient of the flat plate (one face wetted, A_ref = 1
+    m^2) under full diffuse re-emission with energy accommodation alpha_E:
+    per molecule E[|w|^2 - |w'|^2] = alpha_E (|w|^2 - 2 tau^2), summed over the
+    one-sided flux: alpha_E [M3 + (S_t^2 + 1 - 2 tau^2) M1] / S^3 with the flux
+    moments M1 = chi(s) / (2 sqrt(pi)) and M3 = [(s^2 + 1) e^{-s^2} +
+    sqrt(pi) s (s^2 + 3/2)(1 + erf s)] / (2 sqrt(pi)) of the normal speed,
+    s = S cos(a), S_t = S sin(a)."""
+    a = math.radians(angle_deg)
+    s, st = S * math.cos(a), S * math.sin(a)
+    ec = math.erfc(-s)
+    m1 = (math.exp(-s * s) + math.sqrt(math.pi) * s * ec) / (2 * math.sqrt(math.pi))
+    m3 = ((s * s + 1) * math.exp(-s * s) + math.sqrt(math.pi) * s * (s * s + 1.5) * ec) / (2 * math.sqrt(math.pi))
+    return alpha_E * (m3 + (st * st + 1.0 - 2.0 * tau * tau) * m1) / S ** 3
+
+
+def workload_energy(args):
+    """Energy exchange and incomplete energy accommodation: diffuse
+    re-emission at tau_r^2 = alpha_E tau^2 + (1 - alpha_E)|w|^2 / 2, alpha_E
+    from 0 to 1, on the plate (S = 3, 30 deg; C_H against its flux-moment
+    closed form), the capped cylinder (S = 3, 45 deg) and the concave
+    satellite (S = 7, the C3 attitude), 1e7 particles each, one batched launch
+    per mesh; reports C_D and the heat-transfer coefficient C_H."""
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    ctx = tpmc.Context(0)
+    n = int(args.particles_energy)
+    tau = math.sqrt(T_W / T_INF)
+    setups = (("plate", I.plate(), (math.sin(math.radians(30)), 0.0, -math.cos(math.radians(30))), 3.0, 1.0),
+              ("cylinder", I.capped_cylinder(), (math.sqrt(0.5), 0.0, math.sqrt(0.5)), 3.0, 1.0),
+              ("satellite", I.satellite(50_000), (-0.5, 0.0, -math.sqrt(3.0) / 2.0), 7.0, 1.0))
+    rows, hits, dt_total, tunings = [], 0, 0.0, {}
+    for name, (V, T), U, S, alpha in setups:
+        mesh = ctx.build_mesh(V, T, builder=args.bvh)
+        qs = [I.query(q=I.quat_for_flow(U), S=S, T_inf=T_INF, T_w=T_W, alpha=alpha, n=n, seed=i, alpha_E=aE)
+              for i, aE in enumerate(ENERGY_ACC)]
+        tunings[name] = tune_for(args, mesh, qs, key=name)
+        b = tpmc.Batch(mesh, qs)
+        b.launch().results()
+        for _ in range(args.warmup):
+            b.launch(use_graph=True).results()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = b.launch(use_graph=True).results()
+        dt = (time.perf_counter() - t0) / args.steps
+        b.close()
+        dt_total += dt
+        hits += sum(r["hits"] for r in res)
+        for aE, r in zip(ENERGY_ACC, res):
+            row = {"mesh": name, "S": S, "alpha_E": aE, "CD": r["CD"], "CD_sigma": r["CD_sigma"], "CH": r["CH"],
+                   "CH_sigma": r["CH_sigma"], "hits_per_particle": r["hits"] / n}
+            if name == "plate":
+                row["CH_exact"] = plate_ch(S, 30.0, tau, aE)
+            rows.append(row)
+    _line("particle-surface hits/sec on 1 MI355X (energy accommodation and heat transfer)", hits / dt_total, "hits/s",
+          dt_total, args.steps, args.warmup,
+          {"workload": f"plate / capped cylinder / concave satellite, alpha_E in {list(ENERGY_ACC)}, {n} particles "
+                       "each, one batched launch per mesh", "path": "batched persistent launch, graph replay",
+           "bvh": args.bvh},
+          {"cases": rows, "tuning": tunings})
+
+
 MOMENT_PITCH = tuple(range(-40, 41, 10))
 MOMENT_YAW = (-20, 0, 20)
 
@@ -575,13 +643,15 @@ def main():
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
     ap.add_argument("--workload", default="plate-cylinder",
-                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv"],
+                    choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv",
+                             "energy"],
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
     ap.add_argument("--particles-pratt", type=float, default=1e7)
     ap.add_argument("--particles-moments", type=float, default=4e6)
     ap.add_argument("--particles-boxcv", type=float, default=1e8)
+    ap.add_argument("--particles-energy", type=float, default=1e7)
     ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
     ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
     ap.add_argument("--slots", type=int, default=64, help="served: request slots")
@@ -609,7 +679,8 @@ def main():
         sys.exit(2)
     if args.workload != "plate-cylinder":
         {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served,
-         "pratt": workload_pratt, "moments": workload_moments, "boxcv": workload_boxcv}[args.workload](args)
+         "pratt": workload_pratt, "moments": workload_moments, "boxcv": workload_boxcv,
+         "energy": workload_energy}[args.workload](args)
         return
 
     import torch
