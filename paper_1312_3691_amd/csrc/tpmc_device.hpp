@@ -295,8 +295,8 @@ __device__ __forceinline__ void normal_speed_F32(float s, float es2, float erfs,
 // The law depends on s alone, so one table serves every query; it is filled
 // once per device by FP64 bisection (vn_table_kernel).  It only chooses where
 // the iteration starts.
-constexpr int kVnNS = 41, kVnNT = 129;
-constexpr float kVnS0 = -4.0f, kVnDS = 0.25f, kVnT0 = -24.0f, kVnDT = 0.375f;
+constexpr int kVnNS = 225, kVnNT = 385;
+constexpr float kVnS0 = -4.0f, kVnDS = 0.0625f, kVnT0 = -24.0f, kVnDT = 0.125f;
 
 __device__ __forceinline__ float normal_speed_start(const float* __restrict__ tab, double s, double u) {
   const float sf = (float)s;
