@@ -368,7 +368,8 @@ __device__ inline double sample_normal_speed(const float* __restrict__ tab, cons
 // solve (the frame is expanded afterwards), which keeps the persistent kernel
 // inside its register budget.
 __device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ lat_tab,
-                                     const float* __restrict__ vn_tab, uint64_t pid, double x[3], double w[3]) {
+                                     const float* __restrict__ vn_tab, const double* __restrict__ sc_tab, uint64_t pid,
+                                     double x[3], double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
   double p0, p1, p2, p3;  // sphere: mu, cos(phi), sin(th), cos(th); box: n_a, position on the face (2)
@@ -388,14 +389,14 @@ __device__ inline void seed_particle(const QueryDev& q, const float* __restrict_
     LatEval le;
     p0 = sample_latitude(q, lat_tab, unif64(r0.a), le);
     p1 = sqrt(fmax(0.0, 1.0 - p0 * p0));
-    sincospi(2.0 * unif64(r0.b), &p2, &p3);
+    sincos_2pi_draw(sc_tab, r0.b, p2, p3);  // of 2 pi unif64(r0.b)
     const double s_n = q.S * p0;
     k = le.valid ? normal_speed_consts_near(s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(s_n);
   }
   const double wn = sample_normal_speed(vn_tab, k, unif64(r0.c));
   const double rad = sqrt(-2.0 * log_draw(r0.d));  // ln unif64(r0.d)
   double sb, cb;
-  sincospi(2.0 * unif64(r1.a), &sb, &cb);
+  sincos_2pi_draw(sc_tab, r1.a, sb, cb);  // of 2 pi unif64(r1.a)
   const double g1 = rad * cb * kInvSqrt2, g2 = rad * sb * kInvSqrt2;
   if (q.box) {
     const int j = fa == 2 ? 0 : fa + 1;  // t1 axis; the remaining axis is t2's

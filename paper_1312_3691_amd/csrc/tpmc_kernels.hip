@@ -37,6 +37,17 @@ int grid_for(uint64_t n, int cap) {
 // normal_speed_start); part of the code object, filled once per device.
 __device__ float g_lat_start[kLatNS * kLatNT];
 __device__ float g_vn_start[kVnNS * kVnNT];
+// sin and cos of 2 pi j / 256, j = 0..255 (sincos_2pi_draw)
+__device__ double g_sc_tab[512];
+
+__global__ void sc_table_kernel(double* __restrict__ tab) {
+  const int j = threadIdx.x;
+  if (j >= 256) return;
+  double s, c;
+  sincospi((double)j / 128.0, &s, &c);
+  tab[2 * j] = s;
+  tab[2 * j + 1] = c;
+}
 
 __global__ void lat_table_kernel(float* __restrict__ tab) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -88,7 +99,7 @@ __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double x[3], w[3];
-    seed_particle(q, g_lat_start, g_vn_start, i, x, w);
+    seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, i, x, w);
     x0[i] = (float)x[0];
     x1[i] = (float)x[1];
     x2[i] = (float)x[2];
@@ -716,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               float xs[3], ws[3];
               if (pid < p_end) {
                 double x[3], w[3];
-                seed_particle(q, g_lat_start, g_vn_start, pid, x, w);
+                seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, pid, x, w);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                   xs[c] = (float)x[c];
@@ -917,9 +928,12 @@ void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t
 hipError_t init_seed_tables(hipStream_t st) {
   float* tab = nullptr;
   float* lat = nullptr;
+  double* sc = nullptr;
   hipError_t e = hipGetSymbolAddress((void**)&tab, HIP_SYMBOL(g_vn_start));
   if (e == hipSuccess) e = hipGetSymbolAddress((void**)&lat, HIP_SYMBOL(g_lat_start));
+  if (e == hipSuccess) e = hipGetSymbolAddress((void**)&sc, HIP_SYMBOL(g_sc_tab));
   if (e != hipSuccess) return e;
+  sc_table_kernel<<<1, 256, 0, st>>>(sc);
   vn_table_kernel<<<(kVnNS * kVnNT + 255) / 256, 256, 0, st>>>(tab);
   lat_table_kernel<<<(kLatNS * kLatNT + 255) / 256, 256, 0, st>>>(lat);
   e = hipGetLastError();

@@ -1,4 +1,4 @@
-// tpmc_math.hpp -- FP64 logarithm of the seeding draws (Box-Muller radius).
+// tpmc_math.hpp -- FP64 logarithm, sine and cosine of the seeding draws.
 //
 // The seeding draws are u = (k + 1/2) 2^-32 for a 32-bit integer k (unif64 in
 // tpmc_device.hpp), so u = n 2^-33 with n = 2k + 1 odd, and the reduction is
@@ -43,6 +43,26 @@ __host__ __device__ inline double log_draw(uint32_t k) {
   const double lm = fma(s * w, p, 2.0 * s);  // ln m = 2s + s w P(w)
   const double E = (double)(e - 33);
   return fma(E, 0x1.62e42fefa3980p-1, fma(E, 0x1.bcd5e4f1d9cc0p-47, lm));
+}
+
+// sin(2 pi u) and cos(2 pi u) for u = (k + 1/2) 2^-32, from a table of
+// sin and cos at the 256 angles 2 pi j / 256 (tab[2j], tab[2j + 1]) and the
+// angle addition formulas: with n = 2k + 1 the angle is pi n 2^-32, its top
+// eight bits j = n >> 25 pick the table angle a = 2 pi j / 256, and the rest
+// delta = pi (n mod 2^25) 2^-32 in [0, 2 pi / 256) is exact up to the rounding
+// of pi 2^-32; sin(delta) to delta^7 and cos(delta) to delta^6 (first omitted
+// terms below 1e-17 absolute).  Within two ulps of the exact values when the
+// table entries are within one (a CPU test compares with 40-digit values).
+__host__ __device__ inline void sincos_2pi_draw(const double* __restrict__ tab, uint32_t k, double& s, double& c) {
+  const uint64_t n = 2ull * k + 1ull;
+  const uint32_t j = (uint32_t)(n >> 25);                       // 0..255
+  const double d = (double)(uint32_t)(n & 0x1FFFFFFull) * 0x1.921fb54442d18p-31;  // pi 2^-32 per unit
+  const double z = d * d;
+  const double sd = d * fma(z, fma(z, fma(z, -0x1.a01a01a01a01ap-13, 0x1.1111111111111p-7), -0x1.5555555555555p-3), 1.0);
+  const double cd = fma(z, fma(z, fma(z, -0x1.6c16c16c16c17p-10, 0x1.5555555555555p-5), -0.5), 1.0);
+  const double sa = tab[2 * j], ca = tab[2 * j + 1];
+  s = fma(sa, cd, ca * sd);
+  c = fma(ca, cd, -(sa * sd));
 }
 
 }  // namespace tpmc

@@ -1,8 +1,9 @@
-"""The seeding's logarithm of a draw (csrc/tpmc_math.hpp), built for the host
-and compared with 40-digit values: ln u for u = (k + 1/2) 2^-32 within 1.5
-ulp over the range of k (both ends, powers of two, the sqrt(2) fold, random
-k).  The largest errors (~1.4 ulp) sit near u = 0.7, where -ln 2 and ln m
-partly cancel.  No GPU is needed."""
+"""The seeding's logarithm, sine and cosine of a draw (csrc/tpmc_math.hpp),
+built for the host and compared with 40-digit values over the range of k
+(both ends, powers of two, the sqrt(2) fold, random k): ln u for
+u = (k + 1/2) 2^-32 within 1.5 ulp (the largest errors, ~1.4 ulp, sit near
+u = 0.7, where -ln 2 and ln m partly cancel), sin and cos of 2 pi u within
+2 x 2^-53 absolute.  No GPU is needed."""
 import math
 import os
 import random
@@ -27,7 +28,7 @@ def harness(tmp_path_factory):
     return exe
 
 
-def test_log_draw_within_one_ulp(harness):
+def test_draw_math_against_40_digits(harness):
     mp = pytest.importorskip("mpmath")
     mp.mp.dps = 40
     rng = random.Random(7)
@@ -38,11 +39,15 @@ def test_log_draw_within_one_ulp(harness):
     ks += [rng.getrandbits(32) for _ in range(4000)]
     ks = sorted({k for k in ks if 0 <= k < (1 << 32)})
     out = subprocess.run([harness], input="\n".join(map(str, ks)), capture_output=True, text=True, check=True).stdout
-    got = [float.fromhex(v) for v in out.split()]
-    assert len(got) == len(ks)
-    worst = 0.0
-    for k, g in zip(ks, got):
-        exact = mp.log((mp.mpf(k) + mp.mpf(0.5)) * mp.mpf(2) ** -32)
-        err = abs(mp.mpf(g) - exact) / math.ulp(abs(float(exact)))
-        worst = max(worst, float(err))
+    rows = [[float.fromhex(v) for v in line.split()] for line in out.strip().split("\n")]
+    assert len(rows) == len(ks)
+    worst = worst_sc = 0.0
+    for k, (lg, s, c) in zip(ks, rows):
+        u = (mp.mpf(k) + mp.mpf(0.5)) * mp.mpf(2) ** -32
+        exact = mp.log(u)
+        worst = max(worst, float(abs(mp.mpf(lg) - exact) / math.ulp(abs(float(exact)))))
+        # sin and cos multiply unit vectors: absolute error in units of 2^-53
+        for v, t in ((s, mp.sin(2 * mp.pi * u)), (c, mp.cos(2 * mp.pi * u))):
+            worst_sc = max(worst_sc, float(abs(mp.mpf(v) - t)) / 2.0 ** -53)
     assert worst <= 1.5, worst
+    assert worst_sc <= 2.0, worst_sc
