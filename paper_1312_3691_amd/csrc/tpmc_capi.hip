@@ -293,8 +293,13 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   q->tr_cap2 = (float)std::fmax(tau * tau, 0.5 * (S + 15.0) * (S + 15.0));
   const double Dmax = q->eacc ? 2.0 * std::fmax(8.0 * tau, 5.0 * (S + 15.0)) : 2.0 * std::fmax(S + 15.0, 8.0 * tau);
   const double hits_max = (double)in->n_particles * (double)in->max_reflections;
-  const double sF = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax)), std::ldexp(1.0, 50));
-  const double sL = std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax * q->r * 1.01)), std::ldexp(1.0, 50));
+  // One hit's scaled momentum (and moment) also stays below 2^30, so the
+  // kernels convert it with a 32-bit conversion.
+  const double sF = std::fmin(std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax)), std::ldexp(1.0, 50)),
+                              pow2_floor(std::ldexp(1.0, 30) / Dmax));
+  const double sL = std::fmin(std::fmin(pow2_floor(std::ldexp(1.0, 62) / (hits_max * Dmax * q->r * 1.01)),
+                                        std::ldexp(1.0, 50)),
+                              pow2_floor(std::ldexp(1.0, 30) / (Dmax * q->r * 1.01)));
   const double pD = (double)in->max_reflections * Dmax;
   const double sD2 = std::fmin(pow2_floor(std::ldexp(1.0, 62) / ((double)in->n_particles * pD * pD)),
                                std::ldexp(1.0, 50));

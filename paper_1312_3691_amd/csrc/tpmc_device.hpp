@@ -560,6 +560,9 @@ __device__ __forceinline__ void reemit(const QueryDev& q, uint64_t pid, uint32_t
 // Fixed point and wave-level reductions.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ long long fx(float v, float scale) { return __float2ll_rn(v * scale); }
+// The same for |v * scale| < 2^31: round to nearest even, then a 32-bit
+// conversion (3 instructions instead of 12).
+__device__ __forceinline__ long long fx32(float v, float scale) { return (long long)(int)rintf(v * scale); }
 __device__ __forceinline__ long long fxd(double v, double scale) { return __double2ll_rn(v * scale); }
 
 __device__ __forceinline__ long long wave_sum(long long v) {

@@ -391,8 +391,9 @@ template <int MODE, bool TOT_LDS = true>
 __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long* __restrict__ g,
                                       unsigned long long* lds, uint32_t nt, Acc& A) {
   long long v[7];
-  v[0] = fx(h.dx, q.scaleF); v[1] = fx(h.dy, q.scaleF); v[2] = fx(h.dz, q.scaleF);
-  v[3] = fx(h.lx, q.scaleL); v[4] = fx(h.ly, q.scaleL); v[5] = fx(h.lz, q.scaleL);
+  // one hit's values are below 2^30 in magnitude after scaling (scale choice)
+  v[0] = fx32(h.dx, q.scaleF); v[1] = fx32(h.dy, q.scaleF); v[2] = fx32(h.dz, q.scaleF);
+  v[3] = fx32(h.lx, q.scaleL); v[4] = fx32(h.ly, q.scaleL); v[5] = fx32(h.lz, q.scaleL);
   v[6] = 1;
   if (MODE == kTallyTotals && TOT_LDS) {  // the lane's own LDS slots [c][lane]
     if (h.valid) {
