@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 4
+#define TPMC_ABI_VERSION 5
 
 typedef enum {
   TPMC_OK = 0,
@@ -150,8 +150,10 @@ typedef struct {
   uint32_t tile_particles; /* multiple of 64 in [64, 2^22], default 16384: particles per work tile
                               of the persistent kernel; read when a batch or server is created */
   uint32_t groups_per_cu;  /* 1..32, default 8: workgroups (256 lanes) per compute unit of the
-                              persistent launches and the cap of the plain trace grid */
-  uint32_t reserved;       /* must be 0 */
+                              persistent launches (batches and server steps) */
+  uint32_t plain_groups_per_cu; /* 0..32, default 4 (0 selects it): cap, in workgroups per compute
+                              unit, of the grid of tpmc_trace; the grid also keeps at least four
+                              particles per lane, so small queries get fewer workgroups */
 } tpmc_tuning;
 
 /* Copy out / replace the context's tuning.  set validates every field

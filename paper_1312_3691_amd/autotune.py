@@ -1,6 +1,6 @@
 """Launch autotuner for the persistent batched kernel.
 
-The three launch parameters of a context (tpmc_set_tuning) -- refill_lanes
+The three launch parameters of the persistent launches (tpmc_set_tuning) -- refill_lanes
 (how few lanes of a wave may still be traversing before the lanes whose ray
 segment ended are served together), tile_particles (particles per work tile
 a workgroup claims) and groups_per_cu (persistent workgroups per compute unit)

@@ -17,6 +17,9 @@
 
 using namespace tpmc;
 
+// default cap of the plain trace grid, workgroups per compute unit
+static constexpr uint32_t kPlainGroupsPerCu = 4;
+
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
@@ -423,7 +426,7 @@ extern "C" tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out) 
   c->tune.refill_lanes = 32;
   c->tune.tile_particles = 16384;
   c->tune.groups_per_cu = 8;
-  c->tune.reserved = 0;
+  c->tune.plain_groups_per_cu = kPlainGroupsPerCu;
   *out = c;
   return TPMC_OK;
 }
@@ -442,8 +445,10 @@ extern "C" tpmc_status tpmc_set_tuning(tpmc_ctx ctx, const tpmc_tuning* t) {
     return fail(TPMC_E_INVALID, "tile_particles = %u is not a multiple of 64 in [64, 2^22]", t->tile_particles);
   if (t->groups_per_cu < 1 || t->groups_per_cu > 32)
     return fail(TPMC_E_INVALID, "groups_per_cu = %u outside 1..32", t->groups_per_cu);
-  if (t->reserved != 0) return fail(TPMC_E_INVALID, "reserved must be 0");
+  if (t->plain_groups_per_cu > 32)
+    return fail(TPMC_E_INVALID, "plain_groups_per_cu = %u outside 0..32", t->plain_groups_per_cu);
   ctx->tune = *t;
+  if (ctx->tune.plain_groups_per_cu == 0) ctx->tune.plain_groups_per_cu = kPlainGroupsPerCu;
   return TPMC_OK;
 }
 
@@ -650,10 +655,14 @@ extern "C" tpmc_status tpmc_particles_planes(tpmc_particles p, float* dev_planes
 }
 
 // Plain trace grid: at least four particles per lane (so that lanes whose
-// particle retires have another to take), at most groups_per_cu per CU.
+// particle retires have another to take), at most plain_groups_per_cu per CU.
+// Every workgroup of a plain launch flushes its tallies and scalars with
+// device atomics once, onto the same few addresses for a small mesh, so the
+// cap is kept lower than the persistent launches' (whose workgroups flush once
+// per query they took part in).
 static int trace_grid(tpmc_ctx ctx, uint64_t n) {
   const uint64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
-  const uint64_t cap = (uint64_t)ctx->n_cu * ctx->tune.groups_per_cu;
+  const uint64_t cap = (uint64_t)ctx->n_cu * ctx->tune.plain_groups_per_cu;
   return (int)(g < cap ? (g ? g : 1) : cap);
 }
 

@@ -67,7 +67,8 @@ _QP = ctypes.POINTER(Query)
 _RP = ctypes.POINTER(Result)
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("refill_lanes", _u32), ("tile_particles", _u32), ("groups_per_cu", _u32), ("reserved", _u32)]
+    _fields_ = [("refill_lanes", _u32), ("tile_particles", _u32), ("groups_per_cu", _u32),
+                ("plain_groups_per_cu", _u32)]
 
 
 _SIGS = {
@@ -110,6 +111,11 @@ for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = _res
+
+ABI_VERSION = 5  # the structures below are laid out for this version of include/tpmc.h
+if _lib.tpmc_abi_version() != ABI_VERSION:
+    raise ImportError(f"libtpmc.so has ABI version {_lib.tpmc_abi_version()}, this binding expects "
+                      f"{ABI_VERSION}: rebuild the library (python -c 'import __graft_entry__ as g; g.build()')")
 
 
 def _check(status: int):
@@ -216,7 +222,7 @@ class Context:
         t = Tuning()
         _check(_lib.tpmc_get_tuning(self._h, ctypes.byref(t)))
         return {"refill_lanes": t.refill_lanes, "tile_particles": t.tile_particles,
-                "groups_per_cu": t.groups_per_cu}
+                "groups_per_cu": t.groups_per_cu, "plain_groups_per_cu": t.plain_groups_per_cu}
 
     def set_tuning(self, **kw) -> None:
         """Replace some fields of the launch tuning (tpmc_set_tuning); results do not change."""
@@ -225,7 +231,8 @@ class Context:
         if unknown:
             raise ValueError(f"unknown tuning fields {sorted(unknown)}")
         cur.update(kw)
-        t = Tuning(int(cur["refill_lanes"]), int(cur["tile_particles"]), int(cur["groups_per_cu"]), 0)
+        t = Tuning(int(cur["refill_lanes"]), int(cur["tile_particles"]), int(cur["groups_per_cu"]),
+                   int(cur["plain_groups_per_cu"]))
         _check(_lib.tpmc_set_tuning(self._h, ctypes.byref(t)))
 
 

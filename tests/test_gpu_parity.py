@@ -425,9 +425,9 @@ def test_tuning_does_not_change_results(ctx, T):
             mesh = ctx.build_mesh(V, Tr)
             qs = _batch_queries(4)
             ref = None
-            for t in ({"refill_lanes": 1, "tile_particles": 64, "groups_per_cu": 1},
-                      {"refill_lanes": 64, "tile_particles": 4096, "groups_per_cu": 32},
-                      {"refill_lanes": 33, "tile_particles": 1 << 22, "groups_per_cu": 3}):
+            for t in ({"refill_lanes": 1, "tile_particles": 64, "groups_per_cu": 1, "plain_groups_per_cu": 1},
+                      {"refill_lanes": 64, "tile_particles": 4096, "groups_per_cu": 32, "plain_groups_per_cu": 32},
+                      {"refill_lanes": 33, "tile_particles": 1 << 22, "groups_per_cu": 3, "plain_groups_per_cu": 3}):
                 ctx.set_tuning(**t)
                 plain, pr = T.run(mesh, qs, A_ref=1.0)
                 b = T.Batch(mesh, qs)
@@ -441,11 +441,14 @@ def test_tuning_does_not_change_results(ctx, T):
                         for k in p:
                             assert np.array_equal(np.asarray(p[k]), np.asarray(q[k])), (t, k)
         for bad in ({"refill_lanes": 0}, {"refill_lanes": 65}, {"tile_particles": 100}, {"tile_particles": 0},
-                    {"tile_particles": (1 << 22) + 64}, {"groups_per_cu": 0}, {"groups_per_cu": 33}):
+                    {"tile_particles": (1 << 22) + 64}, {"groups_per_cu": 0}, {"groups_per_cu": 33},
+                    {"plain_groups_per_cu": 33}):
             with pytest.raises(T.TpmcError):
                 ctx.set_tuning(**bad)
-        t = T.Tuning(48, 16384, 8, 1)  # reserved must be 0
+        t = T.Tuning(48, 16384, 8, 33)  # plain_groups_per_cu above 32
         assert T._lib.tpmc_set_tuning(ctx._h, ctypes.byref(t)) == 1
+        ctx.set_tuning(plain_groups_per_cu=0)  # 0 selects the default
+        assert ctx.tuning["plain_groups_per_cu"] == 4
     finally:
         ctx.set_tuning(**base)
     assert ctx.tuning == base
