@@ -240,6 +240,7 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   q->erfS = std::erf(S);
   q->erfcS = std::erfc(S);
   q->expmS2 = std::exp(-S * S);
+  q->lat_k = q->s_zero ? 0.0 : sqrtpi / (4.0 * S);
   // Z(S) = e^{-S^2} + sqrt(pi) (S + 1/(2S)) erf S; Gamma/(n c_mp) = sqrt(pi) r^2 Z (Sec. III.A.1)
   q->Z = q->s_zero ? 2.0 : q->expmS2 + sqrtpi * (S + 0.5 / S) * q->erfS;
   q->Gamma_hat = q->s_zero ? 2.0 * sqrtpi * q->r * q->r

@@ -77,17 +77,17 @@ __device__ __forceinline__ float unif32(uint32_t k) { return ((float)(k >> 9) + 
 // ---------------------------------------------------------------------------
 // Besides G and its derivatives, returns e = exp(-(S t)^2) and ta = erfc(|S t|),
 // which the normal-speed law at s = S mu reuses (normal_speed_consts_near).
-__device__ __forceinline__ void latitude_G(const QueryDev& q, double t, double& G, double& dG, double& d2G, double& e,
-                                           double& ta) {
+// Both come from the shifted table ee (exp_erfc_grid).
+__device__ __forceinline__ void latitude_G(const QueryDev& q, const double* __restrict__ ee, double t, double& G,
+                                           double& dG, double& d2G, double& e, double& ta) {
   const double S = q.S;
   const double St = S * t;
-  e = exp(-St * St);
-  ta = erfc(fabs(St));
+  exp_erfc_grid(ee, fabs(St), e, ta);
   const double c = St >= 0.0 ? 2.0 - ta : ta;  // erfc(-S t) = 1 + erf(S t)
   double E;                                     // erf(S t) + erf(S)
   if (S < 0.25) E = erf(St) + q.erfS;  // uniform branch: small S keeps erf(St) exact
   else E = St < -1.0 ? c - q.erfcS : (c - 1.0) + q.erfS;
-  G = kSqrtPi / (4.0 * S) * E + 0.5 * kSqrtPi * S * (t * t * c - q.erfcS) + 0.5 * (t * e + q.expmS2);
+  G = q.lat_k * E + 0.5 * kSqrtPi * S * (t * t * c - q.erfcS) + 0.5 * (t * e + q.expmS2);
   dG = e + kSqrtPi * St * c;
   d2G = S * kSqrtPi * c;
 }
@@ -177,7 +177,8 @@ struct LatEval {
   bool valid;
 };
 
-__device__ inline double sample_latitude(const QueryDev& q, const float* __restrict__ lat_tab, double u, LatEval& le) {
+__device__ inline double sample_latitude(const QueryDev& q, const float* __restrict__ lat_tab,
+                                        const double* __restrict__ ee, double u, LatEval& le) {
   le.valid = false;
   if (q.s_zero) return 2.0 * u - 1.0;  // S -> 0: g -> cos(phi)/2, mu uniform
   const double target = u * q.Z;
@@ -199,7 +200,7 @@ __device__ inline double sample_latitude(const QueryDev& q, const float* __restr
   for (int it = 0; it < 100; ++it) {
     double G, dG, d2G;
     le.t = x;
-    latitude_G(q, x, G, dG, d2G, le.e, le.ta);
+    latitude_G(q, ee, x, G, dG, d2G, le.e, le.ta);
     const double dx = halley_step(x, G - target, dG, d2G, lo, hi);
     // cubic convergence: after a step below 1e-5 the remaining error is far
     // below the FP64 resolution of mu
@@ -215,11 +216,11 @@ struct NormalSpeedConsts {
   double s, es2, erfs, erfcs, erfcms, chi;
 };
 
-__device__ __forceinline__ NormalSpeedConsts normal_speed_consts(double s) {
+__device__ __forceinline__ NormalSpeedConsts normal_speed_consts(const double* __restrict__ ee, double s) {
   NormalSpeedConsts k;
   k.s = s;
-  k.es2 = exp(-s * s);
-  const double t = erfc(fabs(s));  // the small one of erfc(s), erfc(-s)
+  double t;  // the small one of erfc(s), erfc(-s)
+  exp_erfc_grid(ee, fabs(s), k.es2, t);
   k.erfcs = s >= 0.0 ? t : 2.0 - t;
   k.erfcms = s >= 0.0 ? 2.0 - t : t;  // 1 + erf(s)
   k.erfs = s >= 0.0 ? 1.0 - t : t - 1.0;
@@ -236,10 +237,11 @@ __device__ __forceinline__ NormalSpeedConsts normal_speed_consts(double s) {
 // exp(2xh - h^2) = sum_n H_n(x) h^n / n!).  For |h| (y + 1) <= 1e-4 the terms
 // fall by at least ~2e-4 each, so six terms leave a relative error near 1e-21;
 // otherwise (or across s = 0) the constants are evaluated directly.
-__device__ __forceinline__ NormalSpeedConsts normal_speed_consts_near(double s, double s0, double e0, double ta0) {
+__device__ __forceinline__ NormalSpeedConsts normal_speed_consts_near(const double* __restrict__ ee, double s,
+                                                                     double s0, double e0, double ta0) {
   const double y = fabs(s0);
   const double h = fabs(s) - y;
-  if (!((s >= 0.0) == (s0 >= 0.0) && fabs(h) * (y + 1.0) <= 1e-4)) return normal_speed_consts(s);
+  if (!((s >= 0.0) == (s0 >= 0.0) && fabs(h) * (y + 1.0) <= 1e-4)) return normal_speed_consts(ee, s);
   constexpr double kInv[7] = {1.0, 1.0, 1.0 / 2, 1.0 / 3, 1.0 / 4, 1.0 / 5, 1.0 / 6};
   const double x = -y;
   double Hm = 1.0, Hn = 2.0 * x;          // H_0, H_1
@@ -266,11 +268,11 @@ __device__ __forceinline__ NormalSpeedConsts normal_speed_consts_near(double s, 
   return k;
 }
 
-__device__ __forceinline__ void normal_speed_F(const NormalSpeedConsts& k, double x, double& F, double& dF,
-                                               double& d2F) {
+__device__ __forceinline__ void normal_speed_F(const double* __restrict__ ee, const NormalSpeedConsts& k, double x,
+                                               double& F, double& dF, double& d2F) {
   const double a = x - k.s;
-  const double ea = exp(-a * a);
-  const double t = erfc(fabs(a));
+  double ea, t;
+  exp_erfc_grid(ee, fabs(a), ea, t);
   // erf(x - s) + erf(s) as a difference of small erfc values wherever a sum would cancel
   const double esum = k.s < 0.0 ? k.erfcms - t : (a < 0.0 ? t - k.erfcs : (1.0 - t) + k.erfs);
   F = k.es2 - ea + kSqrtPi * k.s * esum;
@@ -315,7 +317,8 @@ __device__ __forceinline__ float normal_speed_start(const float* __restrict__ ta
   return sf > 1.0f ? sf + 0.5f / sf + erfinvf(2.0f * uf - 1.0f) : sqrtf(-log1pf(-uf));
 }
 
-__device__ inline double sample_normal_speed(const float* __restrict__ tab, const NormalSpeedConsts& k, double u) {
+__device__ inline double sample_normal_speed(const float* __restrict__ tab, const double* __restrict__ ee,
+                                             const NormalSpeedConsts& k, double u) {
   const double s = k.s;
   const double target = u * k.chi;
   // The root lies below max(s, 0) + 7: the upper tail there is below e^{-49},
@@ -344,7 +347,7 @@ __device__ inline double sample_normal_speed(const float* __restrict__ tab, cons
 #pragma unroll 1
   for (int it = 0; it < 100; ++it) {
     double F, dF, d2F;
-    normal_speed_F(k, x, F, dF, d2F);
+    normal_speed_F(ee, k, x, F, dF, d2F);
     const double dx = halley_step(x, F - target, dF, d2F, lo, hi);
     if (dx <= 1e-5 * x || hi - lo <= 1e-15 * x) break;
   }
@@ -368,8 +371,8 @@ __device__ inline double sample_normal_speed(const float* __restrict__ tab, cons
 // solve (the frame is expanded afterwards), which keeps the persistent kernel
 // inside its register budget.
 __device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ lat_tab,
-                                     const float* __restrict__ vn_tab, const double* __restrict__ sc_tab, uint64_t pid,
-                                     double x[3], double w[3]) {
+                                     const float* __restrict__ vn_tab, const double* __restrict__ sc_tab,
+                                     const double* __restrict__ ee, uint64_t pid, double x[3], double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
   double p0, p1, p2, p3;  // sphere: mu, cos(phi), sin(th), cos(th); box: n_a, position on the face (2)
@@ -384,16 +387,16 @@ __device__ inline void seed_particle(const QueryDev& q, const float* __restrict_
     p1 = 2.0 * unif64(r0.b) - 1.0;
     p2 = 2.0 * unif64(r1.b) - 1.0;
     p3 = 0.0;
-    k = normal_speed_consts(q.face_s[f]);
+    k = normal_speed_consts(ee, q.face_s[f]);
   } else {
     LatEval le;
-    p0 = sample_latitude(q, lat_tab, unif64(r0.a), le);
+    p0 = sample_latitude(q, lat_tab, ee, unif64(r0.a), le);
     p1 = sqrt(fmax(0.0, 1.0 - p0 * p0));
     sincos_2pi_draw(sc_tab, r0.b, p2, p3);  // of 2 pi unif64(r0.b)
     const double s_n = q.S * p0;
-    k = le.valid ? normal_speed_consts_near(s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(s_n);
+    k = le.valid ? normal_speed_consts_near(ee, s_n, q.S * le.t, le.e, le.ta) : normal_speed_consts(ee, s_n);
   }
-  const double wn = sample_normal_speed(vn_tab, k, unif64(r0.c));
+  const double wn = sample_normal_speed(vn_tab, ee, k, unif64(r0.c));
   const double rad = sqrt(-2.0 * log_draw(r0.d));  // ln unif64(r0.d)
   double sb, cb;
   sincos_2pi_draw(sc_tab, r1.a, sb, cb);  // of 2 pi unif64(r1.a)

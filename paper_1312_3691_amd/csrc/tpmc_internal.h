@@ -57,7 +57,8 @@ struct alignas(16) QueryDev {
   float tr_cap2;                     // cap of the re-emission temperature tau_r^2
   float scaleE, scaleE2;             // fixed-point scales of E and E^2
   uint32_t eacc;                     // energy accommodation on (else tau_r = tau)
-  uint32_t pad2_[3];
+  uint32_t pad2_;
+  double lat_k;                      // sqrt(pi) / (4 S), the erf term's factor in the latitude CDF
 };
 
 // Device result of the finalisation kernel (mirrors tpmc_result).

@@ -39,6 +39,16 @@ __device__ float g_lat_start[kLatNS * kLatNT];
 __device__ float g_vn_start[kVnNS * kVnNT];
 // sin and cos of 2 pi j / 256, j = 0..255 (sincos_2pi_draw)
 __device__ double g_sc_tab[512];
+// exp(-y_j^2) and erfc(y_j) at y_j = j / 256 (exp_erfc_grid)
+__device__ double g_ee_tab[2 * kExpErfcN];
+
+__global__ void ee_table_kernel(double* __restrict__ tab) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kExpErfcN) return;
+  const double y = (double)j * 0x1p-8;  // y and y^2 are exact
+  tab[2 * j] = exp(-(y * y));
+  tab[2 * j + 1] = erfc(y);
+}
 
 __global__ void sc_table_kernel(double* __restrict__ tab) {
   const int j = threadIdx.x;
@@ -49,7 +59,7 @@ __global__ void sc_table_kernel(double* __restrict__ tab) {
   tab[2 * j + 1] = c;
 }
 
-__global__ void lat_table_kernel(float* __restrict__ tab) {
+__global__ void lat_table_kernel(float* __restrict__ tab, const double* __restrict__ ee) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kLatNS * kLatNT) return;
   QueryDev q{};
@@ -57,34 +67,35 @@ __global__ void lat_table_kernel(float* __restrict__ tab) {
   q.erfS = erf(q.S);
   q.erfcS = erfc(q.S);
   q.expmS2 = exp(-q.S * q.S);
+  q.lat_k = kSqrtPi / (4.0 * q.S);
   const double t = (double)kLatT0 + (double)(i % kLatNT) * (double)kLatDT;
   const double u = 1.0 / (1.0 + exp(-t));
   double Z, G, dG, d2G, e, ta;
-  latitude_G(q, 1.0, Z, dG, d2G, e, ta);
+  latitude_G(q, ee, 1.0, Z, dG, d2G, e, ta);
   const double target = u * Z;
   double lo = -1.0, hi = 1.0;
   for (int it = 0; it < 60; ++it) {
     const double m = 0.5 * (lo + hi);
-    latitude_G(q, m, G, dG, d2G, e, ta);
+    latitude_G(q, ee, m, G, dG, d2G, e, ta);
     if (G < target) lo = m;
     else hi = m;
   }
   tab[i] = (float)(0.5 * (lo + hi));
 }
 
-__global__ void vn_table_kernel(float* __restrict__ tab) {
+__global__ void vn_table_kernel(float* __restrict__ tab, const double* __restrict__ ee) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= kVnNS * kVnNT) return;
   const double s = (double)kVnS0 + (double)(i / kVnNT) * (double)kVnDS;
   const double t = (double)kVnT0 + (double)(i % kVnNT) * (double)kVnDT;
   const double u = 1.0 / (1.0 + exp(-t));
-  const NormalSpeedConsts k = normal_speed_consts(s);
+  const NormalSpeedConsts k = normal_speed_consts(ee, s);
   const double target = u * k.chi;
   double lo = 0.0, hi = (s > 0.0 ? s : 0.0) + 8.0;
   for (int it = 0; it < 80; ++it) {
     const double m = 0.5 * (lo + hi);
     double F, dF, d2F;
-    normal_speed_F(k, m, F, dF, d2F);
+    normal_speed_F(ee, k, m, F, dF, d2F);
     if (F < target) lo = m;
     else hi = m;
   }
@@ -99,7 +110,7 @@ __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double x[3], w[3];
-    seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, i, x, w);
+    seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, i, x, w);
     x0[i] = (float)x[0];
     x1[i] = (float)x[1];
     x2[i] = (float)x[2];
@@ -728,7 +739,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               float xs[3], ws[3];
               if (pid < p_end) {
                 double x[3], w[3];
-                seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, pid, x, w);
+                seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, pid, x, w);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                   xs[c] = (float)x[c];
@@ -930,13 +941,16 @@ hipError_t init_seed_tables(hipStream_t st) {
   float* tab = nullptr;
   float* lat = nullptr;
   double* sc = nullptr;
+  double* ee = nullptr;
   hipError_t e = hipGetSymbolAddress((void**)&tab, HIP_SYMBOL(g_vn_start));
   if (e == hipSuccess) e = hipGetSymbolAddress((void**)&lat, HIP_SYMBOL(g_lat_start));
   if (e == hipSuccess) e = hipGetSymbolAddress((void**)&sc, HIP_SYMBOL(g_sc_tab));
+  if (e == hipSuccess) e = hipGetSymbolAddress((void**)&ee, HIP_SYMBOL(g_ee_tab));
   if (e != hipSuccess) return e;
   sc_table_kernel<<<1, 256, 0, st>>>(sc);
-  vn_table_kernel<<<(kVnNS * kVnNT + 255) / 256, 256, 0, st>>>(tab);
-  lat_table_kernel<<<(kLatNS * kLatNT + 255) / 256, 256, 0, st>>>(lat);
+  ee_table_kernel<<<(kExpErfcN + 255) / 256, 256, 0, st>>>(ee);  // before the solves that read it
+  vn_table_kernel<<<(kVnNS * kVnNT + 255) / 256, 256, 0, st>>>(tab, ee);
+  lat_table_kernel<<<(kLatNS * kLatNT + 255) / 256, 256, 0, st>>>(lat, ee);
   e = hipGetLastError();
   return e != hipSuccess ? e : hipStreamSynchronize(st);
 }
