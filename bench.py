@@ -368,6 +368,39 @@ def plate_ch(S, angle_deg, tau, alpha_E):
     return alpha_E * (m3 + (st * st + 1.0 - 2.0 * tau * tau) * m1) / S ** 3
 
 
+def workload_ceilings(args):
+    """Measured ceilings of the roofline on this GPU (tpmc_ceiling_*): VALU
+    issue for FP32 FMA, FP64 FMA and 32-bit integer multiply-add; streaming
+    reads from a 2 MiB buffer (held in every XCD's L2), a 64 MiB one (Infinity
+    Cache) and a 4 GiB one (HBM); int64 atomic adds in global memory onto 1, 16,
+    4096 and 2^20 addresses and in LDS onto 1, 16 and 512 addresses.  Each is
+    one event-timed launch after an untimed one."""
+    import torch
+
+    from paper_1312_3691_amd import tpmc
+
+    ctx = tpmc.Context(0)
+    sink = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    out = {"metric": "measured ceilings on 1 MI355X", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "ceiling microkernels (VALU, cache and HBM reads, atomics)"}}
+    valu = {k: ctx.ceiling_valu(k, sink) for k in ("fp32_fma", "fp64_fma", "int32_mul_add")}
+    log(f"valu {valu}")
+    reads = {}
+    for name, nbytes, passes in (("l2_2MiB", 2 << 20, 400), ("mall_64MiB", 64 << 20, 20), ("hbm_4GiB", 4 << 30, 2)):
+        buf = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        reads[name] = ctx.ceiling_read(buf, passes)
+        del buf
+        log(f"read {name} {reads[name] / 1e12:.2f} TB/s")
+    abuf = torch.zeros(1 << 20, dtype=torch.int64, device="cuda")
+    atom = {str(sl): ctx.ceiling_atomic(abuf, sl, 16) for sl in (1, 16, 4096, 1 << 20)}
+    lds = {str(sl): ctx.ceiling_lds_atomic(sink, sl, 256) for sl in (1, 16, 512)}
+    torch.cuda.synchronize()
+    out.update({"valu_lane_ops_per_s": valu, "valu_published_lane_ops_per_s": ALU_PEAK,
+                "read_bytes_per_s": reads, "hbm_published_bytes_per_s": 8e12,
+                "global_atomic_i64_per_s_by_slots": atom, "lds_atomic_i64_per_s_by_slots": lds})
+    print(json.dumps(out), flush=True)
+
+
 def workload_energy(args):
     """Energy exchange and incomplete energy accommodation: diffuse
     re-emission at tau_r^2 = alpha_E tau^2 + (1 - alpha_E)|w|^2 / 2, alpha_E
@@ -644,7 +677,7 @@ def main():
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
     ap.add_argument("--workload", default="plate-cylinder",
                     choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv",
-                             "energy"],
+                             "energy", "ceilings"],
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
@@ -680,7 +713,7 @@ def main():
     if args.workload != "plate-cylinder":
         {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served,
          "pratt": workload_pratt, "moments": workload_moments, "boxcv": workload_boxcv,
-         "energy": workload_energy}[args.workload](args)
+         "energy": workload_energy, "ceilings": workload_ceilings}[args.workload](args)
         return
 
     import torch
@@ -757,8 +790,14 @@ def main():
     achieved = ops / launch_s
     workload = "plate+cylinder sweep, 120 cases x 1e7 particles"
     traffic = stored_traffic("batch_kernel", workload)
+    # the same GPU's measured VALU ceilings (tpmc_ceiling_valu, ~0.1 s): the kernel mixes FP32 and
+    # FP64 work, whose unpacked FMA rates bracket the one-per-lane-per-clock peak
+    sink = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    measured = {k: ctx.ceiling_valu(k, sink) / 1e12 for k in ("fp32_fma", "fp64_fma")}
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK / 1e12, "unit": "Tlane-op/s",
                 "frac": achieved / ALU_PEAK, "traffic": traffic,
+                "measured_ceilings": measured,
+                "frac_of_measured_fp32_fma": achieved / 1e12 / measured["fp32_fma"],
                 "kernel": "batch_kernel (seed + trace + tally fused)", "kernel_ms_per_step": launch_s * 1e3,
                 "launch_ms": kern_ms,
                 "work_per_step": {"particles": particles, "segments": segments, "hits": hits,

@@ -285,6 +285,35 @@ void tpmc_destroy_server(tpmc_server s);
 tpmc_status tpmc_check_mesh(const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt);
 tpmc_status tpmc_check_query(const tpmc_query* q, const float* xyz, uint64_t nv);
 
+/* ---- Measured ceilings of the roofline ----
+ * The path is not a dense contraction and its working set stays in the
+ * caches, so it is bound by VALU issue, cache bandwidth and atomics rather
+ * than by HBM.  These entry points time microkernels on the context's device
+ * and stream (one untimed launch, then one launch between two events; they
+ * synchronise the stream) and return the measured rate.  Buffers are the
+ * caller's device memory; the library allocates nothing.  They change no
+ * other state: the VALU and LDS kernels never write their sink (they keep
+ * their work live through a store that only a one-thread workgroup would make).
+ *   tpmc_ceiling_valu: kind 0 FP32 FMA, 1 FP64 FMA (lane FMAs per second), 2
+ *     32-bit integer multiply plus add (lane multiplies per second; the
+ *     Philox rounds are made of such products); sink >= 16 bytes.
+ *   tpmc_ceiling_read: streams reads of 16 bytes per lane over bytes (a
+ *     positive multiple of 16) of buf, passes times (>= 1); read bytes per
+ *     second.  The buffer's size chooses the level: a few MB stay in each
+ *     XCD's L2, tens of MB in the Infinity Cache, larger ones come from HBM.
+ *   tpmc_ceiling_atomic: per_thread (1..4096) int64 atomic adds per lane into
+ *     slots (1..2^26) int64 words of buf (adds 1 to them: zero or reuse it
+ *     afterwards as needed); atomics per second.
+ *   tpmc_ceiling_lds_atomic: the same into slots (1..1024) int64 words of each
+ *     workgroup's LDS; sink >= 16 bytes. */
+tpmc_status tpmc_ceiling_valu(tpmc_ctx ctx, uint32_t kind, void* dev_sink, double* lane_ops_per_s);
+tpmc_status tpmc_ceiling_read(tpmc_ctx ctx, const void* dev_buf, uint64_t bytes, uint32_t passes,
+                              double* bytes_per_s);
+tpmc_status tpmc_ceiling_atomic(tpmc_ctx ctx, void* dev_buf, uint32_t slots, uint32_t per_thread,
+                                double* atomics_per_s);
+tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots, uint32_t per_thread,
+                                    double* atomics_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpmc.so")
-SOURCES = ["tpmc_capi.hip", "tpmc_kernels.hip", "tpmc_bvh.hip"]
+SOURCES = ["tpmc_capi.hip", "tpmc_kernels.hip", "tpmc_bvh.hip", "tpmc_ceilings.hip"]
 HEADERS = ["tpmc_device.hpp", "tpmc_math.hpp", "tpmc_internal.h", "tpmc_launch.h"]
 ARCH = os.environ.get("TPMC_OFFLOAD_ARCH", "gfx950")
 

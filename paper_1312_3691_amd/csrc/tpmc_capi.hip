@@ -1130,3 +1130,88 @@ extern "C" tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot) {
 }
 
 extern "C" void tpmc_destroy_server(tpmc_server s) { delete s; }
+
+// ---------------------------------------------------------------------------
+// measured ceilings (tpmc_ceilings.hip)
+// ---------------------------------------------------------------------------
+// One untimed launch, then one launch between two events on the context's stream.
+template <class F>
+static tpmc_status time_launch(tpmc_ctx ctx, F launch, double* ms) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  launch();
+  HIP_CHECK_LAUNCH("ceiling");
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a));
+  hipError_t e = hipEventCreate(&b);
+  if (e == hipSuccess) e = hipEventRecord(a, ctx->stream);
+  if (e == hipSuccess) {
+    launch();
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, ctx->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float f = 0.0f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+  (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(TPMC_E_DEVICE, "ceiling timing: %s", hipGetErrorString(e));
+  if (!(f > 0.0f)) return fail(TPMC_E_DEVICE, "ceiling timing: elapsed time %g ms", (double)f);
+  *ms = (double)f;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_ceiling_valu(tpmc_ctx ctx, uint32_t kind, void* dev_sink, double* lane_ops_per_s) {
+  if (!ctx || !dev_sink || !lane_ops_per_s) return fail(TPMC_E_INVALID, "ctx, sink and out must not be NULL");
+  if (kind > 2) return fail(TPMC_E_INVALID, "kind = %u outside 0..2", kind);
+  const int grid = ctx->n_cu * 8;
+  const uint32_t iters = kind == 1 ? 1024u : 2048u;
+  double ms = 0.0;
+  const tpmc_status st =
+      time_launch(ctx, [&] { launch_ceiling_valu(kind, grid, iters, dev_sink, ctx->stream); }, &ms);
+  if (st != TPMC_OK) return st;
+  *lane_ops_per_s = (double)grid * kBlock * (double)ceiling_valu_ops_per_lane(iters) / (ms * 1e-3);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_ceiling_read(tpmc_ctx ctx, const void* dev_buf, uint64_t bytes, uint32_t passes,
+                                         double* bytes_per_s) {
+  if (!ctx || !dev_buf || !bytes_per_s) return fail(TPMC_E_INVALID, "ctx, buffer and out must not be NULL");
+  if (bytes == 0 || bytes % 16 != 0) return fail(TPMC_E_INVALID, "bytes = %llu is not a positive multiple of 16",
+                                                 (unsigned long long)bytes);
+  if (passes < 1) return fail(TPMC_E_INVALID, "passes must be >= 1");
+  const int grid = ctx->n_cu * 8;
+  double ms = 0.0;
+  const tpmc_status st =
+      time_launch(ctx, [&] { launch_ceiling_read(dev_buf, bytes, passes, grid, ctx->stream); }, &ms);
+  if (st != TPMC_OK) return st;
+  *bytes_per_s = (double)bytes * passes / (ms * 1e-3);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_ceiling_atomic(tpmc_ctx ctx, void* dev_buf, uint32_t slots, uint32_t per_thread,
+                                           double* atomics_per_s) {
+  if (!ctx || !dev_buf || !atomics_per_s) return fail(TPMC_E_INVALID, "ctx, buffer and out must not be NULL");
+  if (slots < 1 || slots > (1u << 26)) return fail(TPMC_E_INVALID, "slots = %u outside 1..2^26", slots);
+  if (per_thread < 1 || per_thread > 4096) return fail(TPMC_E_INVALID, "per_thread = %u outside 1..4096", per_thread);
+  const int grid = ctx->n_cu * 8;
+  double ms = 0.0;
+  const tpmc_status st =
+      time_launch(ctx, [&] { launch_ceiling_atomic(dev_buf, slots, per_thread, grid, ctx->stream); }, &ms);
+  if (st != TPMC_OK) return st;
+  *atomics_per_s = (double)grid * kBlock * per_thread / (ms * 1e-3);
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots, uint32_t per_thread,
+                                               double* atomics_per_s) {
+  if (!ctx || !dev_sink || !atomics_per_s) return fail(TPMC_E_INVALID, "ctx, sink and out must not be NULL");
+  if (slots < 1 || slots > 1024) return fail(TPMC_E_INVALID, "slots = %u outside 1..1024", slots);
+  if (per_thread < 1 || per_thread > 4096) return fail(TPMC_E_INVALID, "per_thread = %u outside 1..4096", per_thread);
+  const int grid = ctx->n_cu * 8;
+  double ms = 0.0;
+  const tpmc_status st =
+      time_launch(ctx, [&] { launch_ceiling_lds_atomic(dev_sink, slots, per_thread, grid, ctx->stream); }, &ms);
+  if (st != TPMC_OK) return st;
+  *atomics_per_s = (double)grid * kBlock * per_thread / (ms * 1e-3);
+  return TPMC_OK;
+}

@@ -78,6 +78,15 @@ void launch_finalize(const QueryDev* d_qs, const uint32_t* d_idx, const long lon
 void launch_reduce_slots(const QueryDev* d_qs, const uint32_t* d_idx, uint32_t n, long long* tally_base,
                          long long* scal_base, uint32_t max_nt, hipStream_t st);
 void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
+
+// Ceiling microkernels (tpmc_ceilings.hip).  kind 0: FP32 FMA, 1: FP64 FMA,
+// 2: int32 multiply and add; each lane performs ceiling_valu_ops_per_lane(iters)
+// of them.
+void launch_ceiling_valu(uint32_t kind, int grid, uint32_t iters, void* sink, hipStream_t st);
+uint64_t ceiling_valu_ops_per_lane(uint32_t iters);
+void launch_ceiling_read(const void* p, uint64_t bytes, uint32_t passes, int grid, hipStream_t st);
+void launch_ceiling_atomic(void* p, uint32_t slots, uint32_t per_thread, int grid, hipStream_t st);
+void launch_ceiling_lds_atomic(void* sink, uint32_t slots, uint32_t per_thread, int grid, hipStream_t st);
 void launch_reduce_batch(const QueryDev* d_qs, uint32_t nq, long long* tally_base, long long* scal_base,
                          uint32_t max_nt, hipStream_t st);
 

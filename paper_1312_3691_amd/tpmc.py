@@ -106,6 +106,10 @@ _SIGS = {
     "tpmc_destroy_server": ([_vp], None),
     "tpmc_check_mesh": ([_fp, _u64, ctypes.POINTER(_u32), _u64], ctypes.c_int),
     "tpmc_check_query": ([_QP, _fp, _u64], ctypes.c_int),
+    "tpmc_ceiling_valu": ([_vp, _u32, _vp, _dp], ctypes.c_int),
+    "tpmc_ceiling_read": ([_vp, _vp, _u64, _u32, _dp], ctypes.c_int),
+    "tpmc_ceiling_atomic": ([_vp, _vp, _u32, _u32, _dp], ctypes.c_int),
+    "tpmc_ceiling_lds_atomic": ([_vp, _vp, _u32, _u32, _dp], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -234,6 +238,32 @@ class Context:
         t = Tuning(int(cur["refill_lanes"]), int(cur["tile_particles"]), int(cur["groups_per_cu"]),
                    int(cur["plain_groups_per_cu"]))
         _check(_lib.tpmc_set_tuning(self._h, ctypes.byref(t)))
+
+    # measured ceilings (tpmc_ceiling_*); buffers are device tensors of the caller
+    CEILING_VALU_KINDS = {"fp32_fma": 0, "fp64_fma": 1, "int32_mul_add": 2}
+
+    def ceiling_valu(self, kind: str, sink) -> float:
+        out = ctypes.c_double()
+        _check(_lib.tpmc_ceiling_valu(self._h, self.CEILING_VALU_KINDS[kind], _vp(sink.data_ptr()), ctypes.byref(out)))
+        return out.value
+
+    def ceiling_read(self, buf, passes: int) -> float:
+        out = ctypes.c_double()
+        nbytes = buf.numel() * buf.element_size()
+        _check(_lib.tpmc_ceiling_read(self._h, _vp(buf.data_ptr()), nbytes, passes, ctypes.byref(out)))
+        return out.value
+
+    def ceiling_atomic(self, buf, slots: int, per_thread: int) -> float:
+        if buf.numel() * buf.element_size() < 8 * slots:
+            raise ValueError("buffer smaller than slots int64 words")
+        out = ctypes.c_double()
+        _check(_lib.tpmc_ceiling_atomic(self._h, _vp(buf.data_ptr()), slots, per_thread, ctypes.byref(out)))
+        return out.value
+
+    def ceiling_lds_atomic(self, sink, slots: int, per_thread: int) -> float:
+        out = ctypes.c_double()
+        _check(_lib.tpmc_ceiling_lds_atomic(self._h, _vp(sink.data_ptr()), slots, per_thread, ctypes.byref(out)))
+        return out.value
 
 
 class Mesh:
