@@ -580,10 +580,12 @@ def workload_served(args):
     max_slots = int(args.slots)
     pool_words = int(args.hbm_budget_gb * 2 ** 30) // 8
     tuning = tune_for(args, meshes["sat100k"], [q for m, q in reqs if m == "sat100k"][:64])
+    # the step budget is a particle count, so that the tuned tile size does not change it
+    tiles_per_step = max(1, int(args.particles_per_step) // int(tuning["tile_particles"]))
     ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=pool_words)
 
     def run(rate):
-        sched = Scheduler(ex, max_slots=max_slots, pool_words=pool_words, tiles_per_step=int(args.tiles_per_step))
+        sched = Scheduler(ex, max_slots=max_slots, pool_words=pool_words, tiles_per_step=tiles_per_step)
         gaps = rng.exponential(1.0 / rate, n_req) if rate else np.zeros(n_req)
 
         async def main():
@@ -658,7 +660,7 @@ def workload_served(args):
           {"workload": f"{n_warm} + {n_meas} requests over satellites {list(sizes.values())} tris, N log-uniform "
                        f"1e5-1e7, S~U[2,10], alpha=0.9, per-triangle tallies", "slots": max_slots,
            "hbm_budget_gb": args.hbm_budget_gb, "path": "continuous batching, one persistent launch per step",
-           "bvh": args.bvh},
+           "particles_per_step": int(args.particles_per_step), "tiles_per_step": tiles_per_step, "bvh": args.bvh},
           {"saturation": sat, "loads": loads, "query_ms_p50": loads["0.8"]["p50_ms"],
            "query_ms_p99": loads["0.8"]["p99_ms"], "fifo_plain_path": fifo, "served_equals_solo": bool(same),
            "tuning": tuning})
@@ -690,7 +692,8 @@ def main():
     ap.add_argument("--slots", type=int, default=64, help="served: request slots")
     ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="served: per-request tally budget")
     ap.add_argument("--fifo-requests", type=int, default=600, help="served: requests timed on the plain path")
-    ap.add_argument("--tiles-per-step", type=int, default=2048)
+    ap.add_argument("--particles-per-step", type=float, default=2048 * 65536,
+                    help="served: particles per continuous-batching step (split into tiles of the tuned size)")
     ap.add_argument("--bvh", default="sah", choices=["sah", "lbvh"], help="BVH builder (results do not depend on it)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (library defaults)")
     ap.add_argument("--tune-particles", type=float, default=0,
