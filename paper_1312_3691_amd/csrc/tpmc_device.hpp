@@ -101,7 +101,8 @@ struct LatConst32 {
 __device__ __forceinline__ void latitude_G32(const LatConst32& c, float t, float& G, float& dG, float& d2G) {
   const float St = c.S * t;
   const float e = expf(-St * St);
-  const float cc = erfcf(-St);
+  const float ey = e * erfcx32(fabsf(St));    // erfc(|S t|)
+  const float cc = St >= 0.0f ? 2.0f - ey : ey;  // erfc(-S t)
   const float E = c.small ? erff(St) + c.erfS : (St < -1.0f ? cc - c.erfcS : (cc - 1.0f) + c.erfS);
   G = (float)kSqrtPi / (4.0f * c.S) * E + 0.5f * (float)kSqrtPi * c.S * (t * t * cc - c.erfcS) +
       0.5f * (t * e + c.expmS2);
@@ -284,7 +285,7 @@ __device__ __forceinline__ void normal_speed_F32(float s, float es2, float erfs,
                                                  float& F, float& dF, float& d2F) {
   const float a = x - s;
   const float ea = expf(-a * a);
-  const float t = erfcf(fabsf(a));
+  const float t = ea * erfcx32(fabsf(a));  // erfc(|a|)
   const float esum = s < 0.0f ? erfcms - t : (a < 0.0f ? t - erfcs : (1.0f - t) + erfs);
   F = es2 - ea + (float)kSqrtPi * s * esum;
   dF = 2.0f * x * ea;

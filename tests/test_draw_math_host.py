@@ -70,7 +70,8 @@ def test_exp_erfc_grid_against_40_digits(ee_harness):
     series: within 2 ulp of 40-digit values wherever they are normal doubles
     (the grid points, both ends of every shift, the table's end, random y),
     within one subnormal unit below that, zero above the table; and with too
-    few terms the error must show (so the check can fail)."""
+    few terms the error must show (so the check can fail).  Also the FP32
+    erfcx32 of the seeding's approach stage, within 3e-7 relative."""
     mp = pytest.importorskip("mpmath")
     mp.mp.dps = 40
     rng = random.Random(3)
@@ -98,3 +99,11 @@ def test_exp_erfc_grid_against_40_digits(ee_harness):
         assert worst[(nterms, "e")] <= 2.0, worst
         assert worst[(nterms, "erfc")] <= 2.0, worst
     assert worst[(8, "e")] > 100.0, worst  # truncation visible with too few terms
+    # erfcx32 (FP32, the seeding's approach stage): within 3e-7 relative of exp(y^2) erfc(y) at the FP32 y
+    wx = 0.0
+    for r in rows:
+        if 0.0 <= r[8] <= 30.0:
+            yf = mp.mpf(r[8])
+            exact = mp.exp(yf * yf) * mp.erfc(yf)
+            wx = max(wx, float(abs(mp.mpf(r[9]) - exact) / exact))
+    assert wx <= 3e-7, wx
