@@ -28,7 +28,19 @@ __host__ __device__ inline double log_draw(uint32_t k) {
     m *= 0.5;
     ++e;
   }
-  const double s = (m - 1.0) / (m + 1.0);
+  // s = (m - 1)/(m + 1) without the general division's scaling and fix-up
+  // steps (its operands are far from every special case): a reciprocal, two
+  // Newton steps, and the remainder correction that rounds the quotient
+  const double num = m - 1.0, den = m + 1.0;
+#ifdef __HIP_DEVICE_COMPILE__
+  double r = __builtin_amdgcn_rcp(den);
+#else
+  double r = 1.0 / den;
+#endif
+  r = fma(fma(-den, r, 1.0), r, r);
+  r = fma(fma(-den, r, 1.0), r, r);
+  const double q0 = num * r;
+  const double s = fma(fma(-den, q0, num), r, q0);
   const double w = s * s;
   double p = 0x1.8618618618618p-4;  // 2/21
   p = fma(p, w, 0x1.af286bca1af28p-4);
