@@ -846,6 +846,20 @@ def main():
         pdt = time.perf_counter() - t0
         plain = {"hits_per_s": p_hits / pdt, "s_per_step": pdt,
                  "query_ms_p50": float(np.percentile(lat, 50)), "query_ms_p99": float(np.percentile(lat, 99))}
+        # the same queries one at a time through a one-query batch (seeding fused on chip; batch
+        # set-up, launch, results and host sync inside the timed span)
+        log("single-query batches")
+        lat_b = []
+        for c in cl:
+            if ctx.tuning != tunings[c["kind"]]:
+                ctx.set_tuning(**tunings[c["kind"]])
+            t1 = time.perf_counter()
+            b1 = tpmc.Batch(dev_mesh[c["kind"]], [c["query"]])
+            b1.launch(use_graph=False).results(A_ref=1.0)
+            lat_b.append((time.perf_counter() - t1) * 1e3)
+            b1.close()
+        plain["single_query_batch_ms_p50"] = float(np.percentile(lat_b, 50))
+        plain["single_query_batch_ms_p99"] = float(np.percentile(lat_b, 99))
 
     cpu = None
     if not args.no_cpu:
