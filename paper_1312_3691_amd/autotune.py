@@ -81,12 +81,12 @@ def sample_queries(queries: Sequence[dict], particles: int) -> List[dict]:
 
 
 def tune(mesh, queries: Sequence[dict], particles: int = None, reps: int = 1,
-         check_results: bool = True) -> Tuple[Dict[str, int], List[Trial]]:
+         check_results: bool = True, fixed: Dict[str, int] = None) -> Tuple[Dict[str, int], List[Trial]]:
     """Measure the batched launch of `queries` (reduced to about `particles`
     when given) on `mesh` under candidate tunings, set the fastest on the
     mesh's context and return it with every trial.  With check_results, every
     candidate's results must equal the first one's bit for bit (TpmcError
-    otherwise)."""
+    otherwise).  Settings in `fixed` are held and not searched."""
     import torch
 
     from . import tpmc
@@ -118,6 +118,9 @@ def tune(mesh, queries: Sequence[dict], particles: int = None, reps: int = 1,
             b.close()
         return ms
 
-    best, trials = coordinate_search(cost, start=ctx.tuning)
+    fixed = dict(fixed or {})
+    start = dict(ctx.tuning, **fixed)
+    axes = [(name, values) for name, values in AXES if name not in fixed]
+    best, trials = coordinate_search(cost, start=start, axes=axes)
     ctx.set_tuning(**best)
     return best, trials
