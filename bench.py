@@ -180,6 +180,38 @@ def summarize_traffic(pmc_dir, path=None):
     print(json.dumps(out, indent=1))
 
 
+SQ_COUNTERS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+               "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_BUSY_CYCLES"]
+L1_COUNTERS = ["TCP_TOTAL_CACHE_ACCESSES_sum", "TCP_TCC_READ_REQ_sum"]
+
+
+def summarize_counters(pmc_dir):
+    """Markdown summary of the batched kernels' instruction and cache counters
+    from two rocprofv3 --pmc runs under pmc_dir (sq: SQ_COUNTERS, l1:
+    L1_COUNTERS; this benchmark with --steps 1 --warmup 0 --no-cpu --no-plain):
+    per kernel, the median dispatch of each counter, the mean active lanes per
+    VALU instruction (SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU, of 64) and
+    the L1 hit fraction for vector memory."""
+    import re
+    per = {}
+    for sub, names in (("sq", SQ_COUNTERS), ("l1", L1_COUNTERS)):
+        for c in names:
+            for n, d, v in _counter_rows(os.path.join(pmc_dir, sub), c):
+                m = re.search(r"(?<![a-z_])batch_kernel<[^>]*>", n)
+                if m:
+                    per.setdefault(m.group(0), {}).setdefault(c, []).append(v)
+    lines = ["| kernel | " + " | ".join(SQ_COUNTERS + L1_COUNTERS) + " | active lanes per VALU instruction | L1 hit fraction |",
+             "|---" * (len(SQ_COUNTERS) + len(L1_COUNTERS) + 3) + "|"]
+    for k in sorted(per):
+        med = {c: sorted(v)[len(v) // 2] for c, v in per[k].items()}
+        lanes = med.get("SQ_THREAD_CYCLES_VALU", 0.0) / max(med.get("SQ_ACTIVE_INST_VALU", 1.0), 1.0)
+        acc, miss = med.get("TCP_TOTAL_CACHE_ACCESSES_sum", 0.0), med.get("TCP_TCC_READ_REQ_sum", 0.0)
+        hit = 1.0 - miss / acc if acc else float("nan")
+        lines.append(f"| `{k}` | " + " | ".join(f"{med.get(c, float('nan')):.4g}" for c in SQ_COUNTERS + L1_COUNTERS)
+                     + f" | {lanes:.1f} | {hit:.3f} |")
+    print("\n".join(lines))
+
+
 def fixed_tuning(args, key):
     """The --tuning settings for `key` (a mesh kind, or the workload), if given."""
     if not args.tuning:
@@ -679,6 +711,8 @@ def main():
     ap.add_argument("--particles", type=int, default=N_PER_CASE, help="particles per case (default 1e7)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the HBM-counter calibration copies")
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
+    ap.add_argument("--summarize-counters", metavar="PMC_DIR",
+                    help="print the batched kernels' instruction and L1 counters from runs under PMC_DIR/sq, PMC_DIR/l1")
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
     ap.add_argument("--workload", default="plate-cylinder",
                     choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv",
@@ -707,6 +741,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic, args.traffic_out)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
         return
     if args.copy_calibration:
         copy_calibration()
