@@ -160,8 +160,9 @@ def test_golden_bench_cases_regenerate():
     """bench_cases_exact.json (written by tests/golden/make_bench_exact.py, read
     by the benchmark's accuracy report) holds the per-facet closed forms of all
     120 cases: the plate rows equal the corrected eq. plate values (diffuse) and
-    the specular plate form, and the cylinder rows match the survey's table of
-    drag areas at 0/30/60/90 degrees."""
+    the specular plate form, and the cylinder rows match a four-digit table of
+    the capped cylinder's per-facet C_D at 0/30/60/90 degrees computed
+    independently of the oracle."""
     d = json.load(open(os.path.join(GOLD, "bench_cases_exact.json")))["cases"]
     assert len(d) == 120
     for row in d:
