@@ -80,6 +80,15 @@ def sample_queries(queries: Sequence[dict], particles: int) -> List[dict]:
     return [dict(q, n=min(int(q["n"]), max(4096, int(q["n"] * f)))) for q in queries]
 
 
+def free_axes(fixed: Dict[str, int] = None) -> List[Tuple[str, Sequence[int]]]:
+    """The search axes without the settings held in `fixed`."""
+    fixed = fixed or {}
+    unknown = set(fixed) - {name for name, _ in AXES} - {"plain_groups_per_cu"}
+    if unknown:
+        raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+    return [(name, values) for name, values in AXES if name not in fixed]
+
+
 def tune(mesh, queries: Sequence[dict], particles: int = None, reps: int = 1,
          check_results: bool = True, fixed: Dict[str, int] = None) -> Tuple[Dict[str, int], List[Trial]]:
     """Measure the batched launch of `queries` (reduced to about `particles`
@@ -119,8 +128,6 @@ def tune(mesh, queries: Sequence[dict], particles: int = None, reps: int = 1,
         return ms
 
     fixed = dict(fixed or {})
-    start = dict(ctx.tuning, **fixed)
-    axes = [(name, values) for name, values in AXES if name not in fixed]
-    best, trials = coordinate_search(cost, start=start, axes=axes)
+    best, trials = coordinate_search(cost, start=dict(ctx.tuning, **fixed), axes=free_axes(fixed))
     ctx.set_tuning(**best)
     return best, trials

@@ -40,3 +40,19 @@ def test_sample_queries_scales_particles():
     assert AT.sample_queries([{"n": 100}, {"n": 10 ** 8}], 10 ** 6)[0]["n"] == 100
     tiny = AT.sample_queries([{"n": 10_000_000}, {"n": 5000}], 1_000_000)
     assert min(q["n"] for q in tiny) >= 4096
+
+
+def test_held_settings_are_not_searched():
+    axes = AT.free_axes({"tile_particles": 65536})
+    assert [name for name, _ in axes] == ["refill_lanes", "groups_per_cu"]
+    start = dict(AT.DEFAULT, tile_particles=65536)
+    best, trials = AT.coordinate_search(lambda t: t["refill_lanes"] + t["groups_per_cu"], start=start, axes=axes)
+    assert all(t.tuning["tile_particles"] == 65536 for t in trials)
+    assert best == {"refill_lanes": 16, "tile_particles": 65536, "groups_per_cu": 4}
+    assert AT.free_axes(None) == list(AT.AXES)
+    try:
+        AT.free_axes({"tiles": 1})
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("an unknown field must be rejected")
