@@ -63,7 +63,16 @@ class OrcResult(ctypes.Structure):
                 ("Gamma_hat", ctypes.c_double), ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64),
                 ("segments", ctypes.c_uint64), ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64),
                 ("capped", ctypes.c_uint64), ("Qhat", ctypes.c_double), ("CH", ctypes.c_double),
-                ("CH_sigma", ctypes.c_double)]
+                ("CH_sigma", ctypes.c_double), ("Mhat", ctypes.c_double * 3)]
+
+
+_ip = ctypes.POINTER(ctypes.c_int32)
+_dpt = ctypes.POINTER(ctypes.c_double)
+
+
+class OrcParticleOut(ctypes.Structure):
+    _fields_ = [("first_tri", _ip), ("nhits", _ip), ("D", _dpt), ("E", _dpt), ("w_entry", _dpt),
+                ("w_exit", _dpt), ("dw", _dpt), ("L", _dpt)]
 
 
 def build(force: bool = False) -> str:
@@ -96,10 +105,17 @@ def lib():
             L.orc_reflect.argtypes = [ctypes.POINTER(OrcConsts), ctypes.c_uint64, ctypes.c_uint32, dp, dp, dp]
             L.orc_intersect.argtypes = [dp, dp, dp, dp, dp, dp, dp]
             L.orc_intersect.restype = ctypes.c_int
-            ip = ctypes.POINTER(ctypes.c_int32)
-            L.orc_trace_range.argtypes = [dp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint64,
+            up = ctypes.POINTER(ctypes.c_uint32)
+            L.orc_bvh_build.argtypes = [dp, ctypes.c_uint64, up, ctypes.c_uint64]
+            L.orc_bvh_build.restype = ctypes.c_void_p
+            L.orc_bvh_free.argtypes = [ctypes.c_void_p]
+            L.orc_bvh_nodes.argtypes = [ctypes.c_void_p]
+            L.orc_bvh_nodes.restype = ctypes.c_uint64
+            L.orc_closest.argtypes = [dp, up, ctypes.c_uint64, ctypes.c_void_p, dp, dp, ctypes.c_int64, dp, dp]
+            L.orc_closest.restype = ctypes.c_int64
+            L.orc_trace_range.argtypes = [dp, ctypes.c_uint64, up, ctypes.c_uint64, ctypes.c_void_p,
                                           ctypes.POINTER(OrcConsts), ctypes.c_uint64, ctypes.c_uint64, dp, dp,
-                                          ctypes.POINTER(OrcScalars), ip, ip, dp, dp]
+                                          ctypes.POINTER(OrcScalars), ctypes.POINTER(OrcParticleOut)]
             L.orc_trace_range.restype = ctypes.c_int
             L.orc_finalize.argtypes = [ctypes.POINTER(OrcConsts), dp, ctypes.c_uint64, ctypes.POINTER(OrcScalars),
                                        dp, ctypes.c_double, ctypes.POINTER(OrcResult)]
@@ -177,6 +193,52 @@ def intersect(o, d, v0, v1, v2):
     return (float(t[0]), b) if hit else None
 
 
+# Meshes above this many triangles are traced through the oracle's own
+# median-split hierarchy unless a call says otherwise (same closest hits).
+BVH_MIN_TRIS = 2000
+
+
+class BVH:
+    """The oracle's median-split hierarchy of one mesh (FP64, built on the host).
+    Keeps its own copies of the vertex and index arrays."""
+
+    def __init__(self, V, T):
+        self.V = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1, 3))
+        self.T = np.ascontiguousarray(np.asarray(T, dtype=np.uint32).reshape(-1, 3))
+        self._h = lib().orc_bvh_build(_dp(self.V), self.V.shape[0],
+                                      self.T.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), self.T.shape[0])
+        self.nodes = int(lib().orc_bvh_nodes(self._h))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def matches(self, V, T) -> bool:
+        V = np.asarray(V, dtype=np.float64).reshape(-1, 3)
+        T = np.asarray(T).reshape(-1, 3)
+        return V.shape == self.V.shape and T.shape == self.T.shape and np.array_equal(V, self.V) and \
+            np.array_equal(T, self.T)
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h and _lib is not None:
+            _lib.orc_bvh_free(h)
+
+
+def closest(V, T, o, d, prev=-1, bvh=None):
+    """Closest hit of one ray (triangle index or -1, t, barycentrics), by brute
+    force or through ``bvh`` (a ``BVH`` of the same mesh)."""
+    Vd = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1, 3))
+    Ti = np.ascontiguousarray(np.asarray(T, dtype=np.uint32).reshape(-1, 3))
+    oo = np.ascontiguousarray(o, dtype=np.float64)
+    dd = np.ascontiguousarray(d, dtype=np.float64)
+    t = np.zeros(1)
+    b = np.zeros(3)
+    k = lib().orc_closest(_dp(Vd), Ti.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), Ti.shape[0],
+                          bvh.handle if bvh is not None else None, _dp(oo), _dp(dd), int(prev), _dp(t), _dp(b))
+    return int(k), float(t[0]), b
+
+
 def _neumaier_merge(parts):
     s = np.zeros_like(parts[0])
     c = np.zeros_like(parts[0])
@@ -189,18 +251,32 @@ def _neumaier_merge(parts):
 
 
 def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int | None = None,
-        p_range=None, per_particle: bool = False, round_fp32: bool = True, n_chunks: int = N_CHUNKS) -> dict:
+        p_range=None, per_particle: bool = False, round_fp32: bool = True, n_chunks: int = N_CHUNKS,
+        bvh="auto", exits: bool = False) -> dict:
     """Run the oracle on particles ``p_range`` (default all N) of query ``qd``.
 
     Returns a dict with the finalised result (computed with the query's N, so
     it is only a drag estimate when ``p_range`` covers all particles), the raw
     per-triangle sums ``tri`` ([nt, 7]: dw xyz, p x dw xyz, count), the scalar
-    sums and, if asked, per-particle ``first_tri``, ``nhits`` and ``D``.
+    sums and, if asked, per-particle ``first_tri``, ``nhits``, ``D`` and ``E``;
+    with ``exits`` also ``w_entry``, ``w_exit``, ``dw`` and ``L`` ([n, 3]).
+
+    ``bvh``: "auto" traces meshes above BVH_MIN_TRIS triangles through the
+    oracle's hierarchy, True / False force it on / off, or a prebuilt ``BVH``
+    of the same mesh.  The closest hits, hence the results, do not depend on it.
     """
     L = lib()
     Vd = np.ascontiguousarray(np.asarray(V, dtype=np.float64).reshape(-1, 3))
     Ti = np.ascontiguousarray(np.asarray(T, dtype=np.uint32).reshape(-1, 3))
     nt = Ti.shape[0]
+    if isinstance(bvh, BVH):
+        if not bvh.matches(Vd, Ti):
+            raise ValueError("oracle: the hierarchy was built for another mesh")
+        tree = bvh
+    elif bvh is True or (bvh == "auto" and nt > BVH_MIN_TRIS):
+        tree = BVH(Vd, Ti)
+    else:
+        tree = None
     c = setup(Vd, qd, round_fp32)
     p0, p1 = (0, int(qd["n"])) if p_range is None else (int(p_range[0]), int(p_range[1]))
     n = p1 - p0
@@ -210,19 +286,24 @@ def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int 
     nh = np.zeros(n, np.int32) if per_particle else None
     Dp = np.zeros(n) if per_particle else None
     Ep = np.zeros(n) if per_particle else None
+    vec = {name: np.zeros((n, 3)) for name in ("w_entry", "w_exit", "dw", "L")} if exits else {}
 
     def work(i):
         a, b = bounds[i], bounds[i + 1]
         ts = np.zeros(nt * 7)
         tc = np.zeros(nt * 7)
         sc = OrcScalars()
-        ip = ctypes.POINTER(ctypes.c_int32)
-        fptr = first[a - p0:].ctypes.data_as(ip) if per_particle else None
-        hptr = nh[a - p0:].ctypes.data_as(ip) if per_particle else None
-        dptr = _dp(Dp[a - p0:]) if per_particle else None
-        eptr = _dp(Ep[a - p0:]) if per_particle else None
+        po = OrcParticleOut()
+        if per_particle:
+            po.first_tri = first[a - p0:].ctypes.data_as(_ip)
+            po.nhits = nh[a - p0:].ctypes.data_as(_ip)
+            po.D = _dp(Dp[a - p0:])
+            po.E = _dp(Ep[a - p0:])
+        for name, arr in vec.items():
+            setattr(po, name, _dp(arr[a - p0:]))
         L.orc_trace_range(_dp(Vd), Vd.shape[0], Ti.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), nt,
-                          ctypes.byref(c), a, b, _dp(ts), _dp(tc), ctypes.byref(sc), fptr, hptr, dptr, eptr)
+                          tree.handle if tree is not None else None, ctypes.byref(c), a, b, _dp(ts), _dp(tc),
+                          ctypes.byref(sc), ctypes.byref(po))
         return ts + tc, sc
 
     nthreads = threads or min(os.cpu_count() or 1, 16)
@@ -244,4 +325,6 @@ def run(V, T, qd: dict, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0, threads: int 
                threads=nthreads)
     if per_particle:
         out.update(first_tri=first, nhits=nh, D=Dp, E=Ep)
+    out.update(vec)
+    out["bvh_nodes"] = tree.nodes if tree is not None else 0
     return out

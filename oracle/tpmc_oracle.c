@@ -3,8 +3,9 @@
  *
  * TEST INFRASTRUCTURE ONLY (see tpmc_oracle.h).  Plain, slow and written for a
  * reader checking it against the paper: every inverse CDF is solved by pure
- * bisection, every ray is tested against every triangle, every sum is a
- * Neumaier-compensated FP64 sum.  Nothing here is shared with the GPU path.
+ * bisection, every ray is tested against every triangle (or, for large meshes,
+ * against the triangles of every box of a plain median-split hierarchy that it
+ * enters; same closest hit), every sum is a Neumaier-compensated FP64 sum.  Nothing here is shared with the GPU path.
  *
  * Paper: J. B. Parham and L. A. Barba, "Finding the Force -- Consistent
  * Particle Seeding for Satellite Aerodynamics", AIAA.
@@ -12,6 +13,7 @@
 #include "tpmc_oracle.h"
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define ORC_PI 3.14159265358979323846
@@ -385,15 +387,11 @@ void orc_reflect(const orc_consts* c, uint64_t pid, uint32_t b, const double w_i
      * Sec. I; Sentman's definition alpha_E = (E_i - E_r)/(E_i - E_w)), the
      * molecule leaves diffusely at the temperature whose flux-weighted mean
      * energy 2kT_r is E_r = (1 - alpha_E) E_i + alpha_E 2kT_w, i.e.
-     * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 per molecule, capped at
-     * max(tau^2, (S + 15)^2 / 2) so that speeds stay bounded over repeated
-     * re-emissions (the cap binds only after an extreme variate). */
+     * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 per molecule. */
     double tr = c->tau;
     if (c->eacc) {
       double e_in = w_in[0] * w_in[0] + w_in[1] * w_in[1] + w_in[2] * w_in[2];
-      double tr2 = c->alpha_E * c->tau * c->tau + (1.0 - c->alpha_E) * 0.5 * e_in;
-      double cap2 = fmax(c->tau * c->tau, 0.5 * (c->S + 15.0) * (c->S + 15.0));
-      tr = sqrt(tr2 < cap2 ? tr2 : cap2);
+      tr = sqrt(c->alpha_E * c->tau * c->tau + (1.0 - c->alpha_E) * 0.5 * e_in);
     }
     double vn = tr * sqrt(-log(ub));
     double rad = sqrt(-2.0 * log(uc));
@@ -438,6 +436,138 @@ int orc_intersect(const double o[3], const double d[3], const double v0[3], cons
   return 1;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Closest hit on the triangulation (Sec. II.A), by brute force or through a   */
+/* plain bounding-volume hierarchy.                                            */
+/* ------------------------------------------------------------------------- */
+/* Hierarchy: median split.  A node's triangles are split at the median of     */
+/* their centroids along the axis where the centroids spread most (ties in the */
+/* centroid go by triangle index); a leaf holds at most 4 triangles.  Every box */
+/* is the union of its triangles' vertex boxes widened by a margin far above   */
+/* FP64 rounding.  The hierarchy only prunes: a box is skipped when the ray    */
+/* misses it or enters it beyond the best t found so far (with a relative      */
+/* slack), and candidates are ranked by (t, index) exactly as the brute-force  */
+/* loop ranks them, so both return the same triangle, t and barycentrics.      */
+struct orc_bvh {
+  uint64_t n_nodes;
+  double* lo;        /* [n_nodes][3] widened box */
+  double* hi;
+  int64_t* child;    /* [n_nodes][2]: child node ids; {-1, -1} for a leaf */
+  uint64_t* first;   /* leaf: first position in idx */
+  uint32_t* count;   /* leaf: number of triangles */
+  uint32_t* idx;     /* triangle indices in leaf order */
+};
+
+typedef struct {
+  double key;
+  uint32_t tri;
+} orc_key;
+
+static int orc_key_cmp(const void* a, const void* b) {
+  const orc_key* x = (const orc_key*)a;
+  const orc_key* y = (const orc_key*)b;
+  if (x->key < y->key) return -1;
+  if (x->key > y->key) return 1;
+  return (x->tri > y->tri) - (x->tri < y->tri);
+}
+
+static uint64_t bvh_node(orc_bvh* h, const double* V, const uint32_t* T, orc_key* keys, uint64_t a, uint64_t b,
+                         double pad) {
+  uint64_t id = h->n_nodes++;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (uint64_t i = a; i < b; ++i) {
+    uint32_t k = h->idx[i];
+    for (int j = 0; j < 3; ++j) {
+      double c = 0.0;
+      for (int v = 0; v < 3; ++v) {
+        double x = V[3 * (uint64_t)T[3 * (uint64_t)k + v] + j];
+        if (x < lo[j]) lo[j] = x;
+        if (x > hi[j]) hi[j] = x;
+        c += x;
+      }
+      c /= 3.0;
+      if (c < clo[j]) clo[j] = c;
+      if (c > chi[j]) chi[j] = c;
+    }
+  }
+  for (int j = 0; j < 3; ++j) {
+    h->lo[3 * id + j] = lo[j] - pad;
+    h->hi[3 * id + j] = hi[j] + pad;
+  }
+  if (b - a <= 4) {
+    h->child[2 * id] = h->child[2 * id + 1] = -1;
+    h->first[id] = a;
+    h->count[id] = (uint32_t)(b - a);
+    return id;
+  }
+  int axis = 0;
+  for (int j = 1; j < 3; ++j)
+    if (chi[j] - clo[j] > chi[axis] - clo[axis]) axis = j;
+  for (uint64_t i = a; i < b; ++i) {
+    uint32_t k = h->idx[i];
+    double c = 0.0;
+    for (int v = 0; v < 3; ++v) c += V[3 * (uint64_t)T[3 * (uint64_t)k + v] + axis];
+    keys[i].key = c / 3.0;
+    keys[i].tri = k;
+  }
+  qsort(keys + a, b - a, sizeof(orc_key), orc_key_cmp);
+  for (uint64_t i = a; i < b; ++i) h->idx[i] = keys[i].tri;
+  uint64_t m = a + (b - a) / 2;
+  h->first[id] = 0;
+  h->count[id] = 0;
+  int64_t l = (int64_t)bvh_node(h, V, T, keys, a, m, pad);
+  int64_t r = (int64_t)bvh_node(h, V, T, keys, m, b, pad);
+  h->child[2 * id] = l;
+  h->child[2 * id + 1] = r;
+  return id;
+}
+
+orc_bvh* orc_bvh_build(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt) {
+  if (nt == 0) return NULL;
+  orc_bvh* h = (orc_bvh*)calloc(1, sizeof(orc_bvh));
+  uint64_t cap = 2 * nt;
+  h->lo = (double*)malloc(3 * cap * sizeof(double));
+  h->hi = (double*)malloc(3 * cap * sizeof(double));
+  h->child = (int64_t*)malloc(2 * cap * sizeof(int64_t));
+  h->first = (uint64_t*)malloc(cap * sizeof(uint64_t));
+  h->count = (uint32_t*)malloc(cap * sizeof(uint32_t));
+  h->idx = (uint32_t*)malloc(nt * sizeof(uint32_t));
+  orc_key* keys = (orc_key*)malloc(nt * sizeof(orc_key));
+  double amax = 0.0;
+  for (uint64_t i = 0; i < 3 * nv; ++i)
+    if (fabs(V[i]) > amax) amax = fabs(V[i]);
+  for (uint64_t k = 0; k < nt; ++k) h->idx[k] = (uint32_t)k;
+  bvh_node(h, V, T, keys, 0, nt, 1e-9 * (1.0 + amax));
+  free(keys);
+  return h;
+}
+
+void orc_bvh_free(orc_bvh* h) {
+  if (!h) return;
+  free(h->lo); free(h->hi); free(h->child); free(h->first); free(h->count); free(h->idx);
+  free(h);
+}
+
+uint64_t orc_bvh_nodes(const orc_bvh* h) { return h ? h->n_nodes : 0; }
+
+/* Whether the ray o + t d (t >= 0) meets box `id` no later than t_max. */
+static int bvh_box_hit(const orc_bvh* h, uint64_t id, const double o[3], const double d[3], double t_max) {
+  double tn = 0.0, tf = INFINITY;
+  for (int j = 0; j < 3; ++j) {
+    double lo = h->lo[3 * id + j], hi = h->hi[3 * id + j];
+    if (d[j] == 0.0) {
+      if (o[j] < lo || o[j] > hi) return 0;
+      continue;
+    }
+    double t0 = (lo - o[j]) / d[j], t1 = (hi - o[j]) / d[j];
+    if (t0 > t1) { double tmp = t0; t0 = t1; t1 = tmp; }
+    if (t0 > tn) tn = t0;
+    if (t1 < tf) tf = t1;
+  }
+  return tn <= tf && tn <= t_max * (1.0 + 1e-7);
+}
+
 static void tri_verts(const double* V, const uint32_t* T, uint64_t k, double v0[3], double v1[3], double v2[3]) {
   for (int j = 0; j < 3; ++j) {
     v0[j] = V[3 * (uint64_t)T[3 * k + 0] + j];
@@ -446,37 +576,72 @@ static void tri_verts(const double* V, const uint32_t* T, uint64_t k, double v0[
   }
 }
 
+/* Candidate k for the closest hit: t > 0, the triangle just left excluded;
+ * a smaller t wins, equal t goes to the lower index. */
+static void closest_consider(const double* V, const uint32_t* T, uint64_t k, int64_t prev, const double o[3],
+                             const double d[3], int64_t* best, double* best_t, double best_b[3]) {
+  if ((int64_t)k == prev) return;
+  double v0[3], v1[3], v2[3], t, b[3];
+  tri_verts(V, T, k, v0, v1, v2);
+  if (!orc_intersect(o, d, v0, v1, v2, &t, b)) return;
+  if (t < *best_t || (t == *best_t && (int64_t)k < *best)) {
+    *best_t = t;
+    *best = (int64_t)k;
+    best_b[0] = b[0]; best_b[1] = b[1]; best_b[2] = b[2];
+  }
+}
+
+int64_t orc_closest(const double* V, const uint32_t* T, uint64_t nt, const orc_bvh* bvh, const double o[3],
+                    const double d[3], int64_t prev, double* t_out, double b_out[3]) {
+  int64_t best = -1;
+  double best_t = INFINITY;
+  double best_b[3] = {0.0, 0.0, 0.0};
+  if (!bvh) {
+    for (uint64_t k = 0; k < nt; ++k) closest_consider(V, T, k, prev, o, d, &best, &best_t, best_b);
+  } else {
+    uint64_t stack[128];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+      uint64_t id = stack[--sp];
+      if (!bvh_box_hit(bvh, id, o, d, best_t)) continue;
+      if (bvh->child[2 * id] < 0) {
+        for (uint32_t i = 0; i < bvh->count[id]; ++i)
+          closest_consider(V, T, bvh->idx[bvh->first[id] + i], prev, o, d, &best, &best_t, best_b);
+      } else {
+        stack[sp++] = (uint64_t)bvh->child[2 * id + 1];
+        stack[sp++] = (uint64_t)bvh->child[2 * id];
+      }
+    }
+  }
+  *t_out = best_t;
+  b_out[0] = best_b[0]; b_out[1] = best_b[1]; b_out[2] = best_b[2];
+  return best;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Trace, interact and tally (Sec. II.A; multiple reflections, Sec. I).        */
 /* ------------------------------------------------------------------------- */
-int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt,
+int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt, const orc_bvh* bvh,
                     const orc_consts* c, uint64_t p0, uint64_t p1,
-                    double* tri_sum, double* tri_comp, orc_scalars* sc,
-                    int32_t* first_tri, int32_t* nhits, double* Dp, double* Ep) {
+                    double* tri_sum, double* tri_comp, orc_scalars* sc, const orc_particle_out* po) {
   (void)nv;
   for (uint64_t pid = p0; pid < p1; ++pid) {
     double o[3], w[3];
     orc_seed_one(c, pid, o, w, 0);
+    uint64_t i = pid - p0;
+    if (po && po->w_entry)
+      for (int k = 0; k < 3; ++k) po->w_entry[3 * i + k] = w[k];
     int64_t prev = -1;
     uint32_t hits = 0;
     double D = 0.0, E = 0.0;
+    double dwp[3] = {0.0, 0.0, 0.0}, Lp[3] = {0.0, 0.0, 0.0};
     int32_t first = -1;
     sc->rays += 1;
     for (;;) {
       sc->segments += 1;
-      /* Closest hit over every triangle except the one just left; ties in t
-       * keep the lower index because only a strictly smaller t replaces it. */
-      int64_t best = -1;
-      double best_t = INFINITY, best_b[3] = {0, 0, 0};
-      for (uint64_t k = 0; k < nt; ++k) {
-        if ((int64_t)k == prev) continue;
-        double v0[3], v1[3], v2[3], t, b[3];
-        tri_verts(V, T, k, v0, v1, v2);
-        if (orc_intersect(o, w, v0, v1, v2, &t, b) && t < best_t) {
-          best_t = t; best = (int64_t)k;
-          best_b[0] = b[0]; best_b[1] = b[1]; best_b[2] = b[2];
-        }
-      }
+      double best_t, best_b[3];
+      int64_t best = orc_closest(V, T, nt, bvh, o, w, prev, &best_t, best_b);
       if (best < 0) {
         if (hits == 0) sc->missed += 1;
         else sc->escaped += 1;
@@ -505,6 +670,7 @@ int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt
       double* cc = tri_comp + 7 * (uint64_t)best;
       for (int k = 0; k < 3; ++k) { nsum(s + k, cc + k, dw[k]); nsum(s + 3 + k, cc + 3 + k, L[k]); }
       s[6] += 1.0;
+      for (int k = 0; k < 3; ++k) { dwp[k] += dw[k]; Lp[k] += L[k]; }
       D += dw[0] * c->U[0] + dw[1] * c->U[1] + dw[2] * c->U[2];
       /* energy given to the body by this hit, in units of m c_mp^2 / 2 */
       E += (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]) - (wout[0] * wout[0] + wout[1] * wout[1] + wout[2] * wout[2]);
@@ -519,11 +685,17 @@ int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt
     nsum(&sc->D2, &sc->D2_c, D * D);
     nsum(&sc->E, &sc->E_c, E);
     nsum(&sc->E2, &sc->E2_c, E * E);
-    uint64_t i = pid - p0;
-    if (first_tri) first_tri[i] = first;
-    if (nhits) nhits[i] = (int32_t)hits;
-    if (Dp) Dp[i] = D;
-    if (Ep) Ep[i] = E;
+    if (po) {
+      if (po->first_tri) po->first_tri[i] = first;
+      if (po->nhits) po->nhits[i] = (int32_t)hits;
+      if (po->D) po->D[i] = D;
+      if (po->E) po->E[i] = E;
+      for (int k = 0; k < 3; ++k) {
+        if (po->w_exit) po->w_exit[3 * i + k] = w[k];
+        if (po->dw) po->dw[3 * i + k] = dwp[k];
+        if (po->L) po->L[3 * i + k] = Lp[k];
+      }
+    }
   }
   return 0;
 }
@@ -532,7 +704,8 @@ int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt
 /* Force, moment and drag coefficient (eq. drag; Sec. II.A effective mass).    */
 /* Each particle carries the rate Gamma / N, so the force is                   */
 /*   F = rho c_mp^2 (Gamma_hat / N) sum (w - w'),  q = rho S^2 c_mp^2 / 2,      */
-/*   F / q = K sum (w - w') with K = 2 Gamma_hat / (N S^2).                     */
+/*   F / q = K sum (w - w') with K = 2 Gamma_hat / (N S^2); the moment likewise */
+/*   (Mhat = M / (rho c_mp^2), finite at S = 0 like Fhat).                     */
 /* ------------------------------------------------------------------------- */
 void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt, const orc_scalars* sc,
                   const double x_ref[3], double A_ref, orc_result* out) {
@@ -553,6 +726,7 @@ void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt, con
     out->F_over_q[j] = K * F[j];
     out->M_over_q[j] = K * M[j];
     out->Fhat[j] = c->Gamma_hat / N * F[j];
+    out->Mhat[j] = c->Gamma_hat / N * M[j];
   }
   out->CD = (out->F_over_q[0] * c->U[0] + out->F_over_q[1] * c->U[1] + out->F_over_q[2] * c->U[2]) / A_ref;
   double meanD = (sc->D + sc->D_c) / N;

@@ -72,7 +72,24 @@ typedef struct {
   uint64_t rays, hits, segments, missed, escaped, capped;
   double Qhat;               /* energy to the body per unit time / (n c_mp m c_mp^2 / 2) */
   double CH, CH_sigma;       /* heat-transfer coefficient Q / (rho U^3 A_ref / 2) and its sigma */
+  double Mhat[3];            /* moment about x_ref / (rho c_mp^2), finite at S = 0 */
 } orc_result;
+
+/* Optional per-particle outputs of orc_trace_range; every pointer may be NULL.
+ * Arrays have p1 - p0 entries ([n][3] for vectors). */
+typedef struct {
+  int32_t* first_tri;  /* first triangle hit, -1 when the particle missed */
+  int32_t* nhits;      /* hits (tallied collisions) */
+  double* D;           /* momentum given along U, sum over hits of (w - w').U */
+  double* E;           /* energy given, sum over hits of |w|^2 - |w'|^2 */
+  double* w_entry;     /* [n][3] velocity at the control volume (after FP32 rounding if asked) */
+  double* w_exit;      /* [n][3] velocity when it left (escaped, capped) or w_entry (missed) */
+  double* dw;          /* [n][3] sum over its hits of w - w' */
+  double* L;           /* [n][3] sum over its hits of p x (w - w') about the body origin */
+} orc_particle_out;
+
+/* Median-split bounding-volume hierarchy over a triangulation (opaque). */
+typedef struct orc_bvh orc_bvh;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -102,14 +119,26 @@ void orc_reflect(const orc_consts* c, uint64_t pid, uint32_t b,
 int orc_intersect(const double o[3], const double d[3], const double v0[3],
                   const double v1[3], const double v2[3], double* t, double b[3]);
 
-/* Trace particles [p0, p1) through the mesh, accumulating per-triangle sums
- * tri_sum/tri_comp ([nt][7]: dw_x, dw_y, dw_z, (p x dw)_x.._z, count; Neumaier
- * pairs) and the scalar sums.  Optional per-particle outputs (length p1 - p0):
- * first_tri (-1 when missed), nhits, Dp. */
-int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt,
+/* Hierarchy of the mesh V [nv][3], T [nt][3] (NULL when nt == 0); read-only
+ * after the build, so threads may share it.  Free with orc_bvh_free. */
+orc_bvh* orc_bvh_build(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt);
+void orc_bvh_free(orc_bvh* h);
+uint64_t orc_bvh_nodes(const orc_bvh* h);
+
+/* Closest hit of the ray o + t d over all triangles except `prev` (-1: none):
+ * t > 0, equal t to the lower index.  bvh NULL: every triangle is tested;
+ * otherwise through the hierarchy (same answer).  Returns the triangle index
+ * (-1 when nothing is hit) with t and barycentrics. */
+int64_t orc_closest(const double* V, const uint32_t* T, uint64_t nt, const orc_bvh* bvh, const double o[3],
+                    const double d[3], int64_t prev, double* t, double b[3]);
+
+/* Trace particles [p0, p1) through the mesh (bvh as in orc_closest),
+ * accumulating per-triangle sums tri_sum/tri_comp ([nt][7]: dw_x, dw_y, dw_z,
+ * (p x dw)_x.._z, count; Neumaier pairs) and the scalar sums.  po (optional)
+ * receives per-particle outputs. */
+int orc_trace_range(const double* V, uint64_t nv, const uint32_t* T, uint64_t nt, const orc_bvh* bvh,
                     const orc_consts* c, uint64_t p0, uint64_t p1,
-                    double* tri_sum, double* tri_comp, orc_scalars* sc,
-                    int32_t* first_tri, int32_t* nhits, double* Dp, double* Ep);
+                    double* tri_sum, double* tri_comp, orc_scalars* sc, const orc_particle_out* po);
 
 /* Convert merged sums to force, moment and drag coefficient. */
 void orc_finalize(const orc_consts* c, const double* tri_total, uint64_t nt,
