@@ -22,7 +22,7 @@
  *    BVH); every per-query buffer lives in a caller-provided workspace.
  *  - Work is enqueued on the context's HIP stream.  tpmc_seed, tpmc_trace and
  *    tpmc_batch_launch are asynchronous; tpmc_forces, tpmc_tally_copy,
- *    tpmc_batch_results and tpmc_run_batch synchronise the stream.
+ *    tpmc_batch_results and tpmc_server_results synchronise the stream.
  *  - Velocities are dimensionless, w = v / c_mp (Nomenclature: c_mp is the
  *    most probable thermal speed of the free stream).  Lengths are metres in
  *    the body frame.  All results are in the body frame.
@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 5
+#define TPMC_ABI_VERSION 6
 
 typedef enum {
   TPMC_OK = 0,
@@ -93,16 +93,20 @@ typedef struct {
  * energy" exchange, Sec. I): with alpha_E = (E_i - E_r) / (E_i - E_w) (Sentman)
  * and E = 2kT the flux-weighted mean energy of a re-emitted Maxwellian, a
  * molecule of incident velocity w leaves diffusely at the temperature
- * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 (units of T_inf),
- * capped at max(tau^2, (S + 15)^2 / 2) so that every speed stays bounded (the
- * cap binds only after an extreme re-emission variate).  alpha_E = 1 is the
- * default model. */
+ * tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 (units of T_inf).
+ * alpha_E = 1 is the default model.  Limit of this implementation, not of the
+ * model: the kernel bounds tau_r by max(tau, 8 (S + 15)) so that its
+ * fixed-point tallies stay in range; inside a cavity the bound can bind only
+ * at the far tail of the chain of re-emissions (tau_r^2 grows by a random
+ * factor per re-emission), and every re-emission it limits is counted in
+ * tpmc_result.tr_capped (a result with tr_capped > 0 departs from the model). */
 #define TPMC_Q_ENERGY_ACC 4u
 
 /* Result of one query.  Force and moment are divided by the dynamic pressure
- * q = rho U^2 / 2 (so they are areas, m^2, and m^3); Fhat = F / (rho c_mp^2) is
- * finite at S = 0.  CD = (F/q).U / A_ref; CD_sigma is its one-sigma
- * statistical error from the per-particle momentum along U. */
+ * q = rho U^2 / 2 (so they are areas, m^2, and m^3); Fhat = F / (rho c_mp^2)
+ * and Mhat = M / (rho c_mp^2) are finite at S = 0 (a gas at rest).
+ * CD = (F/q).U / A_ref; CD_sigma is its one-sigma statistical error from the
+ * per-particle momentum along U. */
 typedef struct {
   double F_over_q[3], M_over_q[3], Fhat[3];
   double CD, CD_sigma, Gamma_hat; /* Gamma_hat = Gamma / (n c_mp): CV number flux (Sec. III.A.1) */
@@ -114,6 +118,11 @@ typedef struct {
   uint64_t capped;   /* particles retired at max_reflections */
   double Qhat;       /* energy given to the body per unit time / (n c_mp m c_mp^2 / 2) */
   double CH, CH_sigma; /* heat-transfer coefficient Q / (rho U^3 A_ref / 2) and its sigma (NaN at S = 0) */
+  double Mhat[3];    /* moment about ref_point / (rho c_mp^2), m; finite at S = 0 (Fhat's counterpart) */
+  uint64_t tr_capped;   /* diffuse re-emissions whose temperature the kernel's bound limited
+                           (TPMC_Q_ENERGY_ACC only; 0 when the result follows the model exactly) */
+  uint64_t guard_trips; /* ray segments ended by the traversal's step bound instead of by the
+                           search (a damaged hierarchy); 0 for every valid mesh */
 } tpmc_result;
 
 typedef struct {

@@ -289,13 +289,19 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   // |w| <= S + 15 for seeded and specular velocities and |w| <= 8 tau after a
   // diffuse re-emission, so one hit moves at most Dmax; scales are the largest
   // powers of two keeping N * rmax hits of Dmax inside 2^62.
-  // With energy accommodation a re-emitted speed is at most ~7.1 tau_r, and
-  // tau_r^2 <= max(tau^2, (S + 15)^2 / 2) (the cap), so every |w| stays below
-  // B = max(8 tau, 5 (S + 15)).
+  // With energy accommodation a re-emitted speed is at most ~7.1 tau_r; the
+  // kernel bounds tau_r by max(tau, 8 (S + 15)) (a limit of these fixed-point
+  // tallies, not of the model: each re-emission it limits is counted in the
+  // result's tr_capped), so every |w| stays below B = max(8 tau, 57 (S + 15)).
+  // Inside a cavity tau_r follows a multiplicative chain with a power-law
+  // tail (tau_r^2 grows by a Gamma(2)-distributed factor times
+  // (1 - alpha_E) / 2 per re-emission), so the bound sits far above
+  // (S + 15)^2 / 2: at alpha_E = 0.2 in a cup that smaller bound is reached
+  // by about one particle in 1e5, this one by far fewer than one in 1e10.
   q->eacc = (in->flags & TPMC_Q_ENERGY_ACC) ? 1u : 0u;
   q->alpha_E = q->eacc ? (float)in->energy_accommodation : 1.0f;
-  q->tr_cap2 = (float)std::fmax(tau * tau, 0.5 * (S + 15.0) * (S + 15.0));
-  const double Dmax = q->eacc ? 2.0 * std::fmax(8.0 * tau, 5.0 * (S + 15.0)) : 2.0 * std::fmax(S + 15.0, 8.0 * tau);
+  q->tr_cap2 = (float)std::fmax(tau * tau, 64.0 * (S + 15.0) * (S + 15.0));
+  const double Dmax = q->eacc ? 2.0 * std::fmax(8.0 * tau, 57.0 * (S + 15.0)) : 2.0 * std::fmax(S + 15.0, 8.0 * tau);
   const double hits_max = (double)in->n_particles * (double)in->max_reflections;
   // One hit's scaled momentum (and moment) also stays below 2^30, so the
   // kernels convert it with a 32-bit conversion.
@@ -723,6 +729,9 @@ static void copy_result(const ResultDev& r, tpmc_result* o) {
   o->Qhat = r.Qhat;
   o->CH = r.CH;
   o->CH_sigma = r.CH_sigma;
+  for (int k = 0; k < 3; ++k) o->Mhat[k] = r.Mhat[k];
+  o->tr_capped = r.tr_capped;
+  o->guard_trips = r.guard_trips;
 }
 
 // Clears the per-query totals the reduction writes (slots kFx..kCount).
@@ -821,20 +830,14 @@ extern "C" tpmc_status tpmc_batch_workspace_bytes(tpmc_ctx ctx, tpmc_mesh m, con
   return TPMC_OK;
 }
 
-extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq, void* ws,
-                                         uint64_t ws_bytes, tpmc_batch* out) {
-  if (!ctx || !m || !out) return fail(TPMC_E_INVALID, "ctx, mesh and out must not be NULL");
-  *out = nullptr;
-  if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
-  tpmc_batch b = new (std::nothrow) tpmc_batch_s;
-  if (!b) return fail(TPMC_E_INVALID, "out of host memory");
+// Fills b for the queries q on mesh m with its workspace at ws (ws_bytes) and
+// uploads the query table and tile counts (synchronises).  Allocates nothing.
+static tpmc_status batch_init(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq, void* ws,
+                              uint64_t ws_bytes, tpmc_batch_s* b) {
   tpmc_status s = batch_prepare(m, q, nq, ctx->tune.tile_particles, b->hq, b->tiles, b->lay,
                                 static_cast<uint8_t*>(ws));
   if (s == TPMC_OK) s = check_ws(ws, ws_bytes, b->lay.bytes);
-  if (s != TPMC_OK) {
-    delete b;
-    return s;
-  }
+  if (s != TPMC_OK) return s;
   b->ctx = ctx;
   b->mesh = m;
   b->nq = nq;
@@ -847,10 +850,8 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
     any_tri = any_tri || hq.per_tri;
     all_tri = all_tri && hq.per_tri;
   }
-  if (any_tri && !all_tri) {
-    delete b;
+  if (any_tri && !all_tri)
     return fail(TPMC_E_INVALID, "a batch must use one tally kind (TPMC_Q_NO_TRIANGLE_TALLY on all or none)");
-  }
   b->mode = !any_tri ? kTallyTotals
                      : (m->nt <= (uint64_t)kLaneTallyMaxTris ? kTallyLane
                                                             : (m->nt <= (uint64_t)kLdsTallyMaxTris ? kTallyLds : kTallyGlobal));
@@ -866,9 +867,21 @@ extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_q
     e = hipMemcpyAsync(b->lay.tiles, b->tiles.data(), nq * sizeof(uint64_t), hipMemcpyHostToDevice,
                        ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) {
+  if (e != hipSuccess) return fail(TPMC_E_DEVICE, "batch upload: %s", hipGetErrorString(e));
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_batch_create(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq, void* ws,
+                                         uint64_t ws_bytes, tpmc_batch* out) {
+  if (!ctx || !m || !out) return fail(TPMC_E_INVALID, "ctx, mesh and out must not be NULL");
+  *out = nullptr;
+  if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
+  tpmc_batch b = new (std::nothrow) tpmc_batch_s;
+  if (!b) return fail(TPMC_E_INVALID, "out of host memory");
+  const tpmc_status s = batch_init(ctx, m, q, nq, ws, ws_bytes, b);
+  if (s != TPMC_OK) {
     delete b;
-    return fail(TPMC_E_DEVICE, "batch upload: %s", hipGetErrorString(e));
+    return s;
   }
   *out = b;
   return TPMC_OK;

@@ -522,19 +522,25 @@ __device__ __forceinline__ bool slab(const Ray& r, float lox, float loy, float l
 // Gas-surface interaction (Sec. II.A), FP32.  Maxwell model: diffuse with
 // probability alpha -- the particle leaves the side it arrived on with the
 // flux-weighted half-range Maxwellian of T_w (normal speed tau sqrt(-ln u),
-// tangential components N(0, tau^2/2)) -- else specular.
+// tangential components N(0, tau^2/2)) -- else specular.  Returns whether
+// the kernel's bound on the re-emission temperature (tr_cap2, which keeps the
+// fixed-point tallies in range) had to limit tau_r: the model itself has no
+// such bound, so a result with any such event departs from it.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void reemit(const QueryDev& q, uint64_t pid, uint32_t bounce, float nx, float ny, float nz,
+__device__ __forceinline__ bool reemit(const QueryDev& q, uint64_t pid, uint32_t bounce, float nx, float ny, float nz,
                                        float& wx, float& wy, float& wz) {
   const U4 r = stream(q, pid, 2u + bounce);
   const float wn = wx * nx + wy * ny + wz * nz;
+  bool limited = false;
   if (unif32(r.a) < q.alpha) {
     // temperature of the re-emitted Maxwellian: tau, or with energy
-    // accommodation tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2 (capped)
+    // accommodation tau_r^2 = alpha_E tau^2 + (1 - alpha_E) |w|^2 / 2
     float tr = q.tau;
     if (q.eacc) {
       const float e_in = wx * wx + wy * wy + wz * wz;
-      tr = sqrtf(fminf(q.alpha_E * q.tau * q.tau + (1.0f - q.alpha_E) * 0.5f * e_in, q.tr_cap2));
+      const float tr2 = q.alpha_E * q.tau * q.tau + (1.0f - q.alpha_E) * 0.5f * e_in;
+      limited = tr2 > q.tr_cap2;
+      tr = sqrtf(fminf(tr2, q.tr_cap2));
     }
     const float sg = wn < 0.0f ? 1.0f : -1.0f;
     const float sx = sg * nx, sy = sg * ny, sz = sg * nz;
@@ -558,6 +564,7 @@ __device__ __forceinline__ void reemit(const QueryDev& q, uint64_t pid, uint32_t
     wy -= k * ny;
     wz -= k * nz;
   }
+  return limited;
 }
 
 // ---------------------------------------------------------------------------

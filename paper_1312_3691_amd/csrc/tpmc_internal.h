@@ -9,7 +9,7 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
 constexpr int kMaxReflections = 64;
 constexpr int kLdsTallyMaxTris = 512;  // per-workgroup LDS tallies up to this mesh size
 constexpr int kLaneTallyMaxTris = 2;   // per-lane LDS tallies for tiny meshes
-constexpr int kScalarSlots = 18;       // int64 per query, see ScalarSlot
+constexpr int kScalarSlots = 20;       // int64 per query, see ScalarSlot
 
 // Per-query int64 block.  D is the momentum one particle gives the body along
 // the free stream (sum over its hits of (w - w').U); D and D^2 are quantised
@@ -17,7 +17,9 @@ constexpr int kScalarSlots = 18;       // int64 per query, see ScalarSlot
 enum ScalarSlot {
   kSD = 0, kSD2 = 1, kRays = 2, kHits = 3, kSegments = 4, kMissed = 5, kEscaped = 6, kCapped = 7,
   kFx = 8, kFy = 9, kFz = 10, kLx = 11, kLy = 12, kLz = 13, kCount = 14,
-  kSE = 15, kSE2 = 16  // per-particle energy E = sum over hits of |w|^2 - |w'|^2, and E^2
+  kSE = 15, kSE2 = 16,  // per-particle energy E = sum over hits of |w|^2 - |w'|^2, and E^2
+  kTrCap = 17,          // diffuse re-emissions whose temperature the kernel's bound limited
+  kGuard = 18           // ray segments ended by the traversal step bound (a damaged tree)
 };
 
 struct Node;
@@ -67,6 +69,8 @@ struct ResultDev {
   double CD, CD_sigma, Gamma_hat;
   uint64_t rays, hits, segments, missed, escaped, capped;
   double Qhat, CH, CH_sigma;
+  double Mhat[3];
+  uint64_t tr_capped, guard_trips;
 };
 
 // BVH node: the boxes of both children and the two child links (64 bytes).

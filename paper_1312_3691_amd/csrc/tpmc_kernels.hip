@@ -310,6 +310,8 @@ struct Hit {
 struct Acc {
   long long sD, sD2, sE, sE2, tot[7];
   uint32_t rays, hits, segs, missed, escaped, capped;
+  uint32_t tr_capped;     // re-emissions whose temperature the kernel's bound limited
+  uint32_t guard;         // segments ended by the traversal step bound
   uint32_t nodes, tests;  // traversal work (counting kernels only)
 };
 
@@ -318,6 +320,7 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
 #pragma unroll
   for (int c = 0; c < 7; ++c) A.tot[c] = 0;
   A.rays = A.hits = A.segs = A.missed = A.escaped = A.capped = 0;
+  A.tr_capped = A.guard = 0;
   A.nodes = A.tests = 0;
 }
 
@@ -330,7 +333,7 @@ enum Outcome : int { kOutGoOn = 0, kOutMissed = 1, kOutEscaped = 2, kOutCapped =
 // a7-a9 for a lane whose traversal has ended: re-emission and bookkeeping of
 // the hit, or the particle's exit.  The particle retires unless kOutGoOn.
 __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t* orig, const QueryDev& q, Lane& L,
-                                              const Seg& s, Hit& h, int32_t& first_id) {
+                                              const Seg& s, Hit& h, int32_t& first_id, uint32_t& tr_capped) {
   const int k = s.best;
   first_id = -2;  // not the first segment's outcome
   if (k < 0) {
@@ -347,7 +350,7 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
   const float py = s.b0 * tr.v0y + s.b1 * tr.v1y + s.b2 * tr.v2y;
   const float pz = s.b0 * tr.v0z + s.b1 * tr.v1z + s.b2 * tr.v2z;
   float nwx = L.wx, nwy = L.wy, nwz = L.wz;
-  reemit(q, L.pid, L.hits, tr.nx, tr.ny, tr.nz, nwx, nwy, nwz);
+  if (reemit(q, L.pid, L.hits, tr.nx, tr.ny, tr.nz, nwx, nwy, nwz)) ++tr_capped;
   L.E += (L.wx * L.wx + L.wy * L.wy + L.wz * L.wz) - (nwx * nwx + nwy * nwy + nwz * nwz);
   const float dx = L.wx - nwx, dy = L.wy - nwy, dz = L.wz - nwz;
   const float rx = px - q.c0f[0], ry = py - q.c0f[1], rz = pz - q.c0f[2];
@@ -457,7 +460,7 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
       lane_tot[c * kBlock + threadIdx.x] = 0ull;
     }
   }
-  long long s[8 + 7 + 2];
+  long long s[8 + 7 + 4];
   s[0] = wave_sum(A.sD);
   s[1] = wave_sum(A.sD2);
   s[2] = wave_sum((long long)A.rays);
@@ -468,6 +471,8 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
   s[7] = wave_sum((long long)A.capped);
   s[15] = wave_sum(A.sE);
   s[16] = wave_sum(A.sE2);
+  s[17] = wave_sum((long long)A.tr_capped);
+  s[18] = wave_sum((long long)A.guard);
   if (TOTALS) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) s[8 + c] = wave_sum(A.tot[c]);
@@ -478,6 +483,8 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
       if (s[c]) atomic_add_i64(scal + c, s[c]);
     if (s[15]) atomic_add_i64(scal + kSE, s[15]);
     if (s[16]) atomic_add_i64(scal + kSE2, s[16]);
+    if (s[17]) atomic_add_i64(scal + kTrCap, s[17]);
+    if (s[18]) atomic_add_i64(scal + kGuard, s[18]);
     if (TOTALS) {
 #pragma unroll
       for (int c = 0; c < 7; ++c)
@@ -545,7 +552,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
         int out = kOutGoOn;
         int32_t fid = -2;
         if (fin) {
-          out = finish_segment(a.tris, a.orig, q, L, s, h, fid);
+          out = finish_segment(a.tris, a.orig, q, L, s, h, fid, A.tr_capped);
           count_outcome(A, out, h.valid);
         }
         tally<MODE, false>(q, h, a.tally, lt, a.nt, A);
@@ -565,8 +572,11 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
     }
     // Between service passes every traversing lane ends its segment within
     // nt - 1 steps and nt leaf phases; the bound only keeps a damaged tree
-    // from spinning a wave.
-    if (++guard > max_steps) s.cur = kDone;
+    // from spinning a wave, and every segment it ends is counted.
+    if (++guard > max_steps) {
+      if (L.live && s.cur != kDone) ++A.guard;
+      s.cur = kDone;
+    }
     if (L.live && seg_traversing(s))
       trav_step<STACK, COUNT>(a.nodes, a.tris, a.orig, r, L.prev, s, stk, A.nodes, A.tests);
   }
@@ -703,7 +713,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           int out = kOutGoOn;
           int32_t fid;
           if (fin) {
-            out = finish_segment(tris, orig, q, L, s, h, fid);
+            out = finish_segment(tris, orig, q, L, s, h, fid, A.tr_capped);
             count_outcome(A, out, h.valid);
           }
           if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
@@ -793,8 +803,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
         guard = 0;
       }
-      // as in the plain path: a bound only against a damaged tree
-      if (++guard > max_steps) s.cur = kDone;
+      // as in the plain path: a bound only against a damaged tree, counted
+      if (++guard > max_steps) {
+        if (L.live && s.cur != kDone) ++A.guard;
+        s.cur = kDone;
+      }
       if (L.live && seg_traversing(s)) {
         uint32_t n0 = 0, n1 = 0;
         trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
@@ -868,6 +881,7 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
     r.F_over_q[k] = K * F[k];
     r.M_over_q[k] = K * M[k];
     r.Fhat[k] = q.Gamma_hat / N * F[k];
+    r.Mhat[k] = q.Gamma_hat / N * M[k];  // M / (rho c_mp^2), finite at S = 0
   }
   r.CD = (r.F_over_q[0] * q.U[0] + r.F_over_q[1] * q.U[1] + r.F_over_q[2] * q.U[2]) / A_ref;
   const double meanD = (double)s[kSD] * q.inv_scaleD / N;
@@ -890,6 +904,8 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
   r.missed = (uint64_t)s[kMissed];
   r.escaped = (uint64_t)s[kEscaped];
   r.capped = (uint64_t)s[kCapped];
+  r.tr_capped = (uint64_t)s[kTrCap];
+  r.guard_trips = (uint64_t)s[kGuard];
   out[i] = r;
 }
 

@@ -45,7 +45,8 @@ class Result(ctypes.Structure):
                 ("CD", ctypes.c_double), ("CD_sigma", ctypes.c_double), ("Gamma_hat", ctypes.c_double),
                 ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64), ("segments", ctypes.c_uint64),
                 ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64), ("capped", ctypes.c_uint64),
-                ("Qhat", ctypes.c_double), ("CH", ctypes.c_double), ("CH_sigma", ctypes.c_double)]
+                ("Qhat", ctypes.c_double), ("CH", ctypes.c_double), ("CH_sigma", ctypes.c_double),
+                ("Mhat", ctypes.c_double * 3), ("tr_capped", ctypes.c_uint64), ("guard_trips", ctypes.c_uint64)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -116,7 +117,7 @@ for _name, (_args, _res) in _SIGS.items():
     _f.argtypes = _args
     _f.restype = _res
 
-ABI_VERSION = 5  # the structures below are laid out for this version of include/tpmc.h
+ABI_VERSION = 6  # the structures below are laid out for this version of include/tpmc.h
 if _lib.tpmc_abi_version() != ABI_VERSION:
     raise ImportError(f"libtpmc.so has ABI version {_lib.tpmc_abi_version()}, this binding expects "
                       f"{ABI_VERSION}: rebuild the library (python -c 'import __graft_entry__ as g; g.build()')")

@@ -33,16 +33,31 @@ def test_every_declared_symbol_is_exported(T):
     lib = ctypes.CDLL(T.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.tpmc_abi_version() == 5
+    assert lib.tpmc_abi_version() == 6
 
 
-def test_struct_sizes_match_header(T):
-    # tpmc_query: 4+1+2+1 doubles, 2 u64, 2 u32, 4 doubles, 1 double = 120 bytes
-    assert ctypes.sizeof(T.Query) == 8 * 8 + 16 + 8 + 32 + 8
-    # tpmc_result: 12 doubles, 6 u64, 3 doubles
-    assert ctypes.sizeof(T.Result) == 12 * 8 + 6 * 8 + 3 * 8
-    # tpmc_mesh_info: 2 u64, 2 u32, 10 doubles, u64, 2 u32 = 120 bytes
-    assert ctypes.sizeof(T.MeshInfo) == 16 + 8 + 80 + 8 + 8
+def _c_layout(struct: str, fields) -> list:
+    """sizeof and offsetof of a tpmc.h struct, as the C compiler lays it out."""
+    import subprocess
+    import tempfile
+    lines = [f'printf("%zu\\n", sizeof({struct}));'] + [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = "#include <stddef.h>\n#include <stdio.h>\n#include \"tpmc.h\"\nint main(void) {\n" + "\n".join(lines) + "\nreturn 0; }\n"
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(c, "w") as f:
+            f.write(src)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", exe, c])
+        return [int(v) for v in subprocess.check_output([exe]).split()]
+
+
+@pytest.mark.parametrize("name", ["Query", "Result", "MeshInfo", "Tuning"])
+def test_struct_layouts_match_header(T, name):
+    cls = getattr(T, name)
+    cname = {"Query": "tpmc_query", "Result": "tpmc_result", "MeshInfo": "tpmc_mesh_info", "Tuning": "tpmc_tuning"}[name]
+    fields = [f for f, _ in cls._fields_]
+    want = _c_layout(cname, fields)
+    got = [ctypes.sizeof(cls)] + [getattr(cls, f).offset for f in fields]
+    assert got == want, dict(zip(["sizeof"] + fields, zip(got, want)))
 
 
 def _status(fn):
@@ -141,3 +156,4 @@ def test_input_generators_sizes():
     q = I.quat_for_flow((0.3, -0.2, 0.9))
     u = I.flow_dir(q)
     assert np.allclose(u, np.array([0.3, -0.2, 0.9]) / math.sqrt(0.94), atol=1e-12)
+

@@ -92,6 +92,16 @@ def test_seed_parity(ctx, T, case):
 # ---------------------------------------------------------------------------
 
 
+def _check_flags_and_mhat(g, o, rel):
+    """No re-emission limited by the kernel's temperature bound and no segment
+    ended by the traversal's step bound; Mhat = M / (rho c_mp^2) against the
+    oracle's on the scale of |Mhat| + |Fhat| times the control-volume radius."""
+    assert g["tr_capped"] == 0 and g["guard_trips"] == 0, (g["tr_capped"], g["guard_trips"])
+    lever = o["consts"]["r"] + float(np.linalg.norm(o["consts"]["c0"]))
+    scale = np.abs(o["Mhat"]).max() + np.abs(o["Fhat"]).max() * lever
+    assert np.abs(np.asarray(g["Mhat"]) - o["Mhat"]).max() <= rel * scale + 1e-12, (g["Mhat"], o["Mhat"])
+
+
 def _compare(ctx, T, V, Tr, q, A_ref=1.0, x_ref=(0.0, 0.0, 0.0), cd_rel=1e-4, first_frac=0.9999, tri_tol=None):
     mesh = ctx.build_mesh(V, Tr)
     res, pr = T.run(mesh, [q], x_ref=x_ref, A_ref=A_ref, first_tri=True)
@@ -108,6 +118,7 @@ def _compare(ctx, T, V, Tr, q, A_ref=1.0, x_ref=(0.0, 0.0, 0.0), cd_rel=1e-4, fi
     assert abs(g["CD"] - o["CD"]) <= cd_rel * abs(o["CD"]) + 1e-12, (g["CD"], o["CD"])
     assert g["CD_sigma"] == pytest.approx(o["CD_sigma"], rel=1e-3)
     assert g["Gamma_hat"] == pytest.approx(o["Gamma_hat"], rel=1e-14)
+    _check_flags_and_mhat(g, o, cd_rel)
     if q["S"] > 0:  # heat transfer, on the scale of the incident energy (|C_D| / S)
         assert abs(g["CH"] - o["CH"]) <= cd_rel * (abs(o["CH"]) + abs(o["CD"]) / q["S"]) + 1e-12, (g["CH"], o["CH"])
         assert g["CH_sigma"] == pytest.approx(o["CH_sigma"], rel=2e-3, abs=1e-9)
@@ -197,6 +208,7 @@ def test_pratt_shell_parity(ctx, T, S):
     o = O.run(V, Tr, q, A_ref=math.pi, per_particle=True)
     assert np.mean(ft == o["first_tri"]) >= 0.9999
     assert g["rays"] == n and g["missed"] + g["escaped"] + g["capped"] == n
+    assert g["tr_capped"] == 0 and g["guard_trips"] == 0
     assert abs(g["CD"] - o["CD"]) <= 1e-3 * abs(o["CD"]), (g["CD"], o["CD"])
     assert g["hits"] > 1.5 * (g["rays"] - g["missed"])  # multiple reflections inside the cup
     assert abs(g["hits"] - o["hits"]) <= 0.002 * o["hits"] + 3
@@ -254,6 +266,10 @@ def test_moment_sweep_parity(ctx, T, pitch, yaw):
     scale = np.linalg.norm(Mo) + np.linalg.norm(Fo) * 1.0  # 1 m lever
     assert np.abs(np.asarray(g["M_over_q"]) - Mo).max() <= 1e-3 * scale, (g["M_over_q"], Mo)
     assert np.abs(np.asarray(g["F_over_q"]) - Fo).max() <= 1e-3 * np.linalg.norm(Fo)
+    # Mhat = M / (rho c_mp^2) is the same sum scaled by S^2 / 2
+    assert np.allclose(np.asarray(g["Mhat"]), 0.5 * 7.0 ** 2 * np.asarray(g["M_over_q"]), rtol=1e-12, atol=0)
+    assert np.abs(np.asarray(g["Mhat"]) - o["Mhat"]).max() <= 1e-3 * 0.5 * 7.0 ** 2 * scale
+    assert g["tr_capped"] == 0 and g["guard_trips"] == 0
     b = T.Batch(mesh, [q])
     b.launch(use_graph=False)
     r1 = b.results(x_ref=x_ref)[0]
