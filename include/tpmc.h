@@ -289,6 +289,25 @@ tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots, uint32_t n
 tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot);
 void tpmc_destroy_server(tpmc_server s);
 
+/* ---- Batched path without allocation ----
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The batched
+ * path (tpmc_batch_create + tpmc_batch_launch + tpmc_batch_results, same
+ * kernels, same results) in one call, with its workspace in a static device
+ * array of the library, TPMC_NOALLOC_MAX_BYTES bytes on each GPU it runs on,
+ * held until the process ends.  No device memory is allocated or freed.
+ * Queries whose batch workspace (tpmc_batch_workspace_bytes) is larger are
+ * rejected with TPMC_E_WORKSPACE before any work is enqueued.  Every call on a
+ * GPU uses that GPU's one array and leaves its contents behind (each call
+ * clears what it accumulates into before its launch), so calls that overlap on
+ * one GPU -- from two threads, or from two contexts on different streams --
+ * race: the caller serialises them.  Synchronises the context's stream.
+ * out: host [nq]; the other arguments as for tpmc_batch_create and
+ * tpmc_batch_results. */
+#define TPMC_NOALLOC_MAX_BYTES (32ull << 20)
+tpmc_status tpmc_batch_run_noalloc(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, uint32_t nq,
+                                   const double ref_point[3], double A_ref, tpmc_result* out);
+
 /* Host-only checks (no device needed): the validation the entry points above
  * apply.  tpmc_check_query also needs the mesh vertices for the CV test. */
 tpmc_status tpmc_check_mesh(const float* xyz, uint64_t nv, const uint32_t* tri, uint64_t nt);

@@ -20,6 +20,16 @@ using namespace tpmc;
 // default cap of the plain trace grid, workgroups per compute unit
 static constexpr uint32_t kPlainGroupsPerCu = 4;
 
+// Workspace of tpmc_batch_run_noalloc: a device array in the library's code
+// object, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is a stand-in, not a
+// device address): the address each device gives for it at context creation
+// (hipGetSymbolAddress) is kept in g_scratch_ptr and used instead.
+static constexpr uint64_t kScratchBytes = TPMC_NOALLOC_MAX_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;  // [device], null until that device's first context
+
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
@@ -421,6 +431,14 @@ extern "C" tpmc_status tpmc_create(int device, void* hip_stream, tpmc_ctx* out) 
     if (!ready[device]) {
       hipError_t e = init_seed_tables(static_cast<hipStream_t>(hip_stream));
       if (e != hipSuccess) return fail(TPMC_E_DEVICE, "seeding tables: %s", hipGetErrorString(e));
+      void* sp = nullptr;  // this device's copy of the no-allocation workspace
+      e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !sp) return fail(TPMC_E_DEVICE, "static workspace address: %s", hipGetErrorString(e));
+      {
+        std::lock_guard<std::mutex> lock2(g_scratch_mu);
+        if (g_scratch_ptr.size() < (size_t)count) g_scratch_ptr.resize(count, nullptr);
+        g_scratch_ptr[device] = sp;
+      }
       ready[device] = 1;
     }
   }
@@ -954,6 +972,37 @@ extern "C" void tpmc_destroy_batch(tpmc_batch b) {
     (void)hipGraphExecDestroy(b->exec);
   }
   delete b;
+}
+
+// The batched path (tpmc_batch_create + tpmc_batch_launch + tpmc_batch_results)
+// in one call, with its workspace in the library's static device array: no
+// device memory is allocated or freed.  The same kernels, so the same results.
+extern "C" tpmc_status tpmc_batch_run_noalloc(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, uint32_t nq,
+                                              const double ref_point[3], double A_ref, tpmc_result* out) {
+  if (!ctx || !m || !out) return fail(TPMC_E_INVALID, "ctx, mesh and out must not be NULL");
+  if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
+  if (!(A_ref > 0.0) || !std::isfinite(A_ref)) return fail(TPMC_E_INVALID, "A_ref = %g must be > 0", A_ref);
+  if (ref_point && !finite3(ref_point)) return fail(TPMC_E_INVALID, "reference point must be finite");
+  void* ws = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((size_t)ctx->device < g_scratch_ptr.size()) ws = g_scratch_ptr[ctx->device];
+  }
+  if (!ws) return fail(TPMC_E_DEVICE, "no static workspace address for device %d", ctx->device);
+  tpmc_batch_s b;
+  std::vector<QueryDev> hq;
+  std::vector<uint64_t> te;
+  Layout L;
+  tpmc_status s = batch_prepare(m, q, nq, ctx->tune.tile_particles, hq, te, L, nullptr);
+  if (s != TPMC_OK) return s;
+  if (L.bytes > kScratchBytes)
+    return fail(TPMC_E_WORKSPACE, "these queries need %llu bytes of workspace; the static workspace holds %llu",
+                (unsigned long long)L.bytes, (unsigned long long)kScratchBytes);
+  s = batch_init(ctx, m, q, nq, ws, kScratchBytes, &b);
+  if (s != TPMC_OK) return s;
+  batch_enqueue(&b, ctx->stream);  // zeroes the claim counters, scalars and tallies it uses
+  HIP_CHECK_LAUNCH("batch");
+  return finalize_results(ctx, b.lay, nq, ref_point, A_ref, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -98,6 +98,7 @@ _SIGS = {
     "tpmc_batch_launch": ([_vp, _vp, ctypes.c_int], ctypes.c_int),
     "tpmc_batch_results": ([_vp, _vp, _dp, ctypes.c_double, _RP], ctypes.c_int),
     "tpmc_destroy_batch": ([_vp], None),
+    "tpmc_batch_run_noalloc": ([_vp, _vp, _QP, _u32, _dp, ctypes.c_double, _RP], ctypes.c_int),
     "tpmc_server_workspace_bytes": ([_u32, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
     "tpmc_server_create": ([_vp, _u32, _u64, _vp, _u64, ctypes.POINTER(_vp)], ctypes.c_int),
     "tpmc_server_admit": ([_vp, _u32, _vp, _QP, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
@@ -414,6 +415,19 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+NOALLOC_MAX_BYTES = 32 << 20  # TPMC_NOALLOC_MAX_BYTES
+
+
+def batch_run_noalloc(mesh: Mesh, queries, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0):
+    """Batched path with the library's static device workspace (no device
+    allocation); see tpmc_batch_run_noalloc in include/tpmc.h."""
+    qarr = _queries(list(queries))
+    res = (Result * len(qarr))()
+    xr = (ctypes.c_double * 3)(*[float(v) for v in x_ref])
+    _check(_lib.tpmc_batch_run_noalloc(mesh.ctx._h, mesh._h, qarr, len(qarr), xr, float(A_ref), res))
+    return [result_dict(r) for r in res]
 
 
 class Server:

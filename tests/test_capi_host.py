@@ -157,3 +157,8 @@ def test_input_generators_sizes():
     u = I.flow_dir(q)
     assert np.allclose(u, np.array([0.3, -0.2, 0.9]) / math.sqrt(0.94), atol=1e-12)
 
+
+def test_noalloc_limit_matches_header(T):
+    text = open(os.path.join(ROOT, "include", "tpmc.h")).read()
+    m = re.search(r"#define TPMC_NOALLOC_MAX_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == T.NOALLOC_MAX_BYTES
