@@ -306,10 +306,14 @@ struct Hit {
   float dx, dy, dz, lx, ly, lz;
 };
 
-// Per-lane exact integer accumulators.
+// Per-lane exact integer accumulators.  Rays and segments are not kept: a
+// particle retires by missing, escaping or reaching the hit cap, and every
+// segment ends in a hit, an escape or a miss, so rays = missed + escaped +
+// capped and segments = hits + missed + escaped (an escape through a
+// supporting plane is one untraced segment after the hit).
 struct Acc {
   long long sD, sD2, sE, sE2, tot[7];
-  uint32_t rays, hits, segs, missed, escaped, capped;
+  uint32_t hits, missed, escaped, capped;
   uint32_t tr_capped;     // re-emissions whose temperature the kernel's bound limited
   uint32_t guard;         // segments ended by the traversal step bound
   uint32_t nodes, tests;  // traversal work (counting kernels only)
@@ -319,7 +323,7 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
   A.sD = A.sD2 = A.sE = A.sE2 = 0;
 #pragma unroll
   for (int c = 0; c < 7; ++c) A.tot[c] = 0;
-  A.rays = A.hits = A.segs = A.missed = A.escaped = A.capped = 0;
+  A.hits = A.missed = A.escaped = A.capped = 0;
   A.tr_capped = A.guard = 0;
   A.nodes = A.tests = 0;
 }
@@ -383,12 +387,10 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
 
 // Event counts of a lane whose segment ended with outcome `out`.
 __device__ __forceinline__ void count_outcome(Acc& A, int out, bool hit) {
-  A.segs += out == kOutHitLeft ? 2u : 1u;
   A.hits += hit ? 1u : 0u;
   A.missed += out == kOutMissed ? 1u : 0u;
   A.escaped += (out == kOutEscaped || out == kOutHitLeft) ? 1u : 0u;
   A.capped += out == kOutCapped ? 1u : 0u;
-  A.rays += out != kOutGoOn ? 1u : 0u;
 }
 
 __device__ __forceinline__ void retire(const QueryDev& q, const Lane& L, Acc& A) {
@@ -463,12 +465,12 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
   long long s[8 + 7 + 4];
   s[0] = wave_sum(A.sD);
   s[1] = wave_sum(A.sD2);
-  s[2] = wave_sum((long long)A.rays);
   s[3] = wave_sum((long long)A.hits);
-  s[4] = wave_sum((long long)A.segs);
   s[5] = wave_sum((long long)A.missed);
   s[6] = wave_sum((long long)A.escaped);
   s[7] = wave_sum((long long)A.capped);
+  s[2] = s[5] + s[6] + s[7];  // rays
+  s[4] = s[3] + s[5] + s[6];  // segments
   s[15] = wave_sum(A.sE);
   s[16] = wave_sum(A.sE2);
   s[17] = wave_sum((long long)A.tr_capped);
@@ -796,10 +798,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             __builtin_amdgcn_wave_barrier();
           }
         }
-        if (ballot(L.live) == 0ull) {
-          if (exhausted && q_count == 0) break;
-          continue;  // nothing in flight: claim more next round
-        }
+        // nothing in flight and nothing left: the tile is done (with no lane
+        // live but particles left, the next iteration claims more)
+        if (ballot(L.live) == 0ull && exhausted && q_count == 0) break;
         make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
         guard = 0;
       }
