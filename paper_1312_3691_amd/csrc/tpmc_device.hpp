@@ -582,6 +582,14 @@ __device__ __forceinline__ long long wave_sum(long long v) {
   return v;
 }
 
+// The wave's total in scalar registers (the same value in every lane).
+__device__ __forceinline__ long long wave_sum_uniform(long long v) {
+  const long long t = wave_sum(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)t);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)t >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ void atomic_add_i64(long long* p, long long v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }

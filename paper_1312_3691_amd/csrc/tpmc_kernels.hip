@@ -401,8 +401,8 @@ __device__ __forceinline__ void retire(const QueryDev& q, const Lane& L, Acc& A)
 }
 
 // Tally of one hit per lane.  Called by every lane of the wave (convergent).
-// Totals-only sums go to the lane's LDS slots when TOT_LDS (the persistent
-// kernel, short of registers), else to registers.
+// Totals-only sums go to the lane's LDS slots lds[c][lane] when TOT_LDS (the
+// persistent kernel, short of registers), else to registers.
 template <int MODE, bool TOT_LDS = true>
 __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long* __restrict__ g,
                                       unsigned long long* lds, uint32_t nt, Acc& A) {
@@ -411,7 +411,7 @@ __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long
   v[0] = fx32(h.dx, q.scaleF); v[1] = fx32(h.dy, q.scaleF); v[2] = fx32(h.dz, q.scaleF);
   v[3] = fx32(h.lx, q.scaleL); v[4] = fx32(h.ly, q.scaleL); v[5] = fx32(h.lz, q.scaleL);
   v[6] = 1;
-  if (MODE == kTallyTotals && TOT_LDS) {  // the lane's own LDS slots [c][lane]
+  if ((MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) && TOT_LDS) {  // the lane's LDS slots [c][lane]
     if (h.valid) {
 #pragma unroll
       for (int c = 0; c < 7; ++c) atomicAdd(lds + c * kBlock + threadIdx.x, (unsigned long long)v[c]);
@@ -452,46 +452,42 @@ __device__ __forceinline__ void flush_lane_tally(unsigned long long* lds, long l
 
 // Wave-reduce the per-lane accumulators into a query's scalar block.  With
 // TOTALS the query's force and moment totals come from the lane's registers,
-// or, when lane_tot is given, from (and clearing) its LDS slots [c][lane].
+// or, with TOT_LDS, from (and clearing) its LDS slots lane_tot[c][lane] (a
+// compile-time choice, so that the register totals are not kept live across
+// the trace loop of a kernel that never uses them).
+template <bool TOT_LDS = false>
 __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, bool TOTALS,
                                           unsigned long long* lane_tot = nullptr) {
-  if (TOTALS && lane_tot) {
+  if (TOT_LDS && TOTALS) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
       A.tot[c] = (long long)lane_tot[c * kBlock + threadIdx.x];
       lane_tot[c * kBlock + threadIdx.x] = 0ull;
     }
   }
-  long long s[8 + 7 + 4];
-  s[0] = wave_sum(A.sD);
-  s[1] = wave_sum(A.sD2);
-  s[3] = wave_sum((long long)A.hits);
-  s[5] = wave_sum((long long)A.missed);
-  s[6] = wave_sum((long long)A.escaped);
-  s[7] = wave_sum((long long)A.capped);
-  s[2] = s[5] + s[6] + s[7];  // rays
-  s[4] = s[3] + s[5] + s[6];  // segments
-  s[15] = wave_sum(A.sE);
-  s[16] = wave_sum(A.sE2);
-  s[17] = wave_sum((long long)A.tr_capped);
-  s[18] = wave_sum((long long)A.guard);
+  // one value at a time, each total moved to scalar registers, so that the
+  // flush adds little to the kernel's vector-register peak
+  const bool lead = (threadIdx.x & 63) == 0;
+  auto put = [&](long long total, int slot) {
+    if (lead && total) atomic_add_i64(scal + slot, total);
+  };
+  put(wave_sum_uniform(A.sD), kSD);
+  put(wave_sum_uniform(A.sD2), kSD2);
+  const long long hits = wave_sum_uniform((long long)A.hits), missed = wave_sum_uniform((long long)A.missed),
+                  escaped = wave_sum_uniform((long long)A.escaped), capped = wave_sum_uniform((long long)A.capped);
+  put(hits, kHits);
+  put(missed, kMissed);
+  put(escaped, kEscaped);
+  put(capped, kCapped);
+  put(missed + escaped + capped, kRays);
+  put(hits + missed + escaped, kSegments);
+  put(wave_sum_uniform(A.sE), kSE);
+  put(wave_sum_uniform(A.sE2), kSE2);
+  put(wave_sum_uniform((long long)A.tr_capped), kTrCap);
+  put(wave_sum_uniform((long long)A.guard), kGuard);
   if (TOTALS) {
 #pragma unroll
-    for (int c = 0; c < 7; ++c) s[8 + c] = wave_sum(A.tot[c]);
-  }
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (s[c]) atomic_add_i64(scal + c, s[c]);
-    if (s[15]) atomic_add_i64(scal + kSE, s[15]);
-    if (s[16]) atomic_add_i64(scal + kSE2, s[16]);
-    if (s[17]) atomic_add_i64(scal + kTrCap, s[17]);
-    if (s[18]) atomic_add_i64(scal + kGuard, s[18]);
-    if (TOTALS) {
-#pragma unroll
-      for (int c = 0; c < 7; ++c)
-        if (s[8 + c]) atomic_add_i64(scal + kFx + c, s[8 + c]);
-    }
+    for (int c = 0; c < 7; ++c) put(wave_sum_uniform(A.tot[c]), kFx + c);
   }
 }
 
@@ -624,6 +620,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   __shared__ float qbuf[kBlock / 64][6][64];
   __shared__ uint8_t qlane[kBlock / 64][64];  // queue slot -> particle offset in its seeding batch
   extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
+  // per-lane totals [c][lane]: the start of lt, or after the per-triangle area in the mixed mode
+  unsigned long long* const lane_tot = MODE == kTallyAuto ? lt + 7u * a.lds_tris : lt;
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -632,8 +630,10 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
   Acc A;
   acc_zero(A);
-  if (MODE == kTallyLane || MODE == kTallyTotals)
-    for (int c = 0; c < (MODE == kTallyLane ? 2 * 7 : 7); ++c) lt[c * kBlock + threadIdx.x] = 0ull;
+  if (MODE == kTallyLane)
+    for (int c = 0; c < 2 * 7; ++c) lt[c * kBlock + threadIdx.x] = 0ull;
+  if (MODE == kTallyTotals || MODE == kTallyAuto)
+    for (int c = 0; c < 7; ++c) lane_tot[c * kBlock + threadIdx.x] = 0ull;
   for (;;) {
     if (threadIdx.x == 0) {
       // claim a tile: current entry first, then the following ones (bounded scan)
@@ -661,8 +661,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       // leaving the held query: flush its partial sums
       const QueryDev& qh = a.qs[a.entry_query ? a.entry_query[held] : held];
       long long* htally = qh.per_tri ? a.tally_base + qh.tally_offset : nullptr;
-      flush_acc(A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri),
-                MODE == kTallyTotals ? lt : nullptr);
+      flush_acc<MODE == kTallyTotals || MODE == kTallyAuto>(
+          A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri), lane_tot);
       if (MODE == kTallyLane) flush_lane_tally(lt, htally, qh.nt);
       acc_zero(A);
       if (kMayLds && qh.per_tri && qh.nt <= (uint32_t)kLdsTallyMaxTris)
@@ -719,7 +719,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             count_outcome(A, out, h.valid);
           }
           if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
-          else tally<MODE>(q, h, qtally, lt, q.nt, A);
+          else tally<MODE>(q, h, qtally, lane_tot, q.nt, A);
           if (fin) {
             if (out != kOutGoOn) {
               retire(q, L, A);
@@ -912,11 +912,13 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
 
 // Dynamic LDS of the tallies: the workgroup tally of lds_tris triangles, the
 // per-lane slots of <= 2-triangle meshes, or per-lane totals (persistent
-// kernel only; the plain kernel keeps totals in registers).
+// kernel only; the plain kernel keeps totals in registers); the mixed mode
+// of serving steps holds both a workgroup tally and per-lane totals.
 size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent) {
   switch (mode) {
-    case kTallyLds:
-    case kTallyAuto: return (size_t)lds_tris * 7 * sizeof(unsigned long long);
+    case kTallyLds: return (size_t)lds_tris * 7 * sizeof(unsigned long long);
+    case kTallyAuto:  // per-triangle area, then (persistent) the per-lane totals
+      return ((size_t)lds_tris * 7 + (persistent ? (size_t)7 * kBlock : 0)) * sizeof(unsigned long long);
     case kTallyLane: return (size_t)2 * 7 * kBlock * sizeof(unsigned long long);
     case kTallyTotals: return persistent ? (size_t)7 * kBlock * sizeof(unsigned long long) : 0;
     default: return 0;

@@ -4,8 +4,8 @@ kernels to gfx950 assembly and reads the code-object metadata).
 The batched kernel is bound by VALU issue with four 64-lane waves per
 workgroup; at 128 VGPRs or fewer a SIMD holds four waves (512 per lane), one
 more than at 129-170, which hides the latency of the traversal loads and
-measured 13-15 % faster on the plate and cylinder launches.  Every
-per-triangle instance must therefore fit in 128 VGPRs without spilling."""
+measured 13-15 % faster on the plate and cylinder launches.  Every instance
+of the batched path must therefore fit in 128 VGPRs without spilling."""
 import os
 import re
 import shutil
@@ -39,8 +39,9 @@ def _metadata():
                     reason="hipcc not available")
 def test_batch_kernel_fits_four_waves_per_simd():
     meta = _metadata()
-    # batch_kernel<STACK, MODE>: MODE 0 global atomics, 1 workgroup LDS, 2 per-lane LDS tallies
-    inst = {k: v for k, v in meta.items() if re.search(r"batch_kernelILi\d+ELi[012]E", k)}
-    assert len(inst) == 15, sorted(inst)
+    # batch_kernel<STACK, MODE>: global atomics, workgroup LDS, per-lane LDS and totals-only
+    # tallies at every stack depth (the mixed mode of serving steps is not held to it)
+    inst = {k: v for k, v in meta.items() if re.search(r"batch_kernelILi\d+ELi[0-3]E", k)}
+    assert len(inst) == 20, sorted(inst)
     for k, v in inst.items():
         assert v["vgpr"] <= 128 and v["spill"] == 0, (k, v)
