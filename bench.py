@@ -894,7 +894,7 @@ def workload_served(args):
     res, sat = run(0)
     sat_rate = sat["req_per_s"]
     loads = {}
-    for frac in (0.5, 0.8, 0.95):
+    for frac in [float(f) for f in args.served_loads.split(",") if f.strip()]:
         log(f"served: load {frac}")
         _, st = run(frac * sat_rate)
         loads[str(frac)] = dict(st, offered_req_per_s=frac * sat_rate)
@@ -931,8 +931,11 @@ def workload_served(args):
                        f"1e5-1e7, S~U[2,10], alpha=0.9, per-triangle tallies", "slots": max_slots,
            "hbm_budget_gb": args.hbm_budget_gb, "path": "continuous batching, one persistent launch per step",
            "particles_per_step": int(args.particles_per_step), "tiles_per_step": tiles_per_step, "bvh": args.bvh},
-          {"saturation": sat, "loads": loads, "query_ms_p50": loads["0.8"]["p50_ms"],
-           "query_ms_p99": loads["0.8"]["p99_ms"], "fifo_plain_path": fifo, "served_equals_solo": bool(same),
+          {"saturation": sat, "loads": loads, "query_ms_p50": loads.get("0.8", {}).get("p50_ms"),
+           "query_ms_p99": loads.get("0.8", {}).get("p99_ms"), "fifo_plain_path": fifo,
+           "served_over_fifo": sat_rate / fifo["capacity_req_per_s"], "served_equals_solo": bool(same),
+           "meshes": {k: {"nt": m.nt, "depth": m.info["depth"], "stack_slots": m.info["stack_slots"]}
+                      for k, m in meshes.items()},
            "tuning": tuning})
 
 
@@ -967,9 +970,11 @@ def main():
     ap.add_argument("--particles-energy", type=float, default=1e7)
     ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
     ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
-    ap.add_argument("--slots", type=int, default=64, help="served: request slots")
+    ap.add_argument("--slots", type=int, default=128, help="served: request slots")
     ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="served: per-request tally budget")
     ap.add_argument("--fifo-requests", type=int, default=600, help="served: requests timed on the plain path")
+    ap.add_argument("--served-loads", default="0.5,0.8,0.95",
+                    help="served: offered loads as fractions of the saturation throughput (comma-separated)")
     ap.add_argument("--particles-per-step", type=float, default=2048 * 65536,
                     help="served: particles per continuous-batching step (split into tiles of the tuned size)")
     ap.add_argument("--bvh", default="sah", choices=["sah", "lbvh"], help="BVH builder (results do not depend on it)")

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 6
+#define TPMC_ABI_VERSION 7
 
 typedef enum {
   TPMC_OK = 0,
@@ -279,13 +279,33 @@ tpmc_status tpmc_server_create(tpmc_ctx ctx, uint32_t max_slots, uint64_t tally_
  * n_tiles receives the query's tile count. */
 tpmc_status tpmc_server_admit(tpmc_server s, uint32_t slot, tpmc_mesh mesh, const tpmc_query* q,
                               uint64_t tally_offset, uint64_t* n_tiles);
+/* Admit n requests at once (asynchronous): admission i puts q[i] on meshes[i]
+ * into slots[i] (distinct slots) with its tallies at tally_offset[i], as
+ * tpmc_server_admit does, with one upload and one launch for all of them.
+ * Every admission is validated first; on any error nothing is admitted and the
+ * message names the admission.  n_tiles (optional): host [n]. */
+tpmc_status tpmc_server_admit_many(tpmc_server s, uint32_t n, const uint32_t* slots, const tpmc_mesh* meshes,
+                                   const tpmc_query* q, const uint64_t* tally_offset, uint64_t* n_tiles);
 /* One step: entry i traces tiles [tile0[i], tile0[i] + count[i]) of slots[i]
- * (n <= max_slots entries, each slot at most once).  Asynchronous. */
+ * (n <= max_slots entries, each slot at most once).  Asynchronous; no call of
+ * the server waits for a step already on the stream (its uploads go through
+ * pinned host memory). */
 tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, const uint64_t* tile0, const uint64_t* count,
                              uint32_t n);
 /* Wait for the stream; results of the listed slots (out: host [n]). */
 tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
                                 double A_ref, tpmc_result* out);
+/* The same in two halves, so that a caller can enqueue its next step before it
+ * reads the results of the last one: collect enqueues the reduction of the
+ * listed slots and the copy of their results into host memory of the server
+ * (asynchronous; ticket receives its number), collected waits for collection
+ * `ticket` alone (not for later work on the stream) and copies its n results
+ * out (host [n]).  At most two collections are in flight: a third collect
+ * fails with TPMC_E_BUSY until the oldest is read.  A slot may be released and
+ * admitted again once its collection has been enqueued. */
+tpmc_status tpmc_server_collect(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
+                                double A_ref, uint32_t* ticket);
+tpmc_status tpmc_server_collected(tpmc_server s, uint32_t ticket, tpmc_result* out, uint32_t n);
 tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot);
 void tpmc_destroy_server(tpmc_server s);
 

@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 #include <mutex>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/tpmc.h"
@@ -70,6 +71,7 @@ struct tpmc_ctx_s {
 
 struct tpmc_mesh_s {
   tpmc_ctx ctx;
+  int device;  // the context's device, kept so that destruction never reads the context
   uint64_t nv, nt;
   uint32_t depth;
   uint32_t builder;  // tpmc_bvh_builder
@@ -108,6 +110,7 @@ struct tpmc_tally_s {
 
 struct tpmc_batch_s {
   tpmc_ctx ctx;
+  int device;  // as tpmc_mesh_s::device
   tpmc_mesh mesh;
   uint32_t nq;
   std::vector<QueryDev> hq;
@@ -488,6 +491,7 @@ extern "C" void tpmc_destroy_ctx(tpmc_ctx ctx) {
   if (ctx->capture_stream) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamDestroy(ctx->capture_stream);
+    (void)hipGetLastError();
   }
   delete ctx;
 }
@@ -509,6 +513,7 @@ extern "C" tpmc_status tpmc_build_mesh_ex(tpmc_ctx ctx, const float* xyz, uint64
   tpmc_mesh m = new (std::nothrow) tpmc_mesh_s;
   if (!m) return fail(TPMC_E_INVALID, "out of host memory");
   m->ctx = ctx;
+  m->device = ctx->device;
   m->nv = nv;
   m->nt = nt;
   m->host_xyz.assign(xyz, xyz + 3 * nv);
@@ -578,12 +583,16 @@ extern "C" tpmc_status tpmc_get_mesh_info(tpmc_mesh m, tpmc_mesh_info* out) {
   return TPMC_OK;
 }
 
+// Destruction may run after the context's (a garbage collector finalises in
+// any order), so it uses the handle's own device id, and it clears the error
+// state of the calls it makes so that no later check reports them.
 extern "C" void tpmc_destroy_mesh(tpmc_mesh m) {
   if (!m) return;
-  (void)hipSetDevice(m->ctx->device);
+  (void)hipSetDevice(m->device);
   if (m->nodes) (void)hipFree(m->nodes);
   if (m->tris) (void)hipFree(m->tris);
   if (m->orig) (void)hipFree(m->orig);
+  (void)hipGetLastError();
   delete m;
 }
 
@@ -857,6 +866,7 @@ static tpmc_status batch_init(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, ui
   if (s == TPMC_OK) s = check_ws(ws, ws_bytes, b->lay.bytes);
   if (s != TPMC_OK) return s;
   b->ctx = ctx;
+  b->device = ctx->device;
   b->mesh = m;
   b->nq = nq;
   b->total_tiles = 0;
@@ -922,6 +932,7 @@ static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   a.refill = b->refill;
   a.tile = b->tile;
   a.lds_tris = b->mode == kTallyLds ? (uint32_t)m->nt : 0u;
+  a.lane_totals = b->mode == kTallyTotals ? 1u : 0u;
   launch_batch(a, m->stack_slots, b->mode, b->grid, st);
   if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, (uint32_t)m->nt, st);
 }
@@ -968,8 +979,9 @@ extern "C" tpmc_status tpmc_batch_results(tpmc_ctx ctx, tpmc_batch b, const doub
 extern "C" void tpmc_destroy_batch(tpmc_batch b) {
   if (!b) return;
   if (b->exec) {
-    (void)hipSetDevice(b->ctx->device);
+    (void)hipSetDevice(b->device);
     (void)hipGraphExecDestroy(b->exec);
+    (void)hipGetLastError();
   }
   delete b;
 }
@@ -1008,25 +1020,41 @@ extern "C" tpmc_status tpmc_batch_run_noalloc(tpmc_ctx ctx, tpmc_mesh m, const t
 // ---------------------------------------------------------------------------
 // serving: a slot table plus one persistent launch per continuous-batching step
 // ---------------------------------------------------------------------------
+// Every host-to-device upload of the server goes through a ring of pinned
+// host chunks, each guarded by an event recorded after its copy, so that no
+// call waits for the kernels already on the stream (a copy from pageable
+// memory may), and a chunk is rewritten only once its copy has run.
+constexpr int kUploadRing = 8;
+
 struct tpmc_server_s {
   tpmc_ctx ctx;
+  int device;  // as tpmc_mesh_s::device
   uint32_t max_slots;
   uint64_t tally_words;
   uint32_t tile;         // particles per tile, fixed at creation
   QueryDev* qs;          // [max_slots]
-  ResultDev* res;        // [max_slots]
+  ResultDev* res;        // [2][max_slots]: the two collections that may be in flight
   long long* scal;       // [max_slots][kScalarSlots]
   long long* tally;      // pool of tally_words
-  uint32_t* e_query;     // step entries
-  uint64_t* e_tile0;
-  uint64_t* e_tiles;
-  uint32_t* r_idx;       // slots whose results are read
+  uint8_t* entries;      // step entries: tile0 [n] u64, tiles [n] u64, slot [n] u32 (packed for n)
+  uint8_t* admits;       // admission staging: [max_slots] AdmitRec
+  uint32_t* r_idx;       // [2][max_slots] slots whose results are collected
   unsigned long long* e_next;
   std::vector<QueryDev> hq;
   std::vector<tpmc_mesh> mesh_of;
   std::vector<uint8_t> used;
-  std::vector<uint32_t> h_query, h_idx;  // staging, alive until the copies complete
-  std::vector<uint64_t> h_tile0, h_tiles;
+  // pinned upload ring
+  uint8_t* ring_host = nullptr;
+  uint64_t chunk = 0;
+  hipEvent_t ring_ev[kUploadRing] = {};
+  bool ring_used[kUploadRing] = {};
+  uint32_t ring_next = 0;
+  // collections: pinned result buffers and events, two in flight at most
+  ResultDev* res_host = nullptr;  // [2][max_slots]
+  hipEvent_t coll_ev[2] = {};
+  uint32_t coll_n[2] = {0, 0};
+  uint32_t coll_seq = 0;          // collections issued
+  bool coll_pending[2] = {false, false};
 };
 
 static void server_layout(uint32_t max_slots, uint64_t tally_words, uint8_t* base, tpmc_server_s* s,
@@ -1037,21 +1065,45 @@ static void server_layout(uint32_t max_slots, uint64_t tally_words, uint8_t* bas
     off = align256(off + b);
     return o;
   };
-  const uint64_t oq = take(max_slots * sizeof(QueryDev)), orr = take(max_slots * sizeof(ResultDev)),
+  const uint64_t oq = take(max_slots * sizeof(QueryDev)), orr = take(2ull * max_slots * sizeof(ResultDev)),
                  os = take((uint64_t)max_slots * kScalarSlots * 8), ot = take(tally_words * 8),
-                 oeq = take(max_slots * 4ull), oe0 = take(max_slots * 8ull), oee = take(max_slots * 8ull),
-                 ori = take(max_slots * 4ull), oc = take(max_slots * 8ull);
+                 oe = take(max_slots * 20ull), oa = take(max_slots * sizeof(AdmitRec)),
+                 ori = take(2ull * max_slots * 4), oc = take(max_slots * 8ull);
   *bytes = off;
   if (!s) return;
   s->qs = reinterpret_cast<QueryDev*>(base + oq);
   s->res = reinterpret_cast<ResultDev*>(base + orr);
   s->scal = reinterpret_cast<long long*>(base + os);
   s->tally = reinterpret_cast<long long*>(base + ot);
-  s->e_query = reinterpret_cast<uint32_t*>(base + oeq);
-  s->e_tile0 = reinterpret_cast<uint64_t*>(base + oe0);
-  s->e_tiles = reinterpret_cast<uint64_t*>(base + oee);
+  s->entries = base + oe;
+  s->admits = base + oa;
   s->r_idx = reinterpret_cast<uint32_t*>(base + ori);
   s->e_next = reinterpret_cast<unsigned long long*>(base + oc);
+}
+
+static void server_free_host(tpmc_server s) {
+  for (int i = 0; i < kUploadRing; ++i)
+    if (s->ring_ev[i]) (void)hipEventDestroy(s->ring_ev[i]);
+  for (int i = 0; i < 2; ++i)
+    if (s->coll_ev[i]) (void)hipEventDestroy(s->coll_ev[i]);
+  if (s->ring_host) (void)hipHostFree(s->ring_host);
+  if (s->res_host) (void)hipHostFree(s->res_host);
+}
+
+// Copy bytes from host src to device dst on the server's stream through the next ring chunk.
+static tpmc_status server_upload(tpmc_server s, void* dst, const void* src, uint64_t bytes) {
+  if (bytes > s->chunk) return fail(TPMC_E_INVALID, "upload of %llu bytes exceeds the %llu-byte chunk",
+                                    (unsigned long long)bytes, (unsigned long long)s->chunk);
+  const uint32_t k = s->ring_next;
+  s->ring_next = (k + 1) % kUploadRing;
+  if (s->ring_used[k]) HIP_TRY(hipEventSynchronize(s->ring_ev[k]));
+  uint8_t* h = s->ring_host + (uint64_t)k * s->chunk;
+  std::memcpy(h, src, bytes);
+  hipStream_t st = s->ctx->stream;
+  HIP_TRY(hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(s->ring_ev[k], st));
+  s->ring_used[k] = true;
+  return TPMC_OK;
 }
 
 extern "C" tpmc_status tpmc_server_workspace_bytes(uint32_t max_slots, uint64_t tally_words, uint64_t* bytes) {
@@ -1071,6 +1123,7 @@ extern "C" tpmc_status tpmc_server_create(tpmc_ctx ctx, uint32_t max_slots, uint
   tpmc_server s = new (std::nothrow) tpmc_server_s;
   if (!s) return fail(TPMC_E_INVALID, "out of host memory");
   s->ctx = ctx;
+  s->device = ctx->device;
   s->max_slots = max_slots;
   s->tally_words = tally_words;
   s->tile = ctx->tune.tile_particles;
@@ -1078,36 +1131,74 @@ extern "C" tpmc_status tpmc_server_create(tpmc_ctx ctx, uint32_t max_slots, uint
   s->hq.assign(max_slots, QueryDev{});
   s->mesh_of.assign(max_slots, nullptr);
   s->used.assign(max_slots, 0);
+  s->chunk = align256(std::max<uint64_t>(max_slots * sizeof(AdmitRec), max_slots * 20ull));
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->ring_host), s->chunk * kUploadRing);
+  if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->res_host), 2ull * max_slots * sizeof(ResultDev));
+  for (int i = 0; e == hipSuccess && i < kUploadRing; ++i) e = hipEventCreateWithFlags(&s->ring_ev[i], hipEventDisableTiming);
+  for (int i = 0; e == hipSuccess && i < 2; ++i) e = hipEventCreateWithFlags(&s->coll_ev[i], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    server_free_host(s);
+    delete s;
+    return fail(TPMC_E_DEVICE, "server host buffers: %s", hipGetErrorString(e));
+  }
   *out = s;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_admit_many(tpmc_server s, uint32_t n, const uint32_t* slots, const tpmc_mesh* meshes,
+                                              const tpmc_query* q, const uint64_t* tally_offset, uint64_t* n_tiles) {
+  if (!s || (n && (!slots || !meshes || !q || !tally_offset)))
+    return fail(TPMC_E_INVALID, "server, slots, meshes, queries and offsets must not be NULL");
+  if (n == 0) return TPMC_OK;
+  if (n > s->max_slots) return fail(TPMC_E_INVALID, "%u admissions > max_slots %u", n, s->max_slots);
+  // validate everything before changing any state
+  std::vector<AdmitRec> rec(n);
+  std::vector<uint8_t> seen(s->max_slots, 0);
+  for (uint32_t i = 0; i < n; ++i) {
+    const uint32_t slot = slots[i];
+    const tpmc_mesh m = meshes[i];
+    if (!m) return fail(TPMC_E_INVALID, "admission %u: mesh is NULL", i);
+    if (slot >= s->max_slots) return fail(TPMC_E_INVALID, "admission %u: slot %u >= max_slots %u", i, slot, s->max_slots);
+    if (seen[slot]) return fail(TPMC_E_INVALID, "admission %u: slot %u listed twice", i, slot);
+    seen[slot] = 1;
+    if (m->ctx != s->ctx) return fail(TPMC_E_BUSY, "admission %u: mesh belongs to another context", i);
+    std::vector<QueryDev> one;
+    tpmc_status st = make_queries(m, q + i, 1, one);
+    if (st != TPMC_OK) return fail(st, "admission %u: %s", i, g_err.c_str());
+    QueryDev& d = one[0];
+    d.scalar_offset = (uint64_t)slot * kScalarSlots;
+    d.tally_offset = tally_offset[i];
+    if (d.per_tri && (tally_offset[i] > s->tally_words || m->nt * 7 > s->tally_words - tally_offset[i]))
+      return fail(TPMC_E_WORKSPACE, "admission %u: per-triangle tallies of %llu words at offset %llu exceed the pool "
+                  "of %llu", i, (unsigned long long)(m->nt * 7), (unsigned long long)tally_offset[i],
+                  (unsigned long long)s->tally_words);
+    rec[i].q = d;
+    rec[i].slot = slot;
+    rec[i].pad = 0;
+    rec[i].tally_off = tally_offset[i];
+    rec[i].tally_words = d.per_tri ? m->nt * 7 : 0;
+  }
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  uint64_t max_words = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    s->hq[slots[i]] = rec[i].q;
+    s->mesh_of[slots[i]] = meshes[i];
+    s->used[slots[i]] = 1;
+    if (rec[i].tally_words > max_words) max_words = rec[i].tally_words;
+    if (n_tiles) n_tiles[i] = (rec[i].q.N + s->tile - 1) / s->tile;
+  }
+  tpmc_status st = server_upload(s, s->admits, rec.data(), n * sizeof(AdmitRec));
+  if (st != TPMC_OK) return st;
+  launch_admit(reinterpret_cast<const AdmitRec*>(s->admits), n, max_words, s->qs, s->scal, s->tally, s->ctx->stream);
+  HIP_CHECK_LAUNCH("admit");
   return TPMC_OK;
 }
 
 extern "C" tpmc_status tpmc_server_admit(tpmc_server s, uint32_t slot, tpmc_mesh m, const tpmc_query* q,
                                          uint64_t tally_offset, uint64_t* n_tiles) {
   if (!s || !m || !q) return fail(TPMC_E_INVALID, "server, mesh and query must not be NULL");
-  if (slot >= s->max_slots) return fail(TPMC_E_INVALID, "slot %u >= max_slots %u", slot, s->max_slots);
-  if (m->ctx != s->ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
-  std::vector<QueryDev> one;
-  tpmc_status st = make_queries(m, q, 1, one);
-  if (st != TPMC_OK) return st;
-  QueryDev& d = one[0];
-  d.scalar_offset = (uint64_t)slot * kScalarSlots;
-  d.tally_offset = tally_offset;
-  if (d.per_tri && (tally_offset > s->tally_words || m->nt * 7 > s->tally_words - tally_offset))
-    return fail(TPMC_E_WORKSPACE, "per-triangle tallies of %llu words at offset %llu exceed the pool of %llu",
-                (unsigned long long)(m->nt * 7), (unsigned long long)tally_offset,
-                (unsigned long long)s->tally_words);
-  HIP_TRY(hipSetDevice(s->ctx->device));
-  s->hq[slot] = d;
-  s->mesh_of[slot] = m;
-  s->used[slot] = 1;
-  hipStream_t stv = s->ctx->stream;
-  HIP_TRY(hipMemcpyAsync(s->qs + slot, &s->hq[slot], sizeof(QueryDev), hipMemcpyHostToDevice, stv));
-  zero_i64(s->scal + d.scalar_offset, kScalarSlots, stv);
-  if (d.per_tri) zero_i64(s->tally + tally_offset, m->nt * 7, stv);
-  HIP_CHECK_LAUNCH("admit");
-  if (n_tiles) *n_tiles = (d.N + s->tile - 1) / s->tile;
-  return TPMC_OK;
+  return tpmc_server_admit_many(s, 1, &slot, &m, q, &tally_offset, n_tiles);
 }
 
 extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, const uint64_t* tile0,
@@ -1115,15 +1206,15 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   if (!s || (n && (!slots || !tile0 || !count))) return fail(TPMC_E_INVALID, "server and step arrays required");
   if (n == 0) return TPMC_OK;
   if (n > s->max_slots) return fail(TPMC_E_INVALID, "%u entries > max_slots %u", n, s->max_slots);
-  s->h_query.assign(slots, slots + n);
-  s->h_tile0.assign(tile0, tile0 + n);
-  s->h_tiles.assign(count, count + n);
   uint64_t acc = 0;
   int stack = 4;
   uint32_t lds_tris = 0;  // largest per-triangle tally kept in LDS by the auto mode
+  bool any_totals = false, any_tri = false;
   for (uint32_t i = 0; i < n; ++i) {
     const uint32_t sl = slots[i];
     if (sl >= s->max_slots || !s->used[sl]) return fail(TPMC_E_INVALID, "entry %u names an empty slot %u", i, sl);
+    for (uint32_t j = 0; j < i; ++j)
+      if (slots[j] == sl) return fail(TPMC_E_INVALID, "entry %u repeats slot %u", i, sl);
     const uint64_t tiles = (s->hq[sl].N + s->tile - 1) / s->tile;
     if (tile0[i] > tiles || count[i] > tiles - tile0[i])
       return fail(TPMC_E_INVALID, "entry %u: tiles [%llu, +%llu) beyond the slot's %llu", i,
@@ -1132,37 +1223,50 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
     if (s->mesh_of[sl]->stack_slots > stack) stack = s->mesh_of[sl]->stack_slots;
     const QueryDev& hq = s->hq[sl];
     if (hq.per_tri && hq.nt <= (uint32_t)kLdsTallyMaxTris && hq.nt > lds_tris) lds_tris = hq.nt;
+    if (!hq.per_tri) any_totals = true;
+    else any_tri = true;
   }
   if (acc == 0) return TPMC_OK;
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t st = s->ctx->stream;
-  HIP_TRY(hipMemcpyAsync(s->e_query, s->h_query.data(), n * 4ull, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s->e_tile0, s->h_tile0.data(), n * 8ull, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipMemcpyAsync(s->e_tiles, s->h_tiles.data(), n * 8ull, hipMemcpyHostToDevice, st));
+  // one packed upload: tile0 [n] u64, tiles [n] u64, slot [n] u32
+  std::vector<uint8_t> pk(20ull * n);
+  std::memcpy(pk.data(), tile0, 8ull * n);
+  std::memcpy(pk.data() + 8ull * n, count, 8ull * n);
+  std::memcpy(pk.data() + 16ull * n, slots, 4ull * n);
+  tpmc_status ust = server_upload(s, s->entries, pk.data(), pk.size());
+  if (ust != TPMC_OK) return ust;
   zero_i64(reinterpret_cast<long long*>(s->e_next), n, st);
   BatchArgs a;
   a.qs = s->qs;
-  a.entry_query = s->e_query;
-  a.entry_tile0 = s->e_tile0;
-  a.entry_tiles = s->e_tiles;
+  a.entry_tile0 = reinterpret_cast<const uint64_t*>(s->entries);
+  a.entry_tiles = reinterpret_cast<const uint64_t*>(s->entries + 8ull * n);
+  a.entry_query = reinterpret_cast<const uint32_t*>(s->entries + 16ull * n);
   a.entry_next = s->e_next;
   a.tally_base = s->tally;
   a.scal_base = s->scal;
   a.n_entries = n;
   a.refill = s->ctx->tune.refill_lanes;
   a.tile = s->tile;
-  a.lds_tris = lds_tris;
-  launch_batch(a, stack, kTallyAuto, s->ctx->n_cu * (int)s->ctx->tune.groups_per_cu, st);
+  // The single-kind instances use fewer registers than the mixed one (four
+  // waves per SIMD instead of three); every kind gives the same exact sums.
+  const TallyMode mode = !any_tri ? kTallyTotals : (!any_totals && lds_tris == 0 ? kTallyGlobal : kTallyAuto);
+  a.lds_tris = mode == kTallyAuto ? lds_tris : 0u;
+  a.lane_totals = any_totals ? 1u : 0u;
+  launch_batch(a, stack, mode, s->ctx->n_cu * (int)s->ctx->tune.groups_per_cu, st);
   HIP_CHECK_LAUNCH("server step");
   return TPMC_OK;
 }
 
-extern "C" tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
-                                           double A_ref, tpmc_result* out) {
-  if (!s || !slots || !out || n == 0) return fail(TPMC_E_INVALID, "server, slots and out required");
+extern "C" tpmc_status tpmc_server_collect(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
+                                           double A_ref, uint32_t* ticket) {
+  if (!s || !slots || !ticket || n == 0) return fail(TPMC_E_INVALID, "server, slots, ticket and n >= 1 required");
   if (n > s->max_slots) return fail(TPMC_E_INVALID, "%u slots > max_slots %u", n, s->max_slots);
   if (!(A_ref > 0.0) || !std::isfinite(A_ref)) return fail(TPMC_E_INVALID, "A_ref = %g must be > 0", A_ref);
   if (ref_point && !finite3(ref_point)) return fail(TPMC_E_INVALID, "reference point must be finite");
+  const uint32_t b = s->coll_seq % 2;
+  if (s->coll_pending[b])
+    return fail(TPMC_E_BUSY, "two collections are already in flight; read collection %u first", s->coll_seq - 2);
   uint32_t max_nt = 1;
   for (uint32_t i = 0; i < n; ++i) {
     if (slots[i] >= s->max_slots || !s->used[slots[i]]) return fail(TPMC_E_INVALID, "slot %u is empty", slots[i]);
@@ -1170,18 +1274,45 @@ extern "C" tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots,
   }
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t st = s->ctx->stream;
-  s->h_idx.assign(slots, slots + n);
-  HIP_TRY(hipMemcpyAsync(s->r_idx, s->h_idx.data(), n * 4ull, hipMemcpyHostToDevice, st));
-  launch_reduce_slots(s->qs, s->r_idx, n, s->tally, s->scal, max_nt, st);
+  uint32_t* idx = s->r_idx + (uint64_t)b * s->max_slots;
+  ResultDev* res = s->res + (uint64_t)b * s->max_slots;
+  tpmc_status ust = server_upload(s, idx, slots, 4ull * n);
+  if (ust != TPMC_OK) return ust;
+  launch_reduce_slots(s->qs, idx, n, s->tally, s->scal, max_nt, st);
   const double xr = ref_point ? ref_point[0] : 0.0, yr = ref_point ? ref_point[1] : 0.0,
                zr = ref_point ? ref_point[2] : 0.0;
-  launch_finalize(s->qs, s->r_idx, s->scal, n, xr, yr, zr, A_ref, s->res, st);
-  HIP_CHECK_LAUNCH("server results");
-  std::vector<ResultDev> hr(n);
-  HIP_TRY(hipMemcpyAsync(hr.data(), s->res, n * sizeof(ResultDev), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  for (uint32_t i = 0; i < n; ++i) copy_result(hr[i], out + i);
+  launch_finalize(s->qs, idx, s->scal, n, xr, yr, zr, A_ref, res, st);
+  HIP_CHECK_LAUNCH("server collect");
+  HIP_TRY(hipMemcpyAsync(s->res_host + (uint64_t)b * s->max_slots, res, n * sizeof(ResultDev), hipMemcpyDeviceToHost,
+                         st));
+  HIP_TRY(hipEventRecord(s->coll_ev[b], st));
+  s->coll_n[b] = n;
+  s->coll_pending[b] = true;
+  *ticket = s->coll_seq++;
   return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_collected(tpmc_server s, uint32_t ticket, tpmc_result* out, uint32_t n) {
+  if (!s || !out) return fail(TPMC_E_INVALID, "server and out must not be NULL");
+  const uint32_t b = ticket % 2;
+  if (ticket >= s->coll_seq || s->coll_seq - ticket > 2 || !s->coll_pending[b])
+    return fail(TPMC_E_INVALID, "collection %u is not in flight", ticket);
+  if (n != s->coll_n[b]) return fail(TPMC_E_INVALID, "collection %u holds %u results, not %u", ticket, s->coll_n[b], n);
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  HIP_TRY(hipEventSynchronize(s->coll_ev[b]));
+  const ResultDev* h = s->res_host + (uint64_t)b * s->max_slots;
+  for (uint32_t i = 0; i < n; ++i) copy_result(h[i], out + i);
+  s->coll_pending[b] = false;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_server_results(tpmc_server s, const uint32_t* slots, uint32_t n, const double ref_point[3],
+                                           double A_ref, tpmc_result* out) {
+  if (!s || !slots || !out || n == 0) return fail(TPMC_E_INVALID, "server, slots and out required");
+  uint32_t ticket = 0;
+  tpmc_status st = tpmc_server_collect(s, slots, n, ref_point, A_ref, &ticket);
+  if (st != TPMC_OK) return st;
+  return tpmc_server_collected(s, ticket, out, n);
 }
 
 extern "C" tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot) {
@@ -1191,7 +1322,14 @@ extern "C" tpmc_status tpmc_server_release(tpmc_server s, uint32_t slot) {
   return TPMC_OK;
 }
 
-extern "C" void tpmc_destroy_server(tpmc_server s) { delete s; }
+extern "C" void tpmc_destroy_server(tpmc_server s) {
+  if (!s) return;
+  (void)hipSetDevice(s->device);
+  (void)hipDeviceSynchronize();  // pending uploads and collections read the pinned host buffers
+  server_free_host(s);
+  (void)hipGetLastError();
+  delete s;
+}
 
 // ---------------------------------------------------------------------------
 // measured ceilings (tpmc_ceilings.hip)

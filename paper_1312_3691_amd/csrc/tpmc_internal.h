@@ -73,6 +73,14 @@ struct ResultDev {
   uint64_t tr_capped, guard_trips;
 };
 
+// One slot admitted by a serving step's admission kernel: its constants and
+// the per-triangle tally words it clears (none for totals-only requests).
+struct alignas(16) AdmitRec {
+  QueryDev q;
+  uint32_t slot, pad;
+  uint64_t tally_off, tally_words;
+};
+
 // BVH node: the boxes of both children and the two child links (64 bytes).
 // A link >= 0 is an internal node; a link < 0 is the leaf ~link, a position in
 // the Morton-sorted triangle array.

@@ -632,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   acc_zero(A);
   if (MODE == kTallyLane)
     for (int c = 0; c < 2 * 7; ++c) lt[c * kBlock + threadIdx.x] = 0ull;
-  if (MODE == kTallyTotals || MODE == kTallyAuto)
+  if (MODE == kTallyTotals || (MODE == kTallyAuto && a.lane_totals))
     for (int c = 0; c < 7; ++c) lane_tot[c * kBlock + threadIdx.x] = 0ull;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -914,11 +914,11 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
 // per-lane slots of <= 2-triangle meshes, or per-lane totals (persistent
 // kernel only; the plain kernel keeps totals in registers); the mixed mode
 // of serving steps holds both a workgroup tally and per-lane totals.
-size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent) {
+size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent, bool lane_totals = false) {
   switch (mode) {
     case kTallyLds: return (size_t)lds_tris * 7 * sizeof(unsigned long long);
-    case kTallyAuto:  // per-triangle area, then (persistent) the per-lane totals
-      return ((size_t)lds_tris * 7 + (persistent ? (size_t)7 * kBlock : 0)) * sizeof(unsigned long long);
+    case kTallyAuto:  // per-triangle area, then (persistent, if any entry keeps totals only) the per-lane totals
+      return ((size_t)lds_tris * 7 + (persistent && lane_totals ? (size_t)7 * kBlock : 0)) * sizeof(unsigned long long);
     case kTallyLane: return (size_t)2 * 7 * kBlock * sizeof(unsigned long long);
     case kTallyTotals: return persistent ? (size_t)7 * kBlock * sizeof(unsigned long long) : 0;
     default: return 0;
@@ -944,7 +944,7 @@ void launch_trace_stack(const TraceArgs& a, TallyMode mode, int grid, hipStream_
 
 template <int STACK>
 void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t st) {
-  const size_t lds = tally_lds_bytes(mode, a.lds_tris, true);
+  const size_t lds = tally_lds_bytes(mode, a.lds_tris, true, a.lane_totals != 0u);
   switch (mode) {
     case kTallyLane: batch_kernel<STACK, kTallyLane><<<grid, kBlock, lds, st>>>(a); break;
     case kTallyLds: batch_kernel<STACK, kTallyLds><<<grid, kBlock, lds, st>>>(a); break;
@@ -954,7 +954,31 @@ void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t
   }
 }
 
+static_assert(sizeof(QueryDev) % 8 == 0 && kScalarSlots <= kBlock, "admission copies 8-byte words");
+
+// Serving admission, entry blockIdx.y: the slot's constants and cleared
+// scalar block (first workgroup), its per-triangle tally words (all).
+__global__ __launch_bounds__(kBlock) void admit_kernel(const AdmitRec* __restrict__ rec, QueryDev* __restrict__ qs,
+                                                       long long* __restrict__ scal, long long* __restrict__ tally) {
+  const AdmitRec& r = rec[blockIdx.y];
+  if (blockIdx.x == 0) {
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&r.q);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(qs + r.slot);
+    for (uint32_t w = threadIdx.x; w < sizeof(QueryDev) / 8; w += kBlock) dst[w] = src[w];
+    if (threadIdx.x < (uint32_t)kScalarSlots) scal[(uint64_t)r.slot * kScalarSlots + threadIdx.x] = 0;
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < r.tally_words; i += (uint64_t)gridDim.x * kBlock)
+    tally[r.tally_off + i] = 0;
+}
+
 }  // namespace
+
+void launch_admit(const AdmitRec* rec, uint32_t n, uint64_t max_words, QueryDev* qs, long long* scal,
+                  long long* tally, hipStream_t st) {
+  const uint64_t gx = (max_words + kBlock - 1) / kBlock;
+  const dim3 g((uint32_t)(gx < 1 ? 1 : (gx > 1024 ? 1024 : gx)), n);
+  admit_kernel<<<g, kBlock, 0, st>>>(rec, qs, scal, tally);
+}
 
 hipError_t init_seed_tables(hipStream_t st) {
   float* tab = nullptr;

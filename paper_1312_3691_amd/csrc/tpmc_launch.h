@@ -48,6 +48,7 @@ struct BatchArgs {
   uint32_t refill;                 // as TraceArgs::refill
   uint64_t tile;                   // particles per tile (multiple of 64)
   uint32_t lds_tris;               // largest nt of an entry with an LDS tally (kTallyLds / kTallyAuto)
+  uint32_t lane_totals;            // kTallyAuto: some entry keeps totals only (per-lane LDS totals allocated)
 };
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
@@ -78,6 +79,10 @@ void launch_finalize(const QueryDev* d_qs, const uint32_t* d_idx, const long lon
 void launch_reduce_slots(const QueryDev* d_qs, const uint32_t* d_idx, uint32_t n, long long* tally_base,
                          long long* scal_base, uint32_t max_nt, hipStream_t st);
 void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
+// Serving admission: n records (device) -> constants into qs[slot], cleared
+// scalar block and per-triangle tally words; max_words is the largest tally.
+void launch_admit(const AdmitRec* rec, uint32_t n, uint64_t max_words, QueryDev* qs, long long* scal,
+                  long long* tally, hipStream_t st);
 
 // Ceiling microkernels (tpmc_ceilings.hip).  kind 0: FP32 FMA, 1: FP64 FMA,
 // 2: int32 multiply and add; each lane performs ceiling_valu_ops_per_lane(iters)

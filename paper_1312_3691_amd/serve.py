@@ -10,6 +10,12 @@ been traced, its result is read and its slot and pool words are freed for the
 next arrivals.  Integer tallies make each result independent of how its tiles
 were spread over steps and of the requests it shared them with.
 
+The loop is pipelined so that the device does not wait for the host: after
+step k is enqueued, the results of the requests it completes are enqueued for
+collection, and only then are the results of step k - 1 read (they were ready
+when step k started), their slots freed and new requests admitted (all
+admissions of a step in one call) -- all while step k runs.
+
 The policy lives here; the device work is behind an executor so the policy can
 be tested on the CPU (``tests/test_serve_cpu.py``) with a fake executor.
 """
@@ -87,19 +93,43 @@ class Stats:
 
 
 class Executor:
-    """Device side of the loop (see GpuExecutor)."""
+    """Device side of the loop (see GpuExecutor).  admit_many, collect and
+    collected default to admit and results, one call each."""
 
     def tally_words(self, mesh: str, query: dict) -> int:
         raise NotImplementedError
 
+    def validate(self, mesh: str, query: dict) -> None:
+        """Raise for a request that admission would refuse (default: none)."""
+
     def admit(self, slot: int, mesh: str, query: dict, offset: int) -> int:
         raise NotImplementedError
+
+    def admit_many(self, items) -> list:
+        """items: (slot, mesh, query, offset) each; returns the tile counts.
+        All or nothing: on an error the ones admitted before it are released."""
+        tiles = []
+        try:
+            for it in items:
+                tiles.append(self.admit(*it))
+        except Exception:
+            for it in items[:len(tiles)]:
+                self.release(it[0])
+            raise
+        return tiles
 
     def step(self, entries) -> None:
         raise NotImplementedError
 
     def results(self, slots) -> list:
         raise NotImplementedError
+
+    def collect(self, slots):
+        """Enqueue the results of these slots; returns a ticket for collected."""
+        return self.results(slots)
+
+    def collected(self, ticket) -> list:
+        return ticket
 
     def release(self, slot: int) -> None:
         raise NotImplementedError
@@ -117,14 +147,27 @@ class GpuExecutor(Executor):
     def tally_words(self, mesh, query):
         return 0 if int(query.get("flags", 0)) & 1 else 7 * self.meshes[mesh].nt
 
+    def validate(self, mesh, query):
+        from . import tpmc
+        tpmc.check_query(query, self.meshes[mesh].V)
+
     def admit(self, slot, mesh, query, offset):
         return self.server.admit(slot, self.meshes[mesh], query, offset)
+
+    def admit_many(self, items):
+        return self.server.admit_many([(slot, self.meshes[mesh], q, off) for slot, mesh, q, off in items])
 
     def step(self, entries):
         self.server.step(entries)
 
     def results(self, slots):
         return self.server.results(slots, self.x_ref, self.A_ref)
+
+    def collect(self, slots):
+        return self.server.collect(slots, self.x_ref, self.A_ref)
+
+    def collected(self, ticket):
+        return self.server.collected(ticket)
 
     def release(self, slot):
         self.server.release(slot)
@@ -146,6 +189,7 @@ class Scheduler:
         self.stats = Stats()
         self._next_id = 0
         self._wake = None
+        self.pending = None  # (ticket, requests) of the last step's collection, not yet read
 
     # -- client side -------------------------------------------------------
     def submit(self, mesh: str, query: dict, t_arrival: float | None = None) -> asyncio.Future:
@@ -173,27 +217,52 @@ class Scheduler:
 
     # -- device side -------------------------------------------------------
     def _admit(self):
-        while self.queue and self.free_slots:
+        """Admit queued requests into free slots (FIFO; the head waits for memory),
+        all of this round's admissions in one executor call."""
+        picked = []
+        while self.queue and len(picked) < len(self.free_slots):
             req = self.queue[0]
             if req.future.cancelled():
                 self.queue.pop(0)
                 self.stats.cancelled += 1
                 continue
+            try:
+                self.ex.validate(req.mesh, req.query)
+            except Exception as e:  # invalid query: fails this request only
+                self.queue.pop(0)
+                req.future.set_exception(e)
+                self.stats.failed += 1
+                continue
             off = self.pool.alloc(req.words)
             if off is None:  # head of line waits for memory (FIFO, no starvation of big requests)
                 break
             self.queue.pop(0)
-            slot = self.free_slots.pop(0)
-            try:
-                req.tiles = int(self.ex.admit(slot, req.mesh, req.query, off))
-            except Exception as e:  # invalid query: fails this request only
-                self.pool.free(off, req.words)
-                self.free_slots.insert(0, slot)
-                req.future.set_exception(e)
+            req.slot, req.offset = self.free_slots[len(picked)], off
+            picked.append(req)
+        if not picked:
+            return
+        del self.free_slots[:len(picked)]
+        items = [(r.slot, r.mesh, r.query, r.offset) for r in picked]
+        try:
+            tiles = self.ex.admit_many(items)
+            outcome = [(r, t, None) for r, t in zip(picked, tiles)]
+        except Exception:  # one of them was refused: admit one by one, failing only that one
+            outcome = []
+            for r, it in zip(picked, items):
+                try:
+                    outcome.append((r, self.ex.admit(*it), None))
+                except Exception as e:
+                    outcome.append((r, 0, e))
+        now = self.clock()
+        for r, t, err in outcome:
+            if err is not None:
+                self.pool.free(r.offset, r.words)
+                self.free_slots.insert(0, r.slot)
+                r.future.set_exception(err)
                 self.stats.failed += 1
                 continue
-            req.slot, req.offset, req.t_admit = slot, off, self.clock()
-            self.active[slot] = req
+            r.tiles, r.t_admit = int(t), now
+            self.active[r.slot] = r
             self.stats.admitted += 1
         self.stats.max_active = max(self.stats.max_active, len(self.active))
 
@@ -203,17 +272,29 @@ class Scheduler:
         self.free_slots.append(req.slot)
         del self.active[req.slot]
 
-    def step_once(self) -> bool:
-        """Admit, run one step, complete finished requests.  False when idle."""
-        self._admit()
-        for slot, req in list(self.active.items()):
-            if req.future.cancelled():
-                self.stats.cancelled += 1
-                self._retire(req)
-        if not self.active:
-            return bool(self.queue)
-        # share the tile budget: equal shares, remainder to the oldest requests
-        reqs = sorted(self.active.values(), key=lambda r: r.rid)
+    def _finish(self, pending):
+        """Read a collection enqueued after an earlier step and complete its requests."""
+        ticket, done = pending
+        try:
+            res = self.ex.collected(ticket)
+        except Exception as e:  # a device failure fails the requests it held
+            res = [e] * len(done)
+        now = self.clock()
+        for r, out in zip(done, res):
+            if isinstance(out, Exception):
+                if not r.future.done():
+                    r.future.set_exception(out)
+                self.stats.failed += 1
+            else:
+                if not r.future.done():
+                    r.future.set_result(out)
+                self.stats.latencies_ms.append((now - r.t_arrival) * 1e3)
+                self.stats.latency_ids.append(r.rid)
+                self.stats.hits += int(out.get("hits", 0)) if isinstance(out, dict) else 0
+            self._retire(r)
+
+    def _entries(self, reqs):
+        """Share the tile budget: equal shares, remainder to the oldest requests."""
         budget = self.tiles_per_step
         share = max(1, budget // len(reqs))
         entries = []
@@ -235,31 +316,50 @@ class Scheduler:
                 else:
                     entries[e] = (r.slot, entries[e][1], used + more)
                 budget -= more
-        try:
-            self.ex.step(entries)
-        except Exception as e:  # a device failure fails every request on the device
-            for r in reqs:
-                if not r.future.done():
-                    r.future.set_exception(e)
-                self.stats.failed += 1
-                self._retire(r)
-            return True
-        self.stats.steps += 1
-        for slot, t0, n in entries:
-            self.active[slot].next_tile += n
-            self.stats.tiles += n
-        done = [r for r in reqs if r.next_tile >= r.tiles]
-        if done:
-            res = self.ex.results([r.slot for r in done])
-            now = self.clock()
-            for r, out in zip(done, res):
-                if not r.future.done():
-                    r.future.set_result(out)
-                self.stats.latencies_ms.append((now - r.t_arrival) * 1e3)
-                self.stats.latency_ids.append(r.rid)
-                self.stats.hits += int(out.get("hits", 0)) if isinstance(out, dict) else 0
-                self._retire(r)
-        return True
+        return entries
+
+    def step_once(self) -> bool:
+        """Admit, enqueue one step and the collection of the requests it
+        completes, then complete the requests of the previous step's
+        collection.  False when idle."""
+        self._admit()
+        in_flight = set(id(r) for r in self.pending[1]) if self.pending else set()
+        for slot, req in list(self.active.items()):
+            if req.future.cancelled() and id(req) not in in_flight:
+                self.stats.cancelled += 1
+                self._retire(req)
+        reqs = sorted((r for r in self.active.values() if r.next_tile < r.tiles), key=lambda r: r.rid)
+        new_pending = None
+        if reqs:
+            entries = self._entries(reqs)
+            try:
+                self.ex.step(entries)
+            except Exception as e:  # a device failure fails every request of the step
+                for r in reqs:
+                    if not r.future.done():
+                        r.future.set_exception(e)
+                    self.stats.failed += 1
+                    self._retire(r)
+                entries = []
+            if entries:
+                self.stats.steps += 1
+                for slot, t0, n in entries:
+                    self.active[slot].next_tile += n
+                    self.stats.tiles += n
+                done = [r for r in reqs if r.next_tile >= r.tiles]
+                if done:
+                    try:
+                        new_pending = (self.ex.collect([r.slot for r in done]), done)
+                    except Exception as e:
+                        for r in done:
+                            if not r.future.done():
+                                r.future.set_exception(e)
+                            self.stats.failed += 1
+                            self._retire(r)
+        if self.pending is not None:
+            self._finish(self.pending)
+        self.pending = new_pending
+        return bool(reqs) or self.pending is not None or bool(self.queue)
 
     async def run(self, stop: asyncio.Event | None = None):
         """Step while there is work; sleep until a submit when idle."""

@@ -102,6 +102,11 @@ _SIGS = {
     "tpmc_server_workspace_bytes": ([_u32, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
     "tpmc_server_create": ([_vp, _u32, _u64, _vp, _u64, ctypes.POINTER(_vp)], ctypes.c_int),
     "tpmc_server_admit": ([_vp, _u32, _vp, _QP, _u64, ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_server_admit_many": ([_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_vp), _QP, ctypes.POINTER(_u64),
+                                ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_server_collect": ([_vp, ctypes.POINTER(_u32), _u32, _dp, ctypes.c_double, ctypes.POINTER(_u32)],
+                            ctypes.c_int),
+    "tpmc_server_collected": ([_vp, _u32, _RP, _u32], ctypes.c_int),
     "tpmc_server_step": ([_vp, ctypes.POINTER(_u32), ctypes.POINTER(_u64), ctypes.POINTER(_u64), _u32], ctypes.c_int),
     "tpmc_server_results": ([_vp, ctypes.POINTER(_u32), _u32, _dp, ctypes.c_double, _RP], ctypes.c_int),
     "tpmc_server_release": ([_vp, _u32], ctypes.c_int),
@@ -118,7 +123,7 @@ for _name, (_args, _res) in _SIGS.items():
     _f.argtypes = _args
     _f.restype = _res
 
-ABI_VERSION = 6  # the structures below are laid out for this version of include/tpmc.h
+ABI_VERSION = 7  # the structures below are laid out for this version of include/tpmc.h
 if _lib.tpmc_abi_version() != ABI_VERSION:
     raise ImportError(f"libtpmc.so has ABI version {_lib.tpmc_abi_version()}, this binding expects "
                       f"{ABI_VERSION}: rebuild the library (python -c 'import __graft_entry__ as g; g.build()')")
@@ -452,6 +457,36 @@ class Server:
         _check(_lib.tpmc_server_admit(self._h, int(slot), mesh._h, ctypes.byref(q), int(tally_offset),
                                       ctypes.byref(nt)))
         return int(nt.value)
+
+    def admit_many(self, items) -> list:
+        """items: (slot, mesh, query dict, tally offset) each; returns the tile counts."""
+        n = len(items)
+        if n == 0:
+            return []
+        sl = (_u32 * n)(*[int(i[0]) for i in items])
+        ms = (_vp * n)(*[i[1]._h for i in items])
+        qs = _queries([i[2] for i in items])
+        off = (_u64 * n)(*[int(i[3]) for i in items])
+        nt = (_u64 * n)()
+        _check(_lib.tpmc_server_admit_many(self._h, n, sl, ms, qs, off, nt))
+        for i in items:
+            self._q[i[0]] = (i[2], i[1])
+        return [int(v) for v in nt]
+
+    def collect(self, slots, x_ref=(0.0, 0.0, 0.0), A_ref: float = 1.0) -> tuple:
+        """Enqueue the results of these slots; returns a ticket for collected()."""
+        n = len(slots)
+        sl = (_u32 * n)(*[int(s) for s in slots])
+        xr = (ctypes.c_double * 3)(*[float(v) for v in x_ref])
+        t = _u32()
+        _check(_lib.tpmc_server_collect(self._h, sl, n, xr, float(A_ref), ctypes.byref(t)))
+        return (int(t.value), n)
+
+    def collected(self, ticket) -> list:
+        t, n = ticket
+        res = (Result * n)()
+        _check(_lib.tpmc_server_collected(self._h, t, res, n))
+        return [result_dict(r) for r in res]
 
     def step(self, entries):
         n = len(entries)

@@ -177,3 +177,49 @@ def test_cancellation_frees_the_slot():
     r2 = asyncio.run(main())
     assert r2["value"] == solo_value(2, 4096 * 3)
     assert sched.stats.cancelled == 1 and not sched.active
+
+
+class PipelineLog(FakeExecutor):
+    """Records the order of device calls: collection tickets are read only
+    after the following step has been enqueued, admissions come in groups."""
+
+    def __init__(self, *a, **kw):
+        super().__init__(*a, **kw)
+        self.calls = []
+        self.tickets = 0
+        self.held = {}
+
+    def admit_many(self, items):
+        self.calls.append(("admit_many", len(items)))
+        return super().admit_many(items)
+
+    def step(self, entries):
+        self.calls.append(("step", len(entries)))
+        super().step(entries)
+
+    def collect(self, slots):
+        self.tickets += 1
+        self.held[self.tickets] = self.results(slots)
+        self.calls.append(("collect", self.tickets))
+        return self.tickets
+
+    def collected(self, ticket):
+        self.calls.append(("collected", ticket))
+        return self.held.pop(ticket)
+
+
+def test_pipelined_steps_and_grouped_admission():
+    ex = PipelineLog({"m": 100})
+    sched = Scheduler(ex, max_slots=8, pool_words=7 * 100 * 8, tiles_per_step=6)
+    reqs = [("m", _req(i, 4096 * (1 + i % 5)), 0) for i in range(30)]
+    res = _run(sched, reqs)
+    assert all(r["value"] == solo_value(i, 4096 * (1 + i % 5)) for i, r in enumerate(res))
+    seq = ex.calls
+    # every collection is read after the next step (or, at the end, after the last one) was enqueued
+    for k, c in enumerate(seq):
+        if c[0] == "collected":
+            j = seq.index(("collect", c[1]))
+            later_steps = [x for x in seq[j + 1:k] if x[0] == "step"]
+            assert later_steps or not any(x[0] == "step" for x in seq[k:]), (c, seq[j:k + 1])
+    assert max(n for name, n in seq if name == "admit_many") > 1
+    assert not ex.held and sched.pending is None
