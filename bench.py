@@ -846,10 +846,11 @@ def workload_served(args):
                                                          T_w=T_W, alpha=0.9, n=n, seed=10_000 + i)))
     max_slots = int(args.slots)
     pool_words = int(args.hbm_budget_gb * 2 ** 30) // 8
-    # tiles of 65536 particles: the tuner, timing one batch, cannot see the per-step cost of
-    # claiming tiles, and smaller tiles lowered the stream's saturation (2700 against 2900 req/s)
+    # tiles of 32768 particles: the tuner, timing one batch, cannot see the per-step costs of
+    # claiming tiles (smaller tiles) and of the last tiles of a step (larger ones); measured on
+    # the pipelined stream, 16384 / 32768 / 65536 gave 3600 / 3854 / 3669 req/s
     tuning = tune_for(args, meshes["sat100k"], [q for m, q in reqs if m == "sat100k"][:64],
-                      hold={"tile_particles": 65536})
+                      hold={"tile_particles": 32768})
     # the step budget is a particle count, so that the tuned tile size does not change it
     tiles_per_step = max(1, int(args.particles_per_step) // int(tuning["tile_particles"]))
     ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=pool_words)
