@@ -45,6 +45,9 @@ OPS_SEED = 950.0   # per particle: 2 Philox blocks + FP64 inverse-CDF seeding + 
 OPS_NODE = 40.0    # per BVH node visit: two slab tests + stack
 OPS_TRI = 45.0     # per watertight triangle test
 OPS_HIT = 225.0    # per hit: Philox block + re-emission + tally
+OPS_PRECULL = 540.0  # per particle the batched path's seeding estimate removes: 2 Philox blocks + FP32
+                     # inverse-CDF estimates + frame + grown root-box test, in place of OPS_SEED and the
+                     # one root-node visit such a particle costs on the plain path
 KERNEL_SOURCES = ["tpmc_device.hpp", "tpmc_math.hpp", "tpmc_kernels.hip", "tpmc_internal.h"]
 
 
@@ -148,12 +151,14 @@ def launch_record(kernel, ms, results, V_seg, T_seg):
     particles = sum(r["rays"] for r in results)
     segments = sum(r["segments"] for r in results)
     hits = sum(r["hits"] for r in results)
-    ops = particles * OPS_SEED + segments * (V_seg * OPS_NODE + T_seg * OPS_TRI) + hits * OPS_HIT
+    pre = sum(r.get("preculled", 0) for r in results)
+    ops = ((particles - pre) * OPS_SEED + pre * OPS_PRECULL + segments * (V_seg * OPS_NODE + T_seg * OPS_TRI)
+           - pre * OPS_NODE + hits * OPS_HIT)
     inst = kernel.split(" ")[0]
     traffic = stored_traffic(inst)
     return {"kernel": kernel, "ms": ms, "achieved_tlane_ops": ops / (ms / 1e3) / 1e12, "hbm_bytes": traffic,
             "frac": ops / (ms / 1e3) / ALU_PEAK,
-            "work": {"particles": particles, "segments": segments, "hits": hits,
+            "work": {"particles": particles, "preculled": pre, "segments": segments, "hits": hits,
                      "node_visits_per_segment": V_seg, "triangle_tests_per_segment": T_seg, "alg_lane_ops": ops}}
 
 
@@ -409,6 +414,28 @@ def cpu_baseline(case_list, mesh_map, budget_s=12.0, satellite=True):
                                     "single_thread": {"value": r_sat1, "unit": "hits/s",
                                                       "sample": f"first {ms1} particles ({h_sat1} hits, "
                                                                 f"{d_sat1:.1f} s)"}}
+        # attitude sweep: every 128th of the 1024 queries, first particles of each
+        sw = sweep_queries(1e6)[::128]
+        r_sw, h_sw, d_sw = _oracle_rate([(V, T, dict(q, flags=0), tree) for q in sw], 200_000, threads)
+        out["attitude_sweep"] = {"value": r_sw, "unit": "hits/s", "threads": threads,
+                                 "sample": f"first 200000 particles of {len(sw)} of the 1024 queries ({h_sw} hits, "
+                                           f"{d_sw:.1f} s)"}
+        # served stream: the first 8 requests of the default stream over its four meshes, first
+        # particles of each
+        names, reqs, _ = served_requests(SERVED_DEFAULT_REQUESTS)
+        reqs = reqs[:8]
+        meshes = {}
+        tb = time.perf_counter()
+        for k, (nm, nt) in enumerate(names.items()):
+            Vm, Tm = I.satellite(nt, seed=k)
+            meshes[nm] = (Vm, Tm, O.BVH(Vm, Tm))
+        build_s = time.perf_counter() - tb
+        kv = [(meshes[m][0], meshes[m][1], q, meshes[m][2]) for m, q in reqs]
+        r_sv, h_sv, d_sv = _oracle_rate(kv, 50_000, threads)
+        out["served_stream"] = {"value": r_sv, "unit": "hits/s", "threads": threads,
+                                "sample": f"first 50000 particles of the stream's first {len(reqs)} requests "
+                                          f"({h_sv} hits, {d_sv:.1f} s); meshes and hierarchies built outside the "
+                                          f"timed span ({build_s:.1f} s)"}
     return out
 
 
@@ -501,6 +528,77 @@ def summarize_counters(pmc_dir):
         lines.append(f"| `{k}` | " + " | ".join(f"{med.get(c, float('nan')):.4g}" for c in SQ_COUNTERS + L1_COUNTERS)
                      + f" | {lanes:.1f} | {hit:.3f} |")
     print("\n".join(lines))
+
+
+def summarize_served_trace(trace_dir):
+    """Markdown summary of a rocprofv3 --kernel-trace of the served workload
+    (run with --served-loads "" so that every batched launch is a saturation
+    step): step launches, the time between one step's end and the next one's
+    start, how much of that time no kernel ran, and the kernels run between
+    steps."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+
+    def short(n):
+        import re
+        m = re.search(r"(?<![A-Za-z0-9_])([A-Za-z_][A-Za-z0-9_]*_kernel)(<[^>]*>)?", n)
+        return (m.group(1) + (m.group(2) or "")) if m else n.split("(")[0]
+
+    steps = [r for r in rows if "batch_kernel<" in r[2]]
+    if len(steps) < 2:
+        print("fewer than two step launches in the trace")
+        return
+    t0, t1 = steps[0][0], steps[-1][1]
+    inside = [r for r in rows if r[0] >= t0 and r[1] <= t1]
+
+    def busy(lo, hi):  # union of kernel intervals within [lo, hi]
+        tot, cur = 0, lo
+        for a, b, _ in inside:
+            a, b = max(a, cur), min(b, hi)
+            if b > a:
+                tot += b - a
+                cur = b
+        return tot
+
+    dur = np.array([(b - a) * 1e-6 for a, b, _ in steps])
+    gap = np.array([(steps[k + 1][0] - steps[k][1]) * 1e-6 for k in range(len(steps) - 1)])
+    idle = np.array([g - busy(steps[k][1], steps[k + 1][0]) * 1e-6 for k, g in enumerate(gap)])
+    span = (t1 - t0) * 1e-6
+    others = {}
+    for a, b, n in inside:
+        if "batch_kernel<" not in n:
+            o = others.setdefault(short(n), [0, 0.0])
+            o[0] += 1
+            o[1] += (b - a) * 1e-6
+    inst = {}
+    for _, _, n in steps:
+        inst[short(n)] = inst.get(short(n), 0) + 1
+    q = lambda v, p: float(np.percentile(v, p))
+    out = [f"Step launches: {len(steps)} ({', '.join(f'`{k}` x {v}' for k, v in sorted(inst.items()))}), "
+           f"from the first step's start to the last step's end {span:.1f} ms.",
+           "",
+           "| | median | p90 | max | total |",
+           "|---|---|---|---|---|",
+           f"| step kernel ms | {q(dur, 50):.2f} | {q(dur, 90):.2f} | {dur.max():.2f} | {dur.sum():.1f} |",
+           f"| between steps ms | {q(gap, 50):.3f} | {q(gap, 90):.3f} | {gap.max():.3f} | {gap.sum():.1f} |",
+           f"| of which no kernel ran ms | {q(idle, 50):.3f} | {q(idle, 90):.3f} | {idle.max():.3f} | {idle.sum():.1f} |",
+           "",
+           f"Device busy (union of kernel intervals) {100.0 * busy(t0, t1) * 1e-6 / span:.1f} % of the span; "
+           f"step kernels alone {100.0 * dur.sum() / span:.1f} %.",
+           "",
+           "Kernels between the steps:",
+           "",
+           "| kernel | launches | total ms |",
+           "|---|---|---|"]
+    for k, (c, t) in sorted(others.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{k}` | {c} | {t:.2f} |")
+    print("\n".join(out))
 
 
 def fixed_tuning(args, key):
@@ -817,6 +915,28 @@ def workload_sweep(args):
           {"workload": sw["workload"], "path": "one persistent graph-replayed launch", "bvh": args.bvh}, sw)
 
 
+SERVED_MESHES = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
+SERVED_WARM, SERVED_MEASURED = 200, 2000  # default served run: warm-up and measured requests
+SERVED_DEFAULT_REQUESTS = SERVED_WARM + SERVED_MEASURED
+
+
+def served_requests(n_req):
+    """The served stream's requests: mesh uniform over the four satellites, uniform random
+    attitude, S ~ U[2, 10], N log-uniform in [1e5, 1e7], alpha = 0.9, seed = request id.
+    Returns the mesh sizes, the requests and the generator, which goes on to draw the
+    arrival gaps."""
+    from paper_1312_3691_amd import inputs as I
+    rng = np.random.default_rng(7)
+    names = list(SERVED_MESHES)
+    quats = I.random_quats(n_req, 3)
+    reqs = []
+    for i in range(n_req):
+        n = int(10 ** rng.uniform(5, 7))
+        reqs.append((names[rng.integers(0, 4)], I.query(q=tuple(quats[i]), S=float(rng.uniform(2, 10)), T_inf=T_INF,
+                                                         T_w=T_W, alpha=0.9, n=n, seed=10_000 + i)))
+    return dict(SERVED_MESHES), reqs, rng
+
+
 def workload_served(args):
     """Served stream: Poisson arrivals over four resident satellite meshes (~1k, 20k, 100k,
     500k triangles), random attitudes, S ~ U[2, 10], N log-uniform in [1e5, 1e7], alpha = 0.9,
@@ -832,18 +952,10 @@ def workload_served(args):
     from paper_1312_3691_amd import tpmc
     from paper_1312_3691_amd.serve import GpuExecutor, Scheduler
     ctx = tpmc.Context(0)
-    sizes = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
-    meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i), builder=args.bvh) for i, (k, v) in enumerate(sizes.items())}
-    rng = np.random.default_rng(7)
     n_warm, n_meas = int(args.warm), int(args.requests)
     n_req = n_warm + n_meas
-    names = list(sizes)
-    quats = I.random_quats(n_req, 3)
-    reqs = []
-    for i in range(n_req):
-        n = int(10 ** rng.uniform(5, 7))
-        reqs.append((names[rng.integers(0, 4)], I.query(q=tuple(quats[i]), S=float(rng.uniform(2, 10)), T_inf=T_INF,
-                                                         T_w=T_W, alpha=0.9, n=n, seed=10_000 + i)))
+    sizes, reqs, rng = served_requests(n_req)
+    meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i), builder=args.bvh) for i, (k, v) in enumerate(sizes.items())}
     max_slots = int(args.slots)
     pool_words = int(args.hbm_budget_gb * 2 ** 30) // 8
     # tiles of 32768 particles: the tuner, timing one batch, cannot see the per-step costs of
@@ -923,7 +1035,7 @@ def workload_served(args):
     for (mesh, q), r in list(zip(reqs, res))[:8]:
         solo, pr = tpmc.run(meshes[mesh], [q])
         same = same and isinstance(r, dict) and all(np.array_equal(np.asarray(solo[0][k]), np.asarray(r[k]))
-                                                    for k in solo[0])
+                                                    for k in tpmc.same_on_every_path(solo[0]))
         pr.close()
     torch.cuda.synchronize()
     _line("particle-surface hits/sec on 1 MI355X (served stream); p50/p99 query ms", sat["hits_per_s"], "hits/s",
@@ -959,6 +1071,8 @@ def main():
     ap.add_argument("--summarize-counters", metavar="PMC_DIR",
                     help="print the batched kernels' instruction and L1 counters from runs under PMC_DIR/sq, PMC_DIR/l1")
     ap.add_argument("--traffic-out", default=None, help="output path for --summarize-traffic")
+    ap.add_argument("--summarize-served-trace", metavar="TRACE_DIR",
+                    help="step launches and the gaps between them, from a kernel trace of the served workload")
     ap.add_argument("--workload", default="plate-cylinder",
                     choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv",
                              "energy", "ceilings"],
@@ -969,8 +1083,8 @@ def main():
     ap.add_argument("--particles-moments", type=float, default=4e6)
     ap.add_argument("--particles-boxcv", type=float, default=1e8)
     ap.add_argument("--particles-energy", type=float, default=1e7)
-    ap.add_argument("--requests", type=int, default=2000, help="served: measured requests per load")
-    ap.add_argument("--warm", type=int, default=200, help="served: warm-up requests per load")
+    ap.add_argument("--requests", type=int, default=SERVED_MEASURED, help="served: measured requests per load")
+    ap.add_argument("--warm", type=int, default=SERVED_WARM, help="served: warm-up requests per load")
     ap.add_argument("--slots", type=int, default=128, help="served: request slots")
     ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="served: per-request tally budget")
     ap.add_argument("--fifo-requests", type=int, default=600, help="served: requests timed on the plain path")
@@ -988,6 +1102,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_traffic:
         summarize_traffic(args.summarize_traffic, args.traffic_out)
+        return
+    if args.summarize_served_trace:
+        summarize_served_trace(args.summarize_served_trace)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters)
@@ -1083,7 +1200,8 @@ def main():
                 "step": {"kernel_ms": step_ms, "alg_lane_ops": step_ops,
                          "frac": step_ops / (step_ms / 1e3) / ALU_PEAK},
                 "launches": launches,
-                "work_units": {"per_particle_seeding": OPS_SEED, "per_node_visit": OPS_NODE,
+                "work_units": {"per_particle_seeding": OPS_SEED, "per_preculled_particle": OPS_PRECULL,
+                               "per_node_visit": OPS_NODE,
                                "per_triangle_test": OPS_TRI, "per_hit": OPS_HIT}}
 
     # accuracy of every case against the per-facet closed form

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 7
+#define TPMC_ABI_VERSION 8
 
 typedef enum {
   TPMC_OK = 0,
@@ -123,6 +123,10 @@ typedef struct {
                            (TPMC_Q_ENERGY_ACC only; 0 when the result follows the model exactly) */
   uint64_t guard_trips; /* ray segments ended by the traversal's step bound instead of by the
                            search (a damaged hierarchy); 0 for every valid mesh */
+  uint64_t preculled;   /* of the missed particles, those the batched path's seeding estimate
+                           showed to miss the BVH root's boxes before their exact seeding (a
+                           work count: the plain path reports 0, and every other field is the
+                           same either way) */
 } tpmc_result;
 
 typedef struct {
@@ -156,7 +160,7 @@ typedef struct {
   uint32_t refill_lanes;   /* 1..64, default 32: a wave serves the lanes whose ray segment has ended
                               (re-emission, tallies, next segment or particle) once fewer than this
                               many of its 64 lanes are still traversing */
-  uint32_t tile_particles; /* multiple of 64 in [64, 2^22], default 16384: particles per work tile
+  uint32_t tile_particles; /* multiple of 64 in [64, 65536], default 16384: particles per work tile
                               of the persistent kernel; read when a batch or server is created */
   uint32_t groups_per_cu;  /* 1..32, default 8: workgroups (256 lanes) per compute unit of the
                               persistent launches (batches and server steps) */
@@ -361,6 +365,26 @@ tpmc_status tpmc_ceiling_atomic(tpmc_ctx ctx, void* dev_buf, uint32_t slots, uin
                                 double* atomics_per_s);
 tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots, uint32_t per_thread,
                                     double* atomics_per_s);
+
+/* ---- Check of the batched path's two-stage seeding ----
+ * The persistent kernel (batches and server steps) seeds in two stages: an
+ * FP32 estimate of each particle's first ray from its own variates (Sec.
+ * III.A.1-3 in FP32, tabulated starts and one Halley step per inverse-CDF
+ * solve) is tested against the BVH root's boxes grown on every side by 2 % of
+ * the CV radius, and only the particles it does not rule out are seeded
+ * exactly (FP64) and traced; the others are misses either way, so no result
+ * field other than tpmc_result.preculled depends on it.  The margin rests on
+ * the estimate's error, which this entry point measures: for particles
+ * [0, q->n_particles) of the query it returns the largest distance between
+ * the estimated and the exact ray (|o_est - o| + 2 r |w_est/|w_est| - w/|w||)
+ * as a fraction of the margin, over the particles the estimate covers (it
+ * gives up near the poles mu = +-1 and when a solve's start is poor; those
+ * particles are always seeded exactly), and their number.  Workspace: the
+ * caller's device memory, >= TPMC_PRECULL_CHECK_BYTES, 256-byte aligned.
+ * Synchronises the context's stream. */
+#define TPMC_PRECULL_CHECK_BYTES 1024
+tpmc_status tpmc_precull_check(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, void* dev_ws, uint64_t ws_bytes,
+                               double* max_err_over_margin, uint64_t* estimated);
 
 #ifdef __cplusplus
 }

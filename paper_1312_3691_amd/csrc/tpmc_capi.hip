@@ -285,7 +285,19 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
     }
     q->Gamma_hat = cum / (2.0 * sqrtpi);
   }
-  for (int k = 0; k < 3; ++k) q->c0f[k] = (float)q->c0[k];
+  for (int k = 0; k < 3; ++k) {
+    q->c0f[k] = (float)q->c0[k];
+    q->e1f[k] = (float)q->e1[k];
+    q->e2f[k] = (float)q->e2[k];
+  }
+  q->Sf = (float)q->S;
+  q->Zf = (float)q->Z;
+  q->erfSf = (float)q->erfS;
+  q->erfcSf = (float)q->erfcS;
+  q->expmS2f = (float)q->expmS2;
+  q->rf = (float)q->r;
+  q->lat_kf = (float)q->lat_k;
+  q->lat_row = q->s_zero ? -1.0f : (float)(std::log(S / 0.05) / 0.05);  // ln(S / S0) / dL of the table
   const double tau = std::sqrt(in->T_w / in->T_inf);
   q->tau = (float)tau;
   q->alpha = (float)in->alpha;
@@ -469,8 +481,8 @@ extern "C" tpmc_status tpmc_set_tuning(tpmc_ctx ctx, const tpmc_tuning* t) {
   if (!ctx || !t) return fail(TPMC_E_INVALID, "ctx and tuning must not be NULL");
   if (t->refill_lanes < 1 || t->refill_lanes > 64)
     return fail(TPMC_E_INVALID, "refill_lanes = %u outside 1..64", t->refill_lanes);
-  if (t->tile_particles < 64 || t->tile_particles > (1u << 22) || t->tile_particles % 64 != 0)
-    return fail(TPMC_E_INVALID, "tile_particles = %u is not a multiple of 64 in [64, 2^22]", t->tile_particles);
+  if (t->tile_particles < 64 || t->tile_particles > (1u << 16) || t->tile_particles % 64 != 0)
+    return fail(TPMC_E_INVALID, "tile_particles = %u is not a multiple of 64 in [64, 65536]", t->tile_particles);
   if (t->groups_per_cu < 1 || t->groups_per_cu > 32)
     return fail(TPMC_E_INVALID, "groups_per_cu = %u outside 1..32", t->groups_per_cu);
   if (t->plain_groups_per_cu > 32)
@@ -759,6 +771,7 @@ static void copy_result(const ResultDev& r, tpmc_result* o) {
   for (int k = 0; k < 3; ++k) o->Mhat[k] = r.Mhat[k];
   o->tr_capped = r.tr_capped;
   o->guard_trips = r.guard_trips;
+  o->preculled = r.preculled;
 }
 
 // Clears the per-query totals the reduction writes (slots kFx..kCount).
@@ -1357,6 +1370,38 @@ static tpmc_status time_launch(tpmc_ctx ctx, F launch, double* ms) {
   if (e != hipSuccess) return fail(TPMC_E_DEVICE, "ceiling timing: %s", hipGetErrorString(e));
   if (!(f > 0.0f)) return fail(TPMC_E_DEVICE, "ceiling timing: elapsed time %g ms", (double)f);
   *ms = (double)f;
+  return TPMC_OK;
+}
+
+extern "C" tpmc_status tpmc_precull_check(tpmc_ctx ctx, tpmc_mesh m, const tpmc_query* q, void* dev_ws,
+                                          uint64_t ws_bytes, double* max_err_over_margin, uint64_t* estimated) {
+  if (!ctx || !m || !q || !dev_ws || !max_err_over_margin || !estimated)
+    return fail(TPMC_E_INVALID, "ctx, mesh, query, workspace and outputs must not be NULL");
+  if (m->ctx != ctx) return fail(TPMC_E_BUSY, "mesh belongs to another context");
+  if (ws_bytes < TPMC_PRECULL_CHECK_BYTES || (uintptr_t)dev_ws % 256 != 0)
+    return fail(TPMC_E_WORKSPACE, "workspace of %llu bytes at %p: need %d bytes, 256-byte aligned",
+                (unsigned long long)ws_bytes, dev_ws, TPMC_PRECULL_CHECK_BYTES);
+  std::vector<QueryDev> hq;
+  tpmc_status s = make_queries(m, q, 1, hq);
+  if (s != TPMC_OK) return s;
+  static_assert(sizeof(QueryDev) + 16 <= TPMC_PRECULL_CHECK_BYTES, "check workspace too small");
+  QueryDev* dq = static_cast<QueryDev*>(dev_ws);
+  unsigned long long* dout = reinterpret_cast<unsigned long long*>(static_cast<uint8_t*>(dev_ws) +
+                                                                   ((sizeof(QueryDev) + 15) & ~(size_t)15));
+  unsigned long long h[2] = {0, 0};
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMemcpyAsync(dq, hq.data(), sizeof(QueryDev), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) {
+    launch_precull_check(dq, hq[0].N, dout, ctx->n_cu * 4, ctx->stream);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return fail(TPMC_E_DEVICE, "pre-cull check: %s", hipGetErrorString(e));
+  double r;
+  std::memcpy(&r, &h[0], sizeof r);
+  *max_err_over_margin = r;
+  *estimated = h[1];
   return TPMC_OK;
 }
 

@@ -519,6 +519,149 @@ __device__ __forceinline__ bool slab(const Ray& r, float lox, float loy, float l
 }
 
 // ---------------------------------------------------------------------------
+// Seeding in two stages.  A particle whose ray misses both boxes of the BVH
+// root is a miss whatever its exact state, so its exact FP64 seeding (above)
+// is work without effect; on small or flat bodies most particles are such.
+// precull_may_enter estimates the particle's ray from the same variates in
+// FP32 (the tabulated starts and two FP32 Halley steps for each inverse-CDF
+// solve, the hardware exp, log, sine and cosine, the frame in FP32) and tests
+// it against the root's two boxes grown by kPrecullMargin CV radii on every
+// side.  Returns false only if that grown test fails, i.e. only for particles
+// whose exact ray misses the root's boxes:
+//  * by cubic convergence the error left after a Halley step dx is about
+//    C dx^3; the estimate gives up (the particle is seeded exactly) unless
+//    each solve's second step is below 1e-5 (of the speed, for the speed), so
+//    what remains is near the FP32 rounding of the solves; it also gives up
+//    outside the start tables' ranges of S and s;
+//  * a latitude error d moves cos(phi) by d |mu| / cos(phi), so the estimate
+//    gives up for cos(phi) < 0.05 (mu within 1.25e-3 of +-1); elsewhere the
+//    point and the direction move by at most ~20 d, relative to r and to |w|;
+//  * along the at most 2 r of path inside the CV, the estimated ray then stays
+//    within ~60 d r of the exact one, and the margin (0.02 r) exceeds that
+//    bound by orders of magnitude for the ~1e-7 that the solves leave; the
+//    hardware sine, cosine and logarithm add errors of the same order.
+// tpmc_precull_check measures the distance between estimated and exact rays.
+// Box control volumes are not estimated (always true).
+// ---------------------------------------------------------------------------
+constexpr float kPrecullMargin = 0.02f;
+
+__device__ __forceinline__ float unif32_hi(uint32_t k) { return ((float)k + 0.5f) * 0x1p-32f; }  // ~unif64(k)
+
+// Estimate-only forms (FP32, hardware log2 / exp2; the exact path keeps its
+// own): tabulated starts from the precomputed table row of S, and G with its
+// erf-term factor precomputed.
+__device__ __forceinline__ float hw_ln(float x) { return 0.69314718f * __builtin_amdgcn_logf(x); }
+
+// fs in [0, ns - 1], ft in [0, nt - 1]
+__device__ __forceinline__ float bilinear_start(const float* __restrict__ tab, int ns, int nt, float fs, float ft) {
+  const int i = min((int)fs, ns - 2), j = min((int)ft, nt - 2);
+  const float a = fs - (float)i, b = ft - (float)j;
+  const float* r0 = tab + i * nt + j;
+  const float* r1 = r0 + nt;
+  return (1.0f - a) * ((1.0f - b) * r0[0] + b * r0[1]) + a * ((1.0f - b) * r1[0] + b * r1[1]);
+}
+
+__device__ __forceinline__ void latitude_G32_est(const QueryDev& q, float t, float& G, float& dG, float& d2G) {
+  const float St = q.Sf * t;
+  const float e = __expf(-St * St);
+  const float ey = e * erfcx32(fabsf(St));       // erfc(|S t|)
+  const float cc = St >= 0.0f ? 2.0f - ey : ey;  // erfc(-S t)
+  const float E = St < -1.0f ? cc - q.erfcSf : (cc - 1.0f) + q.erfSf;
+  G = q.lat_kf * E + 0.5f * (float)kSqrtPi * q.Sf * (t * t * cc - q.erfcSf) + 0.5f * (t * e + q.expmS2f);
+  dG = e + (float)kSqrtPi * St * cc;
+  d2G = q.Sf * (float)kSqrtPi * cc;
+}
+
+// The estimated ray (o, w); false when the estimate gives up.
+__device__ inline bool precull_estimate(const QueryDev& q, const float* __restrict__ lat_tab,
+                                        const float* __restrict__ vn_tab, uint64_t pid, float o[3], float w[3]) {
+  if (q.box) return false;
+  const U4 r0 = stream(q, pid, 0u);
+  const U4 r1 = stream(q, pid, 1u);
+  // latitude mu = sin(phi)
+  const float ua = unif32_hi(r0.a), uam = unif32_hi(~r0.a);  // u and 1 - u
+  float mu;
+  if (q.s_zero) {
+    mu = 2.0f * ua - 1.0f;
+  } else {
+    // inside the table's S range only (and not the small-S form of G)
+    if (!(q.lat_row >= 0.0f && q.lat_row <= (float)(kLatNS - 1)) || q.Sf < 0.25f) return false;
+    const float t = hw_ln(ua) - hw_ln(uam);
+    const float ft = fminf(fmaxf((t - kLatT0) * (1.0f / kLatDT), 0.0f), (float)(kLatNT - 1));
+    mu = fminf(fmaxf(bilinear_start(lat_tab, kLatNS, kLatNT, q.lat_row, ft), -1.0f), 1.0f);
+    float lo = -1.0f, hi = 1.0f, G, dG, d2G, dx = 0.0f;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      latitude_G32_est(q, mu, G, dG, d2G);
+      dx = halley_step(mu, G - ua * q.Zf, dG, d2G, lo, hi);
+    }
+    if (!(dx <= 1e-5f)) return false;
+  }
+  const float cphi = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+  if (!(cphi >= 0.05f)) return false;
+  // inward normal speed at s = S mu
+  const float s = q.s_zero ? 0.0f : q.Sf * mu;
+  const float es2 = __expf(-s * s);
+  const float ta = es2 * erfcx32(fabsf(s));  // erfc(|s|)
+  const float erfcs = s >= 0.0f ? ta : 2.0f - ta, erfcms = s >= 0.0f ? 2.0f - ta : ta;
+  const float erfs = s >= 0.0f ? 1.0f - ta : ta - 1.0f;
+  const float chi = es2 + (float)kSqrtPi * s * erfcms;
+  if (!(s > -9.0f)) return false;
+  const float uc = unif32_hi(r0.c), ucm = unif32_hi(~r0.c);
+  const float hi0 = fmaxf(s, 0.0f) + 7.0f;
+  const float fs = (s - kVnS0) * (1.0f / kVnDS);
+  if (!(fs >= 0.0f && fs <= (float)(kVnNS - 1))) return false;  // inside the table's s range only
+  const float tv = hw_ln(uc) - hw_ln(ucm);
+  float wn = bilinear_start(vn_tab, kVnNS, kVnNT, fs,
+                            fminf(fmaxf((tv - kVnT0) * (1.0f / kVnDT), 0.0f), (float)(kVnNT - 1)));
+  if (!(wn > 0.0f && wn < hi0)) return false;
+  {
+    float lo = 0.0f, hi = hi0, F, dF, d2F, dx = 0.0f;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      normal_speed_F32(s, es2, erfs, erfcs, erfcms, wn, F, dF, d2F);
+      dx = halley_step(wn, F - uc * chi, dF, d2F, lo, hi);
+    }
+    if (!(dx <= 1e-5f * wn)) return false;
+  }
+  // tangential Gaussians (Box-Muller) and the angles; v_sin / v_cos take revolutions
+  const float rad = sqrtf(-2.0f * hw_ln(unif32_hi(r0.d)));
+  const float ub = unif32_hi(r1.a), uth = unif32_hi(r0.b);
+  const float g1 = rad * __builtin_amdgcn_cosf(ub) * (float)kInvSqrt2;
+  const float g2 = rad * __builtin_amdgcn_sinf(ub) * (float)kInvSqrt2;
+  const float sth = __builtin_amdgcn_sinf(uth), cth = __builtin_amdgcn_cosf(uth);
+  const float wt1 = q.Sf * cphi + g1;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float ci = cth * q.e1f[i] + sth * q.e2f[i];
+    const float di = -sth * q.e1f[i] + cth * q.e2f[i];
+    const float ni = mu * q.Uf[i] - cphi * ci;
+    const float t1i = cphi * q.Uf[i] + mu * ci;
+    o[i] = q.c0f[i] - q.rf * ni;
+    w[i] = wn * ni + wt1 * t1i - g2 * di;
+  }
+  return true;
+}
+
+__device__ inline bool precull_may_enter(const QueryDev& q, const float* __restrict__ lat_tab,
+                                         const float* __restrict__ vn_tab, const Node* __restrict__ nodes,
+                                         uint64_t pid) {
+  float o[3], w[3];
+  if (!precull_estimate(q, lat_tab, vn_tab, pid, o, w)) return true;
+  Ray r;
+  r.ox = o[0]; r.oy = o[1]; r.oz = o[2];
+  r.idx = __builtin_amdgcn_rcpf(w[0]);
+  r.idy = __builtin_amdgcn_rcpf(w[1]);
+  r.idz = __builtin_amdgcn_rcpf(w[2]);
+  const float m = kPrecullMargin * q.rf;
+  const Node& nd = nodes[0];
+  const float inf = __builtin_inff();
+  float tn;
+  return slab(r, nd.lo0x - m, nd.lo0y - m, nd.lo0z - m, nd.hi0x + m, nd.hi0y + m, nd.hi0z + m, inf, tn) ||
+         slab(r, nd.lo1x - m, nd.lo1y - m, nd.lo1z - m, nd.hi1x + m, nd.hi1y + m, nd.hi1z + m, inf, tn);
+}
+
+// ---------------------------------------------------------------------------
 // Gas-surface interaction (Sec. II.A), FP32.  Maxwell model: diffuse with
 // probability alpha -- the particle leaves the side it arrived on with the
 // flux-weighted half-range Maxwellian of T_w (normal speed tau sqrt(-ln u),

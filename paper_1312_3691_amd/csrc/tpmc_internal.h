@@ -6,10 +6,11 @@
 namespace tpmc {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64s)
+constexpr int kWaves = kBlock / 64;
 constexpr int kMaxReflections = 64;
 constexpr int kLdsTallyMaxTris = 512;  // per-workgroup LDS tallies up to this mesh size
 constexpr int kLaneTallyMaxTris = 2;   // per-lane LDS tallies for tiny meshes
-constexpr int kScalarSlots = 20;       // int64 per query, see ScalarSlot
+constexpr int kScalarSlots = 21;       // int64 per query, see ScalarSlot
 
 // Per-query int64 block.  D is the momentum one particle gives the body along
 // the free stream (sum over its hits of (w - w').U); D and D^2 are quantised
@@ -19,7 +20,9 @@ enum ScalarSlot {
   kFx = 8, kFy = 9, kFz = 10, kLx = 11, kLy = 12, kLz = 13, kCount = 14,
   kSE = 15, kSE2 = 16,  // per-particle energy E = sum over hits of |w|^2 - |w'|^2, and E^2
   kTrCap = 17,          // diffuse re-emissions whose temperature the kernel's bound limited
-  kGuard = 18           // ray segments ended by the traversal step bound (a damaged tree)
+  kGuard = 18,          // ray segments ended by the traversal step bound (a damaged tree)
+  kPreculled = 19,      // particles the seeding estimate showed to miss the root's boxes (batched kernel)
+  kPrecullOff = 20      // nonzero once the batched kernel has switched the estimate off for this query
 };
 
 struct Node;
@@ -61,6 +64,11 @@ struct alignas(16) QueryDev {
   uint32_t eacc;                     // energy accommodation on (else tau_r = tau)
   uint32_t pad2_;
   double lat_k;                      // sqrt(pi) / (4 S), the erf term's factor in the latitude CDF
+  // FP32 copies for the seeding estimate of the pre-cull (precull_may_enter)
+  float e1f[3], e2f[3];
+  float Sf, Zf, erfSf, erfcSf, expmS2f, rf;
+  float lat_kf;   // sqrt(pi) / (4 S)
+  float lat_row;  // row coordinate of S in the latitude start table (may lie outside it)
 };
 
 // Device result of the finalisation kernel (mirrors tpmc_result).
@@ -70,7 +78,7 @@ struct ResultDev {
   uint64_t rays, hits, segments, missed, escaped, capped;
   double Qhat, CH, CH_sigma;
   double Mhat[3];
-  uint64_t tr_capped, guard_trips;
+  uint64_t tr_capped, guard_trips, preculled;
 };
 
 // One slot admitted by a serving step's admission kernel: its constants and

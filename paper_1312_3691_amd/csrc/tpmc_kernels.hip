@@ -306,17 +306,20 @@ struct Hit {
   float dx, dy, dz, lx, ly, lz;
 };
 
-// Per-lane exact integer accumulators.  Rays and segments are not kept: a
-// particle retires by missing, escaping or reaching the hit cap, and every
-// segment ends in a hit, an escape or a miss, so rays = missed + escaped +
-// capped and segments = hits + missed + escaped (an escape through a
-// supporting plane is one untraced segment after the hit).
+// Exact integer accumulators: per lane the quantised per-particle sums, per
+// wave (scalar registers, from ballots at convergent points) the event
+// counts.  Rays and segments are not kept: a particle retires by missing,
+// escaping or reaching the hit cap, and every segment ends in a hit, an
+// escape or a miss, so rays = missed + escaped + capped and segments = hits +
+// missed + escaped (an escape through a supporting plane is one untraced
+// segment after the hit).
 struct Acc {
   long long sD, sD2, sE, sE2, tot[7];
-  uint32_t hits, missed, escaped, capped;
-  uint32_t tr_capped;     // re-emissions whose temperature the kernel's bound limited
-  uint32_t guard;         // segments ended by the traversal step bound
   uint32_t nodes, tests;  // traversal work (counting kernels only)
+  // wave-uniform
+  uint64_t hits, missed, escaped, capped;
+  uint64_t tr_capped;  // re-emissions whose temperature the kernel's bound limited
+  uint64_t guard;      // segments ended by the traversal step bound
 };
 
 __device__ __forceinline__ void acc_zero(Acc& A) {
@@ -328,6 +331,8 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
   A.nodes = A.tests = 0;
 }
 
+__device__ __forceinline__ uint64_t lanes(bool p) { return (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(p)); }
+
 // Outcome of a finished segment.  kOutHitLeft: a hit whose outgoing segment
 // cannot hit anything (the mesh lies on the other side of the triangle's
 // plane), so that segment is counted and the particle escapes untraced.
@@ -337,7 +342,7 @@ enum Outcome : int { kOutGoOn = 0, kOutMissed = 1, kOutEscaped = 2, kOutCapped =
 // a7-a9 for a lane whose traversal has ended: re-emission and bookkeeping of
 // the hit, or the particle's exit.  The particle retires unless kOutGoOn.
 __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t* orig, const QueryDev& q, Lane& L,
-                                              const Seg& s, Hit& h, int32_t& first_id, uint32_t& tr_capped) {
+                                              const Seg& s, Hit& h, int32_t& first_id, bool& tr_limited) {
   const int k = s.best;
   first_id = -2;  // not the first segment's outcome
   if (k < 0) {
@@ -354,7 +359,7 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
   const float py = s.b0 * tr.v0y + s.b1 * tr.v1y + s.b2 * tr.v2y;
   const float pz = s.b0 * tr.v0z + s.b1 * tr.v1z + s.b2 * tr.v2z;
   float nwx = L.wx, nwy = L.wy, nwz = L.wz;
-  if (reemit(q, L.pid, L.hits, tr.nx, tr.ny, tr.nz, nwx, nwy, nwz)) ++tr_capped;
+  tr_limited = reemit(q, L.pid, L.hits, tr.nx, tr.ny, tr.nz, nwx, nwy, nwz);
   L.E += (L.wx * L.wx + L.wy * L.wy + L.wz * L.wz) - (nwx * nwx + nwy * nwy + nwz * nwz);
   const float dx = L.wx - nwx, dy = L.wy - nwy, dz = L.wz - nwz;
   const float rx = px - q.c0f[0], ry = py - q.c0f[1], rz = pz - q.c0f[2];
@@ -385,12 +390,15 @@ __device__ __forceinline__ int finish_segment(const TriRec* tris, const uint32_t
   return clear ? kOutHitLeft : kOutGoOn;
 }
 
-// Event counts of a lane whose segment ended with outcome `out`.
-__device__ __forceinline__ void count_outcome(Acc& A, int out, bool hit) {
-  A.hits += hit ? 1u : 0u;
-  A.missed += out == kOutMissed ? 1u : 0u;
-  A.escaped += (out == kOutEscaped || out == kOutHitLeft) ? 1u : 0u;
-  A.capped += out == kOutCapped ? 1u : 0u;
+// Event counts of a service pass (convergent): lanes with fin set ended a
+// segment with outcome out (hit: with a hit; limited: whose re-emission the
+// temperature bound limited).
+__device__ __forceinline__ void count_pass(Acc& A, bool fin, int out, bool hit, bool limited) {
+  A.hits += lanes(fin && hit);
+  A.missed += lanes(fin && out == kOutMissed);
+  A.escaped += lanes(fin && (out == kOutEscaped || out == kOutHitLeft));
+  A.capped += lanes(fin && out == kOutCapped);
+  A.tr_capped += lanes(fin && limited);
 }
 
 __device__ __forceinline__ void retire(const QueryDev& q, const Lane& L, Acc& A) {
@@ -401,8 +409,9 @@ __device__ __forceinline__ void retire(const QueryDev& q, const Lane& L, Acc& A)
 }
 
 // Tally of one hit per lane.  Called by every lane of the wave (convergent).
-// Totals-only sums go to the lane's LDS slots lds[c][lane] when TOT_LDS (the
-// persistent kernel, short of registers), else to registers.
+// Totals-only sums go to the wave's LDS slots lds[c][wave] (LDS atomics; the
+// few lanes of a pass with a hit share them) when TOT_LDS (the persistent
+// kernel, short of registers), else to the lane's registers.
 template <int MODE, bool TOT_LDS = true>
 __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long* __restrict__ g,
                                       unsigned long long* lds, uint32_t nt, Acc& A) {
@@ -411,10 +420,10 @@ __device__ __forceinline__ void tally(const QueryDev& q, const Hit& h, long long
   v[0] = fx32(h.dx, q.scaleF); v[1] = fx32(h.dy, q.scaleF); v[2] = fx32(h.dz, q.scaleF);
   v[3] = fx32(h.lx, q.scaleL); v[4] = fx32(h.ly, q.scaleL); v[5] = fx32(h.lz, q.scaleL);
   v[6] = 1;
-  if ((MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) && TOT_LDS) {  // the lane's LDS slots [c][lane]
+  if ((MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) && TOT_LDS) {  // the wave's LDS slots [c][wave]
     if (h.valid) {
 #pragma unroll
-      for (int c = 0; c < 7; ++c) atomicAdd(lds + c * kBlock + threadIdx.x, (unsigned long long)v[c]);
+      for (int c = 0; c < 7; ++c) atomicAdd(lds + c * kWaves + (threadIdx.x >> 6), (unsigned long long)v[c]);
     }
   } else if (MODE == kTallyTotals || (MODE == kTallyAuto && !q.per_tri)) {
     if (h.valid) {
@@ -451,20 +460,13 @@ __device__ __forceinline__ void flush_lane_tally(unsigned long long* lds, long l
 }
 
 // Wave-reduce the per-lane accumulators into a query's scalar block.  With
-// TOTALS the query's force and moment totals come from the lane's registers,
-// or, with TOT_LDS, from (and clearing) its LDS slots lane_tot[c][lane] (a
-// compile-time choice, so that the register totals are not kept live across
-// the trace loop of a kernel that never uses them).
+// TOTALS the query's force and moment totals come from the lanes' registers,
+// or, with TOT_LDS, from (and clearing) the wave's LDS slots lane_tot[c][wave]
+// (a compile-time choice, so that the register totals are not kept live
+// across the trace loop of a kernel that never uses them).
 template <bool TOT_LDS = false>
 __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, bool TOTALS,
                                           unsigned long long* lane_tot = nullptr) {
-  if (TOT_LDS && TOTALS) {
-#pragma unroll
-    for (int c = 0; c < 7; ++c) {
-      A.tot[c] = (long long)lane_tot[c * kBlock + threadIdx.x];
-      lane_tot[c * kBlock + threadIdx.x] = 0ull;
-    }
-  }
   // one value at a time, each total moved to scalar registers, so that the
   // flush adds little to the kernel's vector-register peak
   const bool lead = (threadIdx.x & 63) == 0;
@@ -473,19 +475,26 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
   };
   put(wave_sum_uniform(A.sD), kSD);
   put(wave_sum_uniform(A.sD2), kSD2);
-  const long long hits = wave_sum_uniform((long long)A.hits), missed = wave_sum_uniform((long long)A.missed),
-                  escaped = wave_sum_uniform((long long)A.escaped), capped = wave_sum_uniform((long long)A.capped);
-  put(hits, kHits);
-  put(missed, kMissed);
-  put(escaped, kEscaped);
-  put(capped, kCapped);
-  put(missed + escaped + capped, kRays);
-  put(hits + missed + escaped, kSegments);
+  put((long long)A.hits, kHits);
+  put((long long)A.missed, kMissed);
+  put((long long)A.escaped, kEscaped);
+  put((long long)A.capped, kCapped);
+  put((long long)(A.missed + A.escaped + A.capped), kRays);
+  put((long long)(A.hits + A.missed + A.escaped), kSegments);
   put(wave_sum_uniform(A.sE), kSE);
   put(wave_sum_uniform(A.sE2), kSE2);
-  put(wave_sum_uniform((long long)A.tr_capped), kTrCap);
-  put(wave_sum_uniform((long long)A.guard), kGuard);
-  if (TOTALS) {
+  put((long long)A.tr_capped, kTrCap);
+  put((long long)A.guard, kGuard);
+  if (TOTALS && TOT_LDS) {
+    long long t[7];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) t[c] = (long long)lane_tot[c * kWaves + (threadIdx.x >> 6)];
+#pragma unroll
+    for (int c = 0; c < 7; ++c) put(t[c], kFx + c);
+    if (lead)  // after every lane of the wave has read them (one wave: LDS in program order)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) lane_tot[c * kWaves + (threadIdx.x >> 6)] = 0ull;
+  } else if (TOTALS) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) put(wave_sum_uniform(A.tot[c]), kFx + c);
   }
@@ -549,10 +558,9 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
         h.valid = false;
         int out = kOutGoOn;
         int32_t fid = -2;
-        if (fin) {
-          out = finish_segment(a.tris, a.orig, q, L, s, h, fid, A.tr_capped);
-          count_outcome(A, out, h.valid);
-        }
+        bool limited = false;
+        if (fin) out = finish_segment(a.tris, a.orig, q, L, s, h, fid, limited);
+        count_pass(A, fin, out, h.valid, limited);
         tally<MODE, false>(q, h, a.tally, lt, a.nt, A);
         if (fin) {
           if (a.first_tri && fid != -2) a.first_tri[L.pid] = fid;
@@ -572,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
     // nt - 1 steps and nt leaf phases; the bound only keeps a damaged tree
     // from spinning a wave, and every segment it ends is counted.
     if (++guard > max_steps) {
-      if (L.live && s.cur != kDone) ++A.guard;
+      A.guard += lanes(L.live && s.cur != kDone);
       s.cur = kDone;
     }
     if (L.live && seg_traversing(s))
@@ -612,15 +620,26 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
 // path's, so results match it bit for bit.
 // ---------------------------------------------------------------------------
 
+// Seeding in two stages (precull_may_enter) in every instance whose LDS
+// leaves room for the survivor rings (not the 64-slot stack).
+template <int STACK, int MODE>
+constexpr bool kPrecullInstance = STACK <= 32;
+
 template <int STACK, int MODE>
 __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   constexpr bool kMayLds = MODE == kTallyLds || MODE == kTallyAuto;
+  constexpr bool kPre = kPrecullInstance<STACK, MODE>;
   constexpr uint32_t kNone = 0xFFFFFFFFu;
+  constexpr uint32_t kRing = 128;  // survivors of the estimate awaiting exact seeding (< 64 + 64)
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
-  __shared__ uint8_t qlane[kBlock / 64][64];  // queue slot -> particle offset in its seeding batch
+  // queue slot -> particle: its offset in its seeding batch, or (two-stage
+  // seeding) in the tile
+  __shared__ uint8_t qlane[kPre ? 1 : kBlock / 64][64];
+  __shared__ uint16_t qoff[kPre ? kBlock / 64 : 1][64];
+  __shared__ uint16_t ring[kPre ? kBlock / 64 : 1][kPre ? kRing : 1];  // survivor offsets in the tile
   extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
-  // per-lane totals [c][lane]: the start of lt, or after the per-triangle area in the mixed mode
+  // per-wave totals [c][wave]: the start of lt, or after the per-triangle area in the mixed mode
   unsigned long long* const lane_tot = MODE == kTallyAuto ? lt + 7u * a.lds_tris : lt;
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
@@ -630,10 +649,17 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
   Acc A;
   acc_zero(A);
+  // two-stage seeding, wave-uniform: particles the estimate removed (for the
+  // held query), and the estimate's yield so far on it.  A wave that finds
+  // more than 60 % of a query's particles surviving the estimate switches it
+  // off for the query (its kPrecullOff slot, read at every tile), since the
+  // estimate then costs more than it saves.
+  uint64_t pre = 0;
+  uint32_t pc_seen = 0, pc_kept = 0;
   if (MODE == kTallyLane)
     for (int c = 0; c < 2 * 7; ++c) lt[c * kBlock + threadIdx.x] = 0ull;
-  if (MODE == kTallyTotals || (MODE == kTallyAuto && a.lane_totals))
-    for (int c = 0; c < 7; ++c) lane_tot[c * kBlock + threadIdx.x] = 0ull;
+  if ((MODE == kTallyTotals || (MODE == kTallyAuto && a.lane_totals)) && threadIdx.x < 7u * kWaves)
+    lane_tot[threadIdx.x] = 0ull;
   for (;;) {
     if (threadIdx.x == 0) {
       // claim a tile: current entry first, then the following ones (bounded scan)
@@ -665,6 +691,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri), lane_tot);
       if (MODE == kTallyLane) flush_lane_tally(lt, htally, qh.nt);
       acc_zero(A);
+      if (kPre) {
+        if (lane == 0 && pre != 0) atomic_add_i64(a.scal_base + qh.scalar_offset + kPreculled, (long long)pre);
+        pre = 0;
+        pc_seen = pc_kept = 0;
+      }
       if (kMayLds && qh.per_tri && qh.nt <= (uint32_t)kLdsTallyMaxTris)
         for (uint32_t i = threadIdx.x; i < qh.nt * 7u; i += kBlock)
           if (lt[i]) atomic_add_i64(htally + i, (long long)lt[i]);
@@ -699,6 +730,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
     uint64_t q_pid0 = 0;               // particle id of queue slot 0
+    uint32_t s_head = 0, s_count = 0;  // wave-uniform survivor ring state (two-stage seeding)
+    bool pc_on = true, pc_off_now = false;  // wave-uniform
+    if (kPre)
+      pc_on = __builtin_amdgcn_readfirstlane((uint32_t)__hip_atomic_load(
+                  a.scal_base + q.scalar_offset + kPrecullOff, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) == 0u;
     for (;;) {
       uint32_t ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
       if (ntrav < a.refill && ballot(L.live && s.p0 >= 0) != 0ull) {
@@ -714,10 +750,9 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           h.valid = false;
           int out = kOutGoOn;
           int32_t fid;
-          if (fin) {
-            out = finish_segment(tris, orig, q, L, s, h, fid, A.tr_capped);
-            count_outcome(A, out, h.valid);
-          }
+          bool limited = false;
+          if (fin) out = finish_segment(tris, orig, q, L, s, h, fid, limited);
+          count_pass(A, fin, out, h.valid, limited);
           if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
           else tally<MODE>(q, h, qtally, lane_tot, q.nt, A);
           if (fin) {
@@ -730,7 +765,73 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           }
         }
         const uint64_t dead = ballot(!L.live);
-        if (dead != 0ull) {
+        if (kPre && dead != 0ull) {
+          while (q_count == 0 && !(exhausted && s_count == 0)) {  // wave-uniform
+            if (s_count < 64 && !exhausted) {
+              // stage 1: claim 64 particles, keep those the estimate cannot rule out
+              unsigned long long base = 0;
+              if (lane == 0) base = atomicAdd(&next_sh, 64ull);
+              base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
+                     ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
+              if (base >= p_end) {
+                exhausted = true;
+              } else {
+                const uint64_t pid = base + lane;
+                const bool valid = pid < p_end;
+                bool maybe = valid;
+                if (valid && pc_on) maybe = precull_may_enter(q, g_lat_start, g_vn_start, nodes, pid);
+                const uint64_t mb = ballot(maybe);
+                if (maybe) ring[wave][(s_head + s_count + (uint32_t)__popcll(mb & lt_mask)) & (kRing - 1)] =
+                    (uint16_t)(pid - p_begin);
+                const uint32_t nvalid = (uint32_t)__popcll(ballot(valid)), nmaybe = (uint32_t)__popcll(mb);
+                s_count += nmaybe;
+                pre += nvalid - nmaybe;
+                A.missed += nvalid - nmaybe;
+                pc_seen += nvalid;
+                pc_kept += nmaybe;
+                if (pc_on && pc_seen >= 256u && 5u * pc_kept > 3u * pc_seen) {
+                  pc_on = false;
+                  pc_off_now = true;
+                }
+                __builtin_amdgcn_wave_barrier();
+              }
+            } else {
+            // stage 2: exact seeding of up to 64 survivors, one per lane; the
+            // exact root test as in the one-stage seeding below
+            const uint32_t n = s_count < 64u ? s_count : 64u;
+            bool keep = false;
+            float xs[3], ws[3];
+            if ((uint32_t)lane < n) {
+              double x[3], w[3];
+              seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab,
+                            p_begin + ring[wave][(s_head + lane) & (kRing - 1)], x, w);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                xs[c] = (float)x[c];
+                ws[c] = (float)w[c];
+              }
+              keep = STACK <= 4 || ray_enters_root(nodes, xs, ws);
+            }
+            A.missed += lanes((uint32_t)lane < n && !keep);
+            const uint64_t kb = ballot(keep);
+            if (keep) {
+              const uint32_t slot = (uint32_t)__popcll(kb & lt_mask);
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                qbuf[wave][c][slot] = xs[c];
+                qbuf[wave][3 + c][slot] = ws[c];
+              }
+              qoff[wave][slot] = ring[wave][(s_head + lane) & (kRing - 1)];  // read again: not held across the seeding
+            }
+            s_head += n;
+            s_count -= n;
+            q_count = (uint32_t)__popcll(kb);
+            q_head = 0;
+            __builtin_amdgcn_wave_barrier();
+            }
+          }
+        }
+        if (!kPre && dead != 0ull) {
           while (q_count == 0 && !exhausted) {  // wave-uniform
             // claim and seed the next (up to) 64 particles, one per lane
             unsigned long long base = 0;
@@ -758,8 +859,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
                   ws[c] = (float)w[c];
                 }
                 keep = STACK <= 4 || ray_enters_root(nodes, xs, ws);
-                if (!keep) count_outcome(A, kOutMissed, false);
               }
+              A.missed += lanes(pid < p_end && !keep);
               const uint64_t kb = ballot(keep);
               if (keep) {
                 const uint32_t slot = (uint32_t)__popcll(kb & lt_mask);
@@ -776,6 +877,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               __builtin_amdgcn_wave_barrier();
             }
           }
+        }
+        if (dead != 0ull) {
           if (q_count > 0) {
             // dead lanes take queue entries in lane order
             const uint32_t rank = __popcll(dead & lt_mask);
@@ -783,7 +886,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               const uint32_t slot = q_head + rank;
               L.ox = qbuf[wave][0][slot]; L.oy = qbuf[wave][1][slot]; L.oz = qbuf[wave][2][slot];
               L.wx = qbuf[wave][3][slot]; L.wy = qbuf[wave][4][slot]; L.wz = qbuf[wave][5][slot];
-              L.pid = q_pid0 + qlane[wave][slot];
+              L.pid = kPre ? p_begin + qoff[wave][slot] : q_pid0 + qlane[wave][slot];
               L.D = 0.0f;
               L.E = 0.0f;
               L.prev = -1;
@@ -800,13 +903,13 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         }
         // nothing in flight and nothing left: the tile is done (with no lane
         // live but particles left, the next iteration claims more)
-        if (ballot(L.live) == 0ull && exhausted && q_count == 0) break;
+        if (ballot(L.live) == 0ull && exhausted && q_count == 0 && s_count == 0) break;
         make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
         guard = 0;
       }
       // as in the plain path: a bound only against a damaged tree, counted
       if (++guard > max_steps) {
-        if (L.live && s.cur != kDone) ++A.guard;
+        A.guard += lanes(L.live && s.cur != kDone);
         s.cur = kDone;
       }
       if (L.live && seg_traversing(s)) {
@@ -814,6 +917,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
       }
     }
+    if (kPre && pc_off_now && lane == 0)  // published at the tile's end, outside the trace loop
+      __hip_atomic_store(a.scal_base + q.scalar_offset + kPrecullOff, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();  // every wave is done with the tile; tile_sh / entry_sh / next_sh may be reused
   }
 }
@@ -907,6 +1012,7 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
   r.capped = (uint64_t)s[kCapped];
   r.tr_capped = (uint64_t)s[kTrCap];
   r.guard_trips = (uint64_t)s[kGuard];
+  r.preculled = (uint64_t)s[kPreculled];
   out[i] = r;
 }
 
@@ -917,10 +1023,10 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
 size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent, bool lane_totals = false) {
   switch (mode) {
     case kTallyLds: return (size_t)lds_tris * 7 * sizeof(unsigned long long);
-    case kTallyAuto:  // per-triangle area, then (persistent, if any entry keeps totals only) the per-lane totals
-      return ((size_t)lds_tris * 7 + (persistent && lane_totals ? (size_t)7 * kBlock : 0)) * sizeof(unsigned long long);
+    case kTallyAuto:  // per-triangle area, then (persistent, if any entry keeps totals only) the per-wave totals
+      return ((size_t)lds_tris * 7 + (persistent && lane_totals ? (size_t)7 * kWaves : 0)) * sizeof(unsigned long long);
     case kTallyLane: return (size_t)2 * 7 * kBlock * sizeof(unsigned long long);
-    case kTallyTotals: return persistent ? (size_t)7 * kBlock * sizeof(unsigned long long) : 0;
+    case kTallyTotals: return persistent ? (size_t)7 * kWaves * sizeof(unsigned long long) : 0;
     default: return 0;
   }
 }
@@ -978,6 +1084,44 @@ void launch_admit(const AdmitRec* rec, uint32_t n, uint64_t max_words, QueryDev*
   const uint64_t gx = (max_words + kBlock - 1) / kBlock;
   const dim3 g((uint32_t)(gx < 1 ? 1 : (gx > 1024 ? 1024 : gx)), n);
   admit_kernel<<<g, kBlock, 0, st>>>(rec, qs, scal, tally);
+}
+
+// Check of the two-stage seeding's estimate: over particles [0, n) of one
+// query, the largest distance between the estimated and the exact ray as a
+// fraction of the margin (out[0], the bits of a non-negative double: they
+// order as integers), and the number of particles the estimate covered
+// (out[1]).  Distance = |o_est - o| + 2 r |w_est / |w_est| - w / |w||: how
+// far apart the two rays can get along the at most 2 r of path in the CV.
+__global__ __launch_bounds__(kBlock) void precull_check_kernel(const QueryDev* __restrict__ qp, uint64_t n,
+                                                               unsigned long long* __restrict__ out) {
+  const QueryDev& q = *qp;
+  double worst = 0.0;
+  unsigned long long cnt = 0;
+  for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < n; pid += (uint64_t)gridDim.x * kBlock) {
+    float o[3], w[3];
+    if (!precull_estimate(q, g_lat_start, g_vn_start, pid, o, w)) continue;
+    double x[3], we[3];
+    seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, pid, x, we);
+    double dp = 0.0, nw = 0.0, ne = 0.0, dd = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      dp += ((double)o[c] - x[c]) * ((double)o[c] - x[c]);
+      nw += (double)w[c] * (double)w[c];
+      ne += we[c] * we[c];
+    }
+    nw = sqrt(nw);
+    ne = sqrt(ne);
+    for (int c = 0; c < 3; ++c) dd += ((double)w[c] / nw - we[c] / ne) * ((double)w[c] / nw - we[c] / ne);
+    const double ratio = (sqrt(dp) + 2.0 * q.r * sqrt(dd)) / ((double)kPrecullMargin * q.r);
+    worst = ratio == ratio ? fmax(worst, ratio) : __builtin_inf();  // a NaN estimate counts as unbounded
+    ++cnt;
+  }
+  atomicMax(out, (unsigned long long)__double_as_longlong(worst));
+  atomicAdd(out + 1, cnt);
+}
+
+void launch_precull_check(const QueryDev* d_q, uint64_t n, unsigned long long* out, int grid, hipStream_t st) {
+  zero_i64_kernel<<<1, kBlock, 0, st>>>(reinterpret_cast<long long*>(out), 2);
+  precull_check_kernel<<<grid, kBlock, 0, st>>>(d_q, n, out);
 }
 
 hipError_t init_seed_tables(hipStream_t st) {

@@ -79,6 +79,9 @@ void launch_finalize(const QueryDev* d_qs, const uint32_t* d_idx, const long lon
 void launch_reduce_slots(const QueryDev* d_qs, const uint32_t* d_idx, uint32_t n, long long* tally_base,
                          long long* scal_base, uint32_t max_nt, hipStream_t st);
 void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid, hipStream_t st);
+// Check of the two-stage seeding's estimate (precull_check_kernel): out[0] the
+// bits of the largest error / margin, out[1] the particles estimated.
+void launch_precull_check(const QueryDev* d_q, uint64_t n, unsigned long long* out, int grid, hipStream_t st);
 // Serving admission: n records (device) -> constants into qs[slot], cleared
 // scalar block and per-triangle tally words; max_words is the largest tally.
 void launch_admit(const AdmitRec* rec, uint32_t n, uint64_t max_words, QueryDev* qs, long long* scal,

@@ -46,7 +46,8 @@ class Result(ctypes.Structure):
                 ("rays", ctypes.c_uint64), ("hits", ctypes.c_uint64), ("segments", ctypes.c_uint64),
                 ("missed", ctypes.c_uint64), ("escaped", ctypes.c_uint64), ("capped", ctypes.c_uint64),
                 ("Qhat", ctypes.c_double), ("CH", ctypes.c_double), ("CH_sigma", ctypes.c_double),
-                ("Mhat", ctypes.c_double * 3), ("tr_capped", ctypes.c_uint64), ("guard_trips", ctypes.c_uint64)]
+                ("Mhat", ctypes.c_double * 3), ("tr_capped", ctypes.c_uint64), ("guard_trips", ctypes.c_uint64),
+                ("preculled", ctypes.c_uint64)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -117,13 +118,14 @@ _SIGS = {
     "tpmc_ceiling_read": ([_vp, _vp, _u64, _u32, _dp], ctypes.c_int),
     "tpmc_ceiling_atomic": ([_vp, _vp, _u32, _u32, _dp], ctypes.c_int),
     "tpmc_ceiling_lds_atomic": ([_vp, _vp, _u32, _u32, _dp], ctypes.c_int),
+    "tpmc_precull_check": ([_vp, _vp, _QP, _vp, _u64, _dp, ctypes.POINTER(_u64)], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = _res
 
-ABI_VERSION = 7  # the structures below are laid out for this version of include/tpmc.h
+ABI_VERSION = 8  # the structures below are laid out for this version of include/tpmc.h
 if _lib.tpmc_abi_version() != ABI_VERSION:
     raise ImportError(f"libtpmc.so has ABI version {_lib.tpmc_abi_version()}, this binding expects "
                       f"{ABI_VERSION}: rebuild the library (python -c 'import __graft_entry__ as g; g.build()')")
@@ -152,6 +154,15 @@ def _queries(qds) -> ctypes.Array:
     for i, qd in enumerate(qds):
         arr[i] = make_query(qd)
     return arr
+
+
+WORK_COUNTS = ("preculled",)  # result fields that count work done, which differs between paths
+
+
+def same_on_every_path(result: dict) -> list:
+    """The fields of a result dict that every path (plain, batched, served,
+    any tuning) reproduces bit for bit: all but the work counts."""
+    return [k for k in result if k not in WORK_COUNTS]
 
 
 def result_dict(r: Result) -> dict:
@@ -292,6 +303,19 @@ class Mesh:
         self.info = {f: (list(getattr(info, f)) if isinstance(getattr(info, f), ctypes.Array) else getattr(info, f))
                      for f, _ in MeshInfo._fields_}
         self.nt = int(info.nt)
+
+    def precull_check(self, query: dict):
+        """Largest error of the batched path's seeding estimate over the query's
+        particles, as a fraction of its margin, and the number of particles it
+        covered (tpmc_precull_check)."""
+        PRECULL_CHECK_BYTES = 1024
+        buf, ptr, nb = _workspace(PRECULL_CHECK_BYTES, self.ctx.device)
+        q = make_query(query)
+        worst, n = ctypes.c_double(), _u64()
+        _check(_lib.tpmc_precull_check(self.ctx._h, self._h, ctypes.byref(q), _vp(ptr), nb, ctypes.byref(worst),
+                                       ctypes.byref(n)))
+        del buf
+        return worst.value, int(n.value)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -33,7 +33,7 @@ def test_every_declared_symbol_is_exported(T):
     lib = ctypes.CDLL(T.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.tpmc_abi_version() == T.ABI_VERSION == 7
+    assert lib.tpmc_abi_version() == T.ABI_VERSION == 8
 
 
 def _c_layout(struct: str, fields) -> list:
