@@ -17,9 +17,13 @@ one-query-per-launch path (seed -> trace -> forces, host sync per query) with
 p50 / p99 query latency; C_D error of every case against the per-facet closed
 form; the concave satellite (~50k triangles, 1e8 particles, one query) and the
 1024-attitude sweep on it (one graph-replayed launch against the plain path);
-and the CPU oracle on bounded samples (all usable host threads and one).
+the served stream (continuous batching over four resident satellite meshes:
+saturation throughput, p50 / p99 latency at 0.8 of it -- the line's
+query_ms_p50 / p99 -- and the FIFO plain path); and the CPU oracle on bounded
+samples (all usable host threads and one).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-satellite]
+                    [--no-served]
 """
 from __future__ import annotations
 
@@ -154,8 +158,9 @@ def launch_record(kernel, ms, results, V_seg, T_seg):
     pre = sum(r.get("preculled", 0) for r in results)
     ops = ((particles - pre) * OPS_SEED + pre * OPS_PRECULL + segments * (V_seg * OPS_NODE + T_seg * OPS_TRI)
            - pre * OPS_NODE + hits * OPS_HIT)
-    inst = kernel.split(" ")[0]
-    traffic = stored_traffic(inst)
+    import re
+    m = re.match(r"batch_kernel<[^>]*>", kernel)
+    traffic = stored_traffic(m.group(0)) if m else None
     return {"kernel": kernel, "ms": ms, "achieved_tlane_ops": ops / (ms / 1e3) / 1e12, "hbm_bytes": traffic,
             "frac": ops / (ms / 1e3) / ALU_PEAK,
             "work": {"particles": particles, "preculled": pre, "segments": segments, "hits": hits,
@@ -938,6 +943,16 @@ def served_requests(n_req):
 
 
 def workload_served(args):
+    """The served stream as its own benchmark line (section text in served_measure)."""
+    d = served_measure(args, int(args.warm), int(args.requests),
+                       [float(f) for f in args.served_loads.split(",") if f.strip()], int(args.fifo_requests))
+    sat = d["saturation"]
+    _line("particle-surface hits/sec on 1 MI355X (served stream); p50/p99 query ms", sat["hits_per_s"], "hits/s",
+          d["n_meas"] / sat["req_per_s"], 1, d["n_warm"], d.pop("config"),
+          {k: v for k, v in d.items() if k not in ("n_warm", "n_meas")})
+
+
+def served_measure(args, n_warm, n_meas, load_fracs, fifo_requests):
     """Served stream: Poisson arrivals over four resident satellite meshes (~1k, 20k, 100k,
     500k triangles), random attitudes, S ~ U[2, 10], N log-uniform in [1e5, 1e7], alpha = 0.9,
     per-request per-triangle tallies admitted against an HBM budget.  Saturation throughput
@@ -952,17 +967,19 @@ def workload_served(args):
     from paper_1312_3691_amd import tpmc
     from paper_1312_3691_amd.serve import GpuExecutor, Scheduler
     ctx = tpmc.Context(0)
-    n_warm, n_meas = int(args.warm), int(args.requests)
     n_req = n_warm + n_meas
     sizes, reqs, rng = served_requests(n_req)
     meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i), builder=args.bvh) for i, (k, v) in enumerate(sizes.items())}
     max_slots = int(args.slots)
     pool_words = int(args.hbm_budget_gb * 2 ** 30) // 8
-    # tiles of 32768 particles: the tuner, timing one batch, cannot see the per-step costs of
-    # claiming tiles (smaller tiles) and of the last tiles of a step (larger ones); measured on
-    # the pipelined stream, 16384 / 32768 / 65536 gave 3600 / 3854 / 3669 req/s
+    # tiles of 32768 particles and a refill threshold of 32 lanes: the tuner, timing one batch,
+    # cannot see the per-step costs of claiming tiles (smaller tiles) and of the last tiles of a
+    # step (larger ones), nor how a step's mix of meshes shares the waves.  Measured on the
+    # pipelined stream (1000 requests): tiles 16384 / 32768 / 65536 gave 3600 / 3854 / 3669 req/s
+    # (one-stage seeding); refill 16 / 24 / 32 / 40 / 48 lanes gave 4091 / 4135 / 4171 / 4069 /
+    # 3815 req/s, workgroups per CU 4 / 8 / 16 at refill 32 gave 4171 / 4176 / 4163.
     tuning = tune_for(args, meshes["sat100k"], [q for m, q in reqs if m == "sat100k"][:64],
-                      hold={"tile_particles": 32768})
+                      hold={"tile_particles": 32768, "refill_lanes": 32})
     # the step budget is a particle count, so that the tuned tile size does not change it
     tiles_per_step = max(1, int(args.particles_per_step) // int(tuning["tile_particles"]))
     ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=pool_words)
@@ -1007,7 +1024,7 @@ def workload_served(args):
     res, sat = run(0)
     sat_rate = sat["req_per_s"]
     loads = {}
-    for frac in [float(f) for f in args.served_loads.split(",") if f.strip()]:
+    for frac in load_fracs:
         log(f"served: load {frac}")
         _, st = run(frac * sat_rate)
         loads[str(frac)] = dict(st, offered_req_per_s=frac * sat_rate)
@@ -1015,7 +1032,7 @@ def workload_served(args):
     # times measured; latencies for the 0.8 load's arrival process by a single-server queue
     log("served: FIFO plain path")
     service = []
-    for mesh, q in reqs[:n_warm + min(n_meas, int(args.fifo_requests))]:
+    for mesh, q in reqs[:n_warm + min(n_meas, fifo_requests)]:
         t0 = time.perf_counter()
         r, pr = tpmc.run(meshes[mesh], [q])
         service.append(time.perf_counter() - t0)
@@ -1038,18 +1055,22 @@ def workload_served(args):
                                                     for k in tpmc.same_on_every_path(solo[0]))
         pr.close()
     torch.cuda.synchronize()
-    _line("particle-surface hits/sec on 1 MI355X (served stream); p50/p99 query ms", sat["hits_per_s"], "hits/s",
-          n_meas / sat_rate, 1, n_warm,
-          {"workload": f"{n_warm} + {n_meas} requests over satellites {list(sizes.values())} tris, N log-uniform "
-                       f"1e5-1e7, S~U[2,10], alpha=0.9, per-triangle tallies", "slots": max_slots,
-           "hbm_budget_gb": args.hbm_budget_gb, "path": "continuous batching, one persistent launch per step",
-           "particles_per_step": int(args.particles_per_step), "tiles_per_step": tiles_per_step, "bvh": args.bvh},
-          {"saturation": sat, "loads": loads, "query_ms_p50": loads.get("0.8", {}).get("p50_ms"),
+    out = {"config": {"workload": f"{n_warm} + {n_meas} requests over satellites {list(sizes.values())} tris, "
+                                  f"N log-uniform 1e5-1e7, S~U[2,10], alpha=0.9, per-triangle tallies",
+                      "slots": max_slots, "hbm_budget_gb": args.hbm_budget_gb,
+                      "path": "continuous batching, one persistent launch per step",
+                      "particles_per_step": int(args.particles_per_step), "tiles_per_step": tiles_per_step,
+                      "bvh": args.bvh},
+           "n_warm": n_warm, "n_meas": n_meas,
+           "saturation": sat, "loads": loads, "query_ms_p50": loads.get("0.8", {}).get("p50_ms"),
            "query_ms_p99": loads.get("0.8", {}).get("p99_ms"), "fifo_plain_path": fifo,
            "served_over_fifo": sat_rate / fifo["capacity_req_per_s"], "served_equals_solo": bool(same),
            "meshes": {k: {"nt": m.nt, "depth": m.info["depth"], "stack_slots": m.info["stack_slots"]}
                       for k, m in meshes.items()},
-           "tuning": tuning})
+           "tuning": tuning}
+    for m in meshes.values():
+        m.close()
+    return out
 
 
 def main():
@@ -1066,6 +1087,9 @@ def main():
     ap.add_argument("--pilot-particles", type=float, default=1e6, help="particles per case of the N pilot")
     ap.add_argument("--no-satellite", action="store_true",
                     help="leave out the concave-satellite and attitude-sweep configurations")
+    ap.add_argument("--no-served", action="store_true",
+                    help="leave out the served stream (run by default with 100 + 1000 requests, the 0.8 load, "
+                         "300 FIFO requests)")
     ap.add_argument("--copy-calibration", action="store_true", help="run only the HBM-counter calibration copies")
     ap.add_argument("--summarize-traffic", metavar="PMC_DIR", help="write profiles/traffic.json from counter runs")
     ap.add_argument("--summarize-counters", metavar="PMC_DIR",
@@ -1240,6 +1264,12 @@ def main():
         sweep = config_sweep(ctx, args, measured, sat["mesh"])
         sat.pop("mesh")
 
+    served = None
+    if not args.no_served:
+        log("served stream")
+        served = served_measure(args, 100, 1000, [0.8], 300)
+        served.update(served.pop("config"))
+
     cpu = None
     if not args.no_cpu:
         log("cpu baseline")
@@ -1258,14 +1288,16 @@ def main():
                                               f"{args.pilot_particles:g}-particle pilot)"),
                        "particles_per_case_min_max": [min(n_case), max(n_case)],
                        "path": "batched persistent launch per mesh, HIP graph replay", "bvh": args.bvh},
-            "query_ms_p50": plain["query_ms_p50"] if plain else None,
-            "query_ms_p99": plain["query_ms_p99"] if plain else None,
+            # query latency: the served stream's at 0.8 of its saturation throughput (the plate +
+            # cylinder queries' own, one per launch on the plain path, are in plain_path)
+            "query_ms_p50": served["query_ms_p50"] if served else None,
+            "query_ms_p99": served["query_ms_p99"] if served else None,
             "segments_per_s": segments / dt, "particles_per_s": particles / dt,
             "accuracy": accuracy, "plain_path": plain,
             "batched_over_plain": (hits / dt) / plain["hits_per_s"] if plain else None,
             "tuning": tunings, "bvh_build_ms": build_ms,
             "roofline": roofline,
-            "configs": {"concave_satellite": sat, "attitude_sweep": sweep},
+            "configs": {"concave_satellite": sat, "attitude_sweep": sweep, "served_stream": served},
             "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
