@@ -31,7 +31,8 @@ def _metadata():
     for m in re.finditer(r"\.name:\s+(\S+)\n(.*?)(?=\n  - \.|\Z)", text, re.S):
         body = m.group(2)
         get = lambda k: int((re.search(r"\." + k + r":\s+(\d+)", body) or [0, 0])[1])
-        meta[m.group(1)] = {"vgpr": get("vgpr_count"), "spill": get("vgpr_spill_count")}
+        meta[m.group(1)] = {"vgpr": get("vgpr_count"), "spill": get("vgpr_spill_count"),
+                            "lds": get("group_segment_fixed_size")}
     return meta
 
 
@@ -45,3 +46,22 @@ def test_batch_kernel_fits_four_waves_per_simd():
     assert len(inst) == 20, sorted(inst)
     for k, v in inst.items():
         assert v["vgpr"] <= 128 and v["spill"] == 0, (k, v)
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                    reason="hipcc not available")
+def test_batch_kernel_lds_fits_four_workgroups_per_cu():
+    """Four workgroups of four waves fill a CU's 160 KB of LDS at 40 KB each: the
+    static LDS (stack, seeding queue, survivor rings) plus the tallies sized at
+    launch must fit that for the benchmark's instances -- the plate (2 triangles,
+    per-lane tallies), the cylinder (256 triangles, workgroup tallies), the
+    satellite (global atomics) and the attitude sweep (per-wave totals)."""
+    meta = _metadata()
+    lds = {}
+    for k, v in meta.items():
+        m = re.search(r"batch_kernelILi(\d+)ELi(\d+)E", k)
+        if m:
+            lds[(int(m.group(1)), int(m.group(2)))] = v["lds"]
+    dynamic = {(4, 2): 2 * 7 * 256 * 8, (16, 1): 256 * 7 * 8, (32, 0): 0, (32, 3): 7 * 4 * 8}
+    for key, dyn in dynamic.items():
+        assert lds[key] + dyn <= 160 * 1024 // 4, (key, lds[key], dyn)
