@@ -933,7 +933,7 @@ static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   zero_i64(reinterpret_cast<long long*>(b->lay.next), b->nq, st);
   zero_i64(b->lay.scal, (uint64_t)b->nq * kScalarSlots, st);
   zero_i64(b->lay.tally, b->tally_words, st);
-  BatchArgs a;
+  BatchArgs a{};
   a.qs = b->lay.qs;
   a.entry_query = nullptr;
   a.entry_tile0 = nullptr;
@@ -1242,15 +1242,36 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   if (acc == 0) return TPMC_OK;
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t st = s->ctx->stream;
-  // one packed upload: tile0 [n] u64, tiles [n] u64, slot [n] u32
+  // one packed upload: tile0 [n] u64, tiles [n] u64, slot [n] u32, the entries
+  // grouped by mesh (largest first; the order changes no result), and where
+  // each XCD's workgroups start: XCD x at the entry holding tile x * acc / 8
+  std::vector<uint32_t> ord(n);
+  for (uint32_t i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](uint32_t x, uint32_t y) {
+    return s->mesh_of[slots[x]]->nt > s->mesh_of[slots[y]]->nt;
+  });
   std::vector<uint8_t> pk(20ull * n);
-  std::memcpy(pk.data(), tile0, 8ull * n);
-  std::memcpy(pk.data() + 8ull * n, count, 8ull * n);
-  std::memcpy(pk.data() + 16ull * n, slots, 4ull * n);
+  uint32_t xs[9];
+  {
+    uint64_t c = 0;
+    uint32_t x = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+      std::memcpy(pk.data() + 8ull * i, tile0 + ord[i], 8);
+      std::memcpy(pk.data() + 8ull * n + 8ull * i, count + ord[i], 8);
+      std::memcpy(pk.data() + 16ull * n + 4ull * i, slots + ord[i], 4);
+      while (x < 8 && c >= x * acc / 8) xs[x++] = i;
+      c += count[ord[i]];
+    }
+    while (x < 9) xs[x++] = n;
+    for (int k = 0; k < 8; ++k)
+      if (xs[k] >= n) xs[k] = n - 1;
+    for (int k = 1; k < 8; ++k)
+      if (xs[k] < xs[k - 1]) xs[k] = xs[k - 1];
+  }
   tpmc_status ust = server_upload(s, s->entries, pk.data(), pk.size());
   if (ust != TPMC_OK) return ust;
   zero_i64(reinterpret_cast<long long*>(s->e_next), n, st);
-  BatchArgs a;
+  BatchArgs a{};
   a.qs = s->qs;
   a.entry_tile0 = reinterpret_cast<const uint64_t*>(s->entries);
   a.entry_tiles = reinterpret_cast<const uint64_t*>(s->entries + 8ull * n);
@@ -1266,6 +1287,7 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   const TallyMode mode = !any_tri ? kTallyTotals : (!any_totals && lds_tris == 0 ? kTallyGlobal : kTallyAuto);
   a.lds_tris = mode == kTallyAuto ? lds_tris : 0u;
   a.lane_totals = any_totals ? 1u : 0u;
+  for (int k = 0; k < 9; ++k) a.xcd_start[k] = xs[k];
   launch_batch(a, stack, mode, s->ctx->n_cu * (int)s->ctx->tune.groups_per_cu, st);
   HIP_CHECK_LAUNCH("server step");
   return TPMC_OK;

@@ -333,6 +333,11 @@ __device__ __forceinline__ void acc_zero(Acc& A) {
 
 __device__ __forceinline__ uint64_t lanes(bool p) { return (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(p)); }
 
+// Set bits of a wave mask below the calling lane (v_mbcnt; no per-lane mask kept live).
+__device__ __forceinline__ uint32_t below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Outcome of a finished segment.  kOutHitLeft: a hit whose outgoing segment
 // cannot hit anything (the mesh lies on the other side of the triangle's
 // plane), so that segment is counted and the particle escapes untraced.
@@ -644,8 +649,11 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint64_t lt_mask = (1ull << lane) - 1ull;
-  uint32_t scan = blockIdx.x % a.n_entries;  // thread 0's position in the entry list
+  uint32_t scan;  // thread 0's position in the entry list
+  {
+    const uint32_t x = blockIdx.x & 7u, lo = a.xcd_start[x], hi = a.xcd_start[x + 1];
+    scan = a.xcd_start[8] == 0u ? blockIdx.x % a.n_entries : (hi > lo ? lo + (blockIdx.x >> 3) % (hi - lo) : lo);
+  }
   uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
   Acc A;
   acc_zero(A);
@@ -781,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
                 bool maybe = valid;
                 if (valid && pc_on) maybe = precull_may_enter(q, g_lat_start, g_vn_start, nodes, pid);
                 const uint64_t mb = ballot(maybe);
-                if (maybe) ring[wave][(s_head + s_count + (uint32_t)__popcll(mb & lt_mask)) & (kRing - 1)] =
+                if (maybe) ring[wave][(s_head + s_count + below(mb)) & (kRing - 1)] =
                     (uint16_t)(pid - p_begin);
                 const uint32_t nvalid = (uint32_t)__popcll(ballot(valid)), nmaybe = (uint32_t)__popcll(mb);
                 s_count += nmaybe;
@@ -815,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             A.missed += lanes((uint32_t)lane < n && !keep);
             const uint64_t kb = ballot(keep);
             if (keep) {
-              const uint32_t slot = (uint32_t)__popcll(kb & lt_mask);
+              const uint32_t slot = below(kb);
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
                 qbuf[wave][c][slot] = xs[c];
@@ -863,7 +871,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               A.missed += lanes(pid < p_end && !keep);
               const uint64_t kb = ballot(keep);
               if (keep) {
-                const uint32_t slot = (uint32_t)__popcll(kb & lt_mask);
+                const uint32_t slot = below(kb);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                   qbuf[wave][c][slot] = xs[c];
@@ -881,7 +889,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         if (dead != 0ull) {
           if (q_count > 0) {
             // dead lanes take queue entries in lane order
-            const uint32_t rank = __popcll(dead & lt_mask);
+            const uint32_t rank = below(dead);
             if (!L.live && rank < q_count) {
               const uint32_t slot = q_head + rank;
               L.ox = qbuf[wave][0][slot]; L.oy = qbuf[wave][1][slot]; L.oz = qbuf[wave][2][slot];

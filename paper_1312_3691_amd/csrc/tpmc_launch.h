@@ -49,6 +49,12 @@ struct BatchArgs {
   uint64_t tile;                   // particles per tile (multiple of 64)
   uint32_t lds_tris;               // largest nt of an entry with an LDS tally (kTallyLds / kTallyAuto)
   uint32_t lane_totals;            // kTallyAuto: some entry keeps totals only (per-lane LDS totals allocated)
+  // Where each XCD's workgroups start claiming: XCD x (workgroups x, x + 8, ...; the
+  // hardware deals workgroups to the eight XCDs in turn) starts in entries
+  // [xcd_start[x], xcd_start[x + 1]) (entries grouped by mesh, ranges by tile share),
+  // so that each XCD's L2 holds the hierarchies of few meshes; all 0: entry
+  // blockIdx % n_entries.
+  uint32_t xcd_start[9];
 };
 
 void zero_i64(long long* p, uint64_t n, hipStream_t st);
