@@ -1048,6 +1048,20 @@ def served_measure(args, n_warm, n_meas, load_fracs, fifo_requests):
             "requests": int(len(service)),
             "p50_ms_at_0.8_of_served_saturation": float(np.percentile(lat, 50)),
             "p99_ms_at_0.8_of_served_saturation": float(np.percentile(lat, 99))}
+    # where a step's time goes, by mesh: the stream's first 16 requests on each mesh, 2e6
+    # particles each, as one batched launch with the served launch settings
+    per_mesh = {}
+    for name, m in meshes.items():
+        qs = [dict(q, n=2_000_000) for mm, q in reqs if mm == name][:16]
+        b = tpmc.Batch(m, qs)
+        b.launch(use_graph=True)
+        res_m = b.results()
+        ms = launch_ms(ctx, b, ctx.tuning, 3)
+        b.close()
+        n_p = sum(r["rays"] for r in res_m)
+        per_mesh[name] = {"nt": m.nt, "requests": len(qs), "ms": ms, "particles_per_s": n_p / (ms * 1e-3),
+                          "hits_per_s": sum(r["hits"] for r in res_m) / (ms * 1e-3),
+                          "preculled_fraction": sum(r["preculled"] for r in res_m) / n_p}
     # every served result equals its solo run (first 8 requests)
     same = True
     for (mesh, q), r in list(zip(reqs, res))[:8]:
@@ -1066,6 +1080,7 @@ def served_measure(args, n_warm, n_meas, load_fracs, fifo_requests):
            "saturation": sat, "loads": loads, "query_ms_p50": loads.get("0.8", {}).get("p50_ms"),
            "query_ms_p99": loads.get("0.8", {}).get("p99_ms"), "fifo_plain_path": fifo,
            "served_over_fifo": sat_rate / fifo["capacity_req_per_s"], "served_equals_solo": bool(same),
+           "per_mesh_batched": per_mesh,
            "meshes": {k: {"nt": m.nt, "depth": m.info["depth"], "stack_slots": m.info["stack_slots"]}
                       for k, m in meshes.items()},
            "tuning": tuning}
