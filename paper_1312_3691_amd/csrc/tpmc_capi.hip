@@ -945,7 +945,7 @@ static void batch_enqueue(tpmc_batch b, hipStream_t st) {
   a.refill = b->refill;
   a.tile = b->tile;
   a.lds_tris = b->mode == kTallyLds ? (uint32_t)m->nt : 0u;
-  a.lane_totals = b->mode == kTallyTotals ? 1u : 0u;
+  a.wave_totals = b->mode == kTallyTotals ? 1u : 0u;
   launch_batch(a, m->stack_slots, b->mode, b->grid, st);
   if (b->mode != kTallyTotals) launch_reduce_batch(b->lay.qs, b->nq, b->lay.tally, b->lay.scal, (uint32_t)m->nt, st);
 }
@@ -1286,7 +1286,7 @@ extern "C" tpmc_status tpmc_server_step(tpmc_server s, const uint32_t* slots, co
   // waves per SIMD instead of three); every kind gives the same exact sums.
   const TallyMode mode = !any_tri ? kTallyTotals : (!any_totals && lds_tris == 0 ? kTallyGlobal : kTallyAuto);
   a.lds_tris = mode == kTallyAuto ? lds_tris : 0u;
-  a.lane_totals = any_totals ? 1u : 0u;
+  a.wave_totals = any_totals ? 1u : 0u;
   for (int k = 0; k < 9; ++k) a.xcd_start[k] = xs[k];
   launch_batch(a, stack, mode, s->ctx->n_cu * (int)s->ctx->tune.groups_per_cu, st);
   HIP_CHECK_LAUNCH("server step");

@@ -466,12 +466,12 @@ __device__ __forceinline__ void flush_lane_tally(unsigned long long* lds, long l
 
 // Wave-reduce the per-lane accumulators into a query's scalar block.  With
 // TOTALS the query's force and moment totals come from the lanes' registers,
-// or, with TOT_LDS, from (and clearing) the wave's LDS slots lane_tot[c][wave]
+// or, with TOT_LDS, from (and clearing) the wave's LDS slots wave_tot[c][wave]
 // (a compile-time choice, so that the register totals are not kept live
 // across the trace loop of a kernel that never uses them).
 template <bool TOT_LDS = false>
 __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, bool TOTALS,
-                                          unsigned long long* lane_tot = nullptr) {
+                                          unsigned long long* wave_tot = nullptr) {
   // one value at a time, each total moved to scalar registers, so that the
   // flush adds little to the kernel's vector-register peak
   const bool lead = (threadIdx.x & 63) == 0;
@@ -493,12 +493,12 @@ __device__ __forceinline__ void flush_acc(Acc& A, long long* __restrict__ scal, 
   if (TOTALS && TOT_LDS) {
     long long t[7];
 #pragma unroll
-    for (int c = 0; c < 7; ++c) t[c] = (long long)lane_tot[c * kWaves + (threadIdx.x >> 6)];
+    for (int c = 0; c < 7; ++c) t[c] = (long long)wave_tot[c * kWaves + (threadIdx.x >> 6)];
 #pragma unroll
     for (int c = 0; c < 7; ++c) put(t[c], kFx + c);
     if (lead)  // after every lane of the wave has read them (one wave: LDS in program order)
 #pragma unroll
-      for (int c = 0; c < 7; ++c) lane_tot[c * kWaves + (threadIdx.x >> 6)] = 0ull;
+      for (int c = 0; c < 7; ++c) wave_tot[c * kWaves + (threadIdx.x >> 6)] = 0ull;
   } else if (TOTALS) {
 #pragma unroll
     for (int c = 0; c < 7; ++c) put(wave_sum_uniform(A.tot[c]), kFx + c);
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   __shared__ uint16_t ring[kPre ? kBlock / 64 : 1][kPre ? kRing : 1];  // survivor offsets in the tile
   extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
   // per-wave totals [c][wave]: the start of lt, or after the per-triangle area in the mixed mode
-  unsigned long long* const lane_tot = MODE == kTallyAuto ? lt + 7u * a.lds_tris : lt;
+  unsigned long long* const wave_tot = MODE == kTallyAuto ? lt + 7u * a.lds_tris : lt;
   __shared__ unsigned long long tile_sh, next_sh;
   __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -666,8 +666,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   uint32_t pc_seen = 0, pc_kept = 0;
   if (MODE == kTallyLane)
     for (int c = 0; c < 2 * 7; ++c) lt[c * kBlock + threadIdx.x] = 0ull;
-  if ((MODE == kTallyTotals || (MODE == kTallyAuto && a.lane_totals)) && threadIdx.x < 7u * kWaves)
-    lane_tot[threadIdx.x] = 0ull;
+  if ((MODE == kTallyTotals || (MODE == kTallyAuto && a.wave_totals)) && threadIdx.x < 7u * kWaves)
+    wave_tot[threadIdx.x] = 0ull;
   for (;;) {
     if (threadIdx.x == 0) {
       // claim a tile: current entry first, then the following ones (bounded scan)
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       const QueryDev& qh = a.qs[a.entry_query ? a.entry_query[held] : held];
       long long* htally = qh.per_tri ? a.tally_base + qh.tally_offset : nullptr;
       flush_acc<MODE == kTallyTotals || MODE == kTallyAuto>(
-          A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri), lane_tot);
+          A, a.scal_base + qh.scalar_offset, MODE == kTallyTotals || (MODE == kTallyAuto && !qh.per_tri), wave_tot);
       if (MODE == kTallyLane) flush_lane_tally(lt, htally, qh.nt);
       acc_zero(A);
       if (kPre) {
@@ -762,7 +762,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           if (fin) out = finish_segment(tris, orig, q, L, s, h, fid, limited);
           count_pass(A, fin, out, h.valid, limited);
           if (use_lds) tally<kTallyLds>(q, h, qtally, lt, q.nt, A);
-          else tally<MODE>(q, h, qtally, lane_tot, q.nt, A);
+          else tally<MODE>(q, h, qtally, wave_tot, q.nt, A);
           if (fin) {
             if (out != kOutGoOn) {
               retire(q, L, A);
@@ -1025,14 +1025,14 @@ __global__ void finalize_kernel(const QueryDev* __restrict__ qs, const uint32_t*
 }
 
 // Dynamic LDS of the tallies: the workgroup tally of lds_tris triangles, the
-// per-lane slots of <= 2-triangle meshes, or per-lane totals (persistent
+// per-lane slots of <= 2-triangle meshes, or per-wave totals (persistent
 // kernel only; the plain kernel keeps totals in registers); the mixed mode
-// of serving steps holds both a workgroup tally and per-lane totals.
-size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent, bool lane_totals = false) {
+// of serving steps holds both a workgroup tally and per-wave totals.
+size_t tally_lds_bytes(TallyMode mode, uint32_t lds_tris, bool persistent, bool wave_totals = false) {
   switch (mode) {
     case kTallyLds: return (size_t)lds_tris * 7 * sizeof(unsigned long long);
     case kTallyAuto:  // per-triangle area, then (persistent, if any entry keeps totals only) the per-wave totals
-      return ((size_t)lds_tris * 7 + (persistent && lane_totals ? (size_t)7 * kWaves : 0)) * sizeof(unsigned long long);
+      return ((size_t)lds_tris * 7 + (persistent && wave_totals ? (size_t)7 * kWaves : 0)) * sizeof(unsigned long long);
     case kTallyLane: return (size_t)2 * 7 * kBlock * sizeof(unsigned long long);
     case kTallyTotals: return persistent ? (size_t)7 * kWaves * sizeof(unsigned long long) : 0;
     default: return 0;
@@ -1058,7 +1058,7 @@ void launch_trace_stack(const TraceArgs& a, TallyMode mode, int grid, hipStream_
 
 template <int STACK>
 void launch_batch_mode(const BatchArgs& a, TallyMode mode, int grid, hipStream_t st) {
-  const size_t lds = tally_lds_bytes(mode, a.lds_tris, true, a.lane_totals != 0u);
+  const size_t lds = tally_lds_bytes(mode, a.lds_tris, true, a.wave_totals != 0u);
   switch (mode) {
     case kTallyLane: batch_kernel<STACK, kTallyLane><<<grid, kBlock, lds, st>>>(a); break;
     case kTallyLds: batch_kernel<STACK, kTallyLds><<<grid, kBlock, lds, st>>>(a); break;

@@ -48,7 +48,7 @@ struct BatchArgs {
   uint32_t refill;                 // as TraceArgs::refill
   uint64_t tile;                   // particles per tile (multiple of 64)
   uint32_t lds_tris;               // largest nt of an entry with an LDS tally (kTallyLds / kTallyAuto)
-  uint32_t lane_totals;            // kTallyAuto: some entry keeps totals only (per-lane LDS totals allocated)
+  uint32_t wave_totals;            // kTallyAuto: some entry keeps totals only (per-wave LDS totals allocated)
   // Where each XCD's workgroups start claiming: XCD x (workgroups x, x + 8, ...; the
   // hardware deals workgroups to the eight XCDs in turn) starts in entries
   // [xcd_start[x], xcd_start[x + 1]) (entries grouped by mesh, ranges by tile share),
