@@ -538,10 +538,10 @@ def summarize_counters(pmc_dir):
 
 def summarize_served_trace(trace_dir):
     """Markdown summary of a rocprofv3 --kernel-trace of the served workload
-    (run with --served-loads "" so that every batched launch is a saturation
-    step): step launches, the time between one step's end and the next one's
-    start, how much of that time no kernel ran, and the kernels run between
-    steps."""
+    (run with --served-loads "" so that every batched launch before the FIFO
+    plain path is a saturation step): step launches, the time between one
+    step's end and the next one's start, how much of that time no kernel ran,
+    and the kernels run between steps."""
     import csv
     import glob
     rows = []
@@ -556,7 +556,9 @@ def summarize_served_trace(trace_dir):
         m = re.search(r"(?<![A-Za-z0-9_])([A-Za-z_][A-Za-z0-9_]*_kernel)(<[^>]*>)?", n)
         return (m.group(1) + (m.group(2) or "")) if m else n.split("(")[0]
 
-    steps = [r for r in rows if "batch_kernel<" in r[2]]
+    # the saturation run's steps: the batched launches before the FIFO plain path's first trace launch
+    first_plain = min((r[0] for r in rows if "trace_kernel<" in r[2]), default=None)
+    steps = [r for r in rows if "batch_kernel<" in r[2] and (first_plain is None or r[0] < first_plain)]
     if len(steps) < 2:
         print("fewer than two step launches in the trace")
         return
