@@ -923,6 +923,98 @@ def workload_sweep(args):
           {"workload": sw["workload"], "path": "one persistent graph-replayed launch", "bvh": args.bvh}, sw)
 
 
+PROBE_PHASES = (("claim", "claim_cycles"), ("traversal", "trav_cycles"), ("leaf", "leaf_cycles"),
+                ("service", "serve_cycles"), ("estimate", "est_cycles"), ("seeding", "seed_cycles"),
+                ("hand-out", "assign_cycles"))
+
+
+def probe_record(p, particles, ms):
+    """Per-64-particle passes, mean active lanes and share of wave time of each
+    phase, from the phase probe's sums over one launch."""
+    per64 = 64.0 / particles
+
+    def mean(a, b):
+        return p[a] / p[b] if p[b] else None
+    share = {name: p[slot] / p["cycles"] for name, slot in PROBE_PHASES}
+    share["other"] = 1.0 - sum(share.values())
+    return {"ms": ms, "particles": particles, "waves": p["waves"],
+            "wave_clock_ghz": p["cycles"] / p["waves"] / (ms * 1e-3) / 1e9,
+            "per_64_particles": {"traversal_steps": p["trav_steps"] * per64, "leaf_passes": p["leaf_passes"] * per64,
+                                 "service_passes": p["serves"] * per64, "estimate_batches": p["est_batches"] * per64,
+                                 "seeding_batches": p["seed_batches"] * per64, "hand_outs": p["assigns"] * per64},
+            "mean_lanes": {"traversal": mean("trav_lanes", "trav_steps"), "leaf": mean("leaf_lanes", "leaf_passes"),
+                           "service": mean("serve_lanes", "serves"), "estimate": mean("est_particles", "est_batches"),
+                           "seeding": mean("seed_particles", "seed_batches"),
+                           "hand_out": mean("assign_lanes", "assigns")},
+            "estimate_kept": mean("est_kept", "est_particles"), "seeding_kept": mean("seed_kept", "seed_particles"),
+            "share": share, "sums": p}
+
+
+def workload_phase_probe(args):
+    """Where the persistent kernel's time goes, from libtpmc_probe.so (the
+    library with the batched kernel's phase probe compiled in): one launch each
+    of the plate and cylinder batches (per-case N as in the benchmark line, or
+    --particles each with --fixed-n), the concave satellite and the attitude
+    sweep, with the autotuned settings (or --tuning).  Prints one JSON line with
+    each launch's passes and mean active lanes per phase and the share of wave
+    time each phase takes, and the same as a markdown table on stderr.  The
+    probe's clock reads lengthen a launch by some per cent; the ordinary
+    library has none of this code."""
+    os.environ["TPMC_PHASE_PROBE"] = "1"
+    import torch
+
+    from paper_1312_3691_amd import inputs as I
+    from paper_1312_3691_amd import tpmc
+    if not tpmc.PHASE_PROBE:
+        raise RuntimeError("the binding was imported before the probe library was selected")
+    ctx = tpmc.Context(0)
+    mm = meshes()
+    dev_mesh = {k: ctx.build_mesh(*v, builder=args.bvh) for k, v in mm.items()}
+    if args.fixed_n:
+        n_case = [args.particles] * len(cases(1))
+    else:
+        n_case = case_particles(ctx, dev_mesh, args.particles, args.pilot_particles)
+    cl = cases(args.particles, n_case)
+    sat = ctx.build_mesh(*I.satellite(50_000), builder=args.bvh)
+    runs = [("plate", dev_mesh["plate"], [c["query"] for c in cl if c["kind"] == "plate"], "plate"),
+            ("cylinder", dev_mesh["cylinder"], [c["query"] for c in cl if c["kind"] == "cylinder"], "cylinder"),
+            ("satellite", sat, [satellite_query(args.particles_sat)], "satellite"),
+            ("sweep", sat, sweep_queries(args.particles_sweep), "sweep")]
+    out = {}
+    for name, mesh, qs, key in runs:
+        tuning = tune_for(args, mesh, qs, key=key)
+        b = tpmc.Batch(mesh, qs)
+        b.launch().results()
+        torch.cuda.synchronize()
+        ctx.phase_probe(reset=True)
+        ms = launch_ms(ctx, b, tuning, 1)
+        p = ctx.phase_probe(reset=True)
+        res = b.results()
+        b.close()
+        rec = probe_record(p, sum(r["rays"] for r in res), ms)
+        rec.update(kernel=f"{batch_instance(mesh, totals_only=name == 'sweep')} ({name}, {mesh.nt} tris, "
+                          f"{len(qs)} queries)", tuning=tuning,
+                   preculled_frac=sum(r["preculled"] for r in res) / rec["particles"])
+        out[name] = rec
+        log(f"{name}: {ms:.2f} ms, shares " + " ".join(f"{k} {v:.3f}" for k, v in rec["share"].items()))
+    rows = ["| launch | traversal steps (lanes) | leaf phases (lanes) | service passes (lanes) | "
+            "estimate batches (kept) | seeding batches (lanes) | share of wave time: claim / traversal / leaf / "
+            "service / estimate / seeding / hand-out / other |", "|---|---|---|---|---|---|---|"]
+    for name, r in out.items():
+        n, ln, sh = r["per_64_particles"], r["mean_lanes"], r["share"]
+
+        def f(k, lk):
+            return f"{n[k]:.2f} ({ln[lk]:.1f})" if ln[lk] is not None else "—"
+        est = f"{n['estimate_batches']:.2f} ({r['estimate_kept']:.2f})" if r["estimate_kept"] is not None else "—"
+        rows.append(f"| {r['kernel']} | {f('traversal_steps', 'traversal')} | {f('leaf_passes', 'leaf')} | "
+                    f"{f('service_passes', 'service')} | {est} | {f('seeding_batches', 'seeding')} | "
+                    + " / ".join(f"{100 * sh[k]:.0f}" for k in ("claim", "traversal", "leaf", "service", "estimate",
+                                                                 "seeding", "hand-out", "other")) + " % |")
+    log("\n".join(rows))
+    print(json.dumps({"probe": "batched kernel phases per 64 particles (libtpmc_probe.so)", "launches": out,
+                      "table_md": rows}), flush=True)
+
+
 SERVED_MESHES = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
 SERVED_WARM, SERVED_MEASURED = 200, 2000  # default served run: warm-up and measured requests
 SERVED_DEFAULT_REQUESTS = SERVED_WARM + SERVED_MEASURED
@@ -1117,7 +1209,7 @@ def main():
                     help="step launches and the gaps between them, from a kernel trace of the served workload")
     ap.add_argument("--workload", default="plate-cylinder",
                     choices=["plate-cylinder", "satellite", "sweep", "served", "pratt", "moments", "boxcv",
-                             "energy", "ceilings"],
+                             "energy", "ceilings", "phase-probe"],
                     help="plate-cylinder (default, the benchmark line) or an additional configuration")
     ap.add_argument("--particles-sat", type=float, default=1e8)
     ap.add_argument("--particles-sweep", type=float, default=1e6)
@@ -1162,7 +1254,8 @@ def main():
     if args.workload != "plate-cylinder":
         {"satellite": workload_satellite, "sweep": workload_sweep, "served": workload_served,
          "pratt": workload_pratt, "moments": workload_moments, "boxcv": workload_boxcv,
-         "energy": workload_energy, "ceilings": workload_ceilings}[args.workload](args)
+         "energy": workload_energy, "ceilings": workload_ceilings,
+         "phase-probe": workload_phase_probe}[args.workload](args)
         return
 
     import torch

@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TPMC_ABI_VERSION 8
+#define TPMC_ABI_VERSION 9
 
 typedef enum {
   TPMC_OK = 0,
@@ -369,7 +369,7 @@ tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots
 /* ---- Check of the batched path's two-stage seeding ----
  * The persistent kernel (batches and server steps) seeds in two stages: an
  * FP32 estimate of each particle's first ray from its own variates (Sec.
- * III.A.1-3 in FP32, tabulated starts and one Halley step per inverse-CDF
+ * III.A.1-3 in FP32, tabulated starts and two Halley steps per inverse-CDF
  * solve) is tested against the BVH root's boxes grown on every side by 2 % of
  * the CV radius, and only the particles it does not rule out are seeded
  * exactly (FP64) and traced; the others are misses either way, so no result
@@ -385,6 +385,29 @@ tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots
 #define TPMC_PRECULL_CHECK_BYTES 1024
 tpmc_status tpmc_precull_check(tpmc_ctx ctx, tpmc_mesh mesh, const tpmc_query* q, void* dev_ws, uint64_t ws_bytes,
                                double* max_err_over_margin, uint64_t* estimated);
+
+/* ---- Phase probe of the persistent kernel (a measuring aid) ----
+ * A library compiled with TPMC_PHASE_PROBE=1 (libtpmc_probe.so, built next to
+ * libtpmc.so by the package's build script) has every wave of the batched
+ * kernel read the shader clock around its phases and count each phase's passes
+ * and active lanes; the ordinary library has no such code.  tpmc_phase_probe
+ * waits for the context's stream, copies the sums of every batched launch on
+ * the context's device since the last reset into out[0 .. TPMC_PROBE_SLOTS)
+ * (caller's host memory, n_slots >= TPMC_PROBE_SLOTS) and, when reset is
+ * nonzero, clears them.  It returns TPMC_E_INVALID, writing nothing, from a
+ * library built without the probe.  Slots (sums over waves; cycles are
+ * shader-clock ticks, lanes the active lanes of each pass):
+ *   0 waves, 1 cycles from a wave's start to its exit,
+ *   2-3 cycles and count of tile claims (with the ends of tiles),
+ *   4-6 traversal steps: cycles, steps, lanes,
+ *   7-9 leaf phases (the batched triangle tests): cycles, passes, lanes,
+ *   10-12 service passes (hit, re-emission, tally): cycles, passes, lanes,
+ *   13-16 seeding estimate (first stage): cycles, batches, particles, kept,
+ *   17-20 exact seeding with the root test: cycles, batches, particles, kept,
+ *   21-23 queue hand-out to idle lanes: cycles, passes, lanes.
+ * The probe's own clock reads lengthen a launch by some per cent. */
+#define TPMC_PROBE_SLOTS 24
+tpmc_status tpmc_phase_probe(tpmc_ctx ctx, uint64_t* out, uint32_t n_slots, int reset);
 
 #ifdef __cplusplus
 }

@@ -3,7 +3,10 @@
     python -m paper_1312_3691_amd.build        # or build() from Python
 
 Every HIP source is compiled with packed-FP32 instruction selection disabled
-(-Xclang -target-feature -Xclang -packed-fp32-ops).
+(-Xclang -target-feature -Xclang -packed-fp32-ops).  The build also links
+libtpmc_probe.so, the same library with the batched kernel's phase probe
+compiled in (TPMC_PHASE_PROBE=1, read through tpmc_phase_probe); the binding
+loads it instead of libtpmc.so only when TPMC_PHASE_PROBE=1 is set.
 """
 from __future__ import annotations
 
@@ -11,10 +14,13 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpmc.so")
+PROBE_LIB = os.path.join(HERE, "libtpmc_probe.so")
+PROBE_SOURCES = ["tpmc_capi.hip", "tpmc_kernels.hip"]  # the sources the probe switch changes
 SOURCES = ["tpmc_capi.hip", "tpmc_kernels.hip", "tpmc_bvh.hip", "tpmc_ceilings.hip"]
 HEADERS = ["tpmc_device.hpp", "tpmc_math.hpp", "tpmc_internal.h", "tpmc_launch.h"]
 ARCH = os.environ.get("TPMC_OFFLOAD_ARCH", "gfx950")
@@ -44,8 +50,9 @@ def torch_lib_dir() -> str:
     return d
 
 
-def compile_command(src: str, obj: str) -> list:
+def compile_command(src: str, obj: str, defines=()) -> list:
     return [hipcc(), f"--offload-arch={ARCH}", "-mcode-object-version=5", "-O3", "-std=c++17", "-fPIC", "-c",
+            *["-D" + d for d in defines],
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             # Machine LICM hoists the FP64 polynomial constants of exp/erfc out of the
             # Newton and particle loops into ~300 registers (occupancy 1); without it
@@ -74,17 +81,32 @@ def _run(cmd, verbose):
         print("\n".join(noise))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source and link paper_1312_3691_amd/libtpmc.so (always rebuilds)."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
-    for s in SOURCES:
-        obj = os.path.join(BUILD_DIR, s.replace(".hip", ".o"))
-        _run(compile_command(os.path.join(CSRC, s), obj), verbose)
-        objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+def _link(objs, lib, verbose):
+    tmp = lib + ".tmp%d" % os.getpid()
     _run(link_command(objs, tmp), verbose)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose: bool = False, probe: bool = True) -> str:
+    """Compile every HIP source and link paper_1312_3691_amd/libtpmc.so, then
+    (probe) libtpmc_probe.so; always rebuilds.  Returns the path of libtpmc.so."""
+    probe_dir = os.path.join(BUILD_DIR, "probe")
+    os.makedirs(probe_dir, exist_ok=True)
+    objs = {s: os.path.join(BUILD_DIR, s.replace(".hip", ".o")) for s in SOURCES}
+    jobs = [compile_command(os.path.join(CSRC, s), objs[s]) for s in SOURCES]
+    probe_objs = dict(objs)
+    if probe:
+        for s in PROBE_SOURCES:
+            probe_objs[s] = os.path.join(probe_dir, s.replace(".hip", ".o"))
+            jobs.append(compile_command(os.path.join(CSRC, s), probe_objs[s], defines=("TPMC_PHASE_PROBE=1",)))
+    # the compiles are independent: run them side by side
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for cmd in jobs]:
+            f.result()
+    _link([objs[s] for s in SOURCES], LIB, verbose)
+    if probe:
+        _link([probe_objs[s] for s in SOURCES], PROBE_LIB, verbose)
     return LIB
 
 

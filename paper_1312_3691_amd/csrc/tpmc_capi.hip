@@ -1427,6 +1427,21 @@ extern "C" tpmc_status tpmc_precull_check(tpmc_ctx ctx, tpmc_mesh m, const tpmc_
   return TPMC_OK;
 }
 
+static_assert(TPMC_PROBE_SLOTS == kProbeSlots, "phase probe layout");
+
+extern "C" tpmc_status tpmc_phase_probe(tpmc_ctx ctx, uint64_t* out, uint32_t n_slots, int reset) {
+  if (!probe_built()) return fail(TPMC_E_INVALID, "library built without the phase probe (TPMC_PHASE_PROBE=1)");
+  if (!ctx || !out) return fail(TPMC_E_INVALID, "ctx and out must not be NULL");
+  if (n_slots < (uint32_t)kProbeSlots)
+    return fail(TPMC_E_INVALID, "n_slots = %u, the probe has %d", n_slots, kProbeSlots);
+  unsigned long long h[kProbeSlots];
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = probe_read(h, reset != 0, ctx->stream);
+  if (e != hipSuccess) return fail(TPMC_E_DEVICE, "phase probe: %s", hipGetErrorString(e));
+  for (int k = 0; k < kProbeSlots; ++k) out[k] = h[k];
+  return TPMC_OK;
+}
+
 extern "C" tpmc_status tpmc_ceiling_valu(tpmc_ctx ctx, uint32_t kind, void* dev_sink, double* lane_ops_per_s) {
   if (!ctx || !dev_sink || !lane_ops_per_s) return fail(TPMC_E_INVALID, "ctx, sink and out must not be NULL");
   if (kind > 2) return fail(TPMC_E_INVALID, "kind = %u outside 0..2", kind);

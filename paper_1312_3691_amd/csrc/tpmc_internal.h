@@ -25,6 +25,23 @@ enum ScalarSlot {
   kPrecullOff = 20      // nonzero once the batched kernel has switched the estimate off for this query
 };
 
+// Phase probe of the batched kernel (compiled in only with TPMC_PHASE_PROBE=1):
+// sums over the waves of every launch since the last reset.  Cycles are
+// shader-clock ticks a wave spends in a phase; lanes are the active lanes of
+// each pass, summed.  The slot numbers are the TPMC_PROBE_* ones of the
+// public header.
+enum ProbeSlot {
+  kPrWaves = 0, kPrCycles = 1,                                                    // waves; cycles start to exit
+  kPrClaimCyc = 2, kPrClaims = 3,                                                 // tile claims and tile ends
+  kPrTravCyc = 4, kPrTravSteps = 5, kPrTravLanes = 6,                             // traversal steps
+  kPrLeafCyc = 7, kPrLeafPasses = 8, kPrLeafLanes = 9,                            // leaf phases
+  kPrServeCyc = 10, kPrServes = 11, kPrServeLanes = 12,                           // service passes
+  kPrEstCyc = 13, kPrEstBatches = 14, kPrEstLanes = 15, kPrEstKept = 16,          // estimate (stage 1)
+  kPrSeedCyc = 17, kPrSeedBatches = 18, kPrSeedLanes = 19, kPrSeedKept = 20,      // exact seeding + root test
+  kPrAssignCyc = 21, kPrAssigns = 22, kPrAssignLanes = 23,                        // queue -> idle lanes
+  kProbeSlots = 24
+};
+
 struct Node;
 struct TriRec;
 

@@ -8,7 +8,15 @@
 #include "tpmc_device.hpp"
 #include "tpmc_launch.h"
 
+#ifndef TPMC_PHASE_PROBE
+#define TPMC_PHASE_PROBE 0
+#endif
+
 namespace tpmc {
+
+#if TPMC_PHASE_PROBE
+__device__ unsigned long long g_probe[kProbeSlots];  // ProbeSlot sums of the batched launches
+#endif
 
 namespace {
 
@@ -338,6 +346,35 @@ __device__ __forceinline__ uint32_t below(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// Phase probe of batch_kernel, in libraries built with TPMC_PHASE_PROBE=1
+// (elsewhere PROBE(...) expands to nothing): each wave reads the shader clock
+// around its phases and sums cycles, passes and active lanes, all
+// wave-uniform, into one VGPR whose lane k holds ProbeSlot k (32 bits: a wave
+// of one launch stays far below 2^32 cycles and passes); lanes kPrTs, kPrTc
+// and kPrTp hold the clock at the wave's start, at the current tile claim and
+// at the current phase's start.  Lanes are written with v_writelane and read
+// with v_readlane (no lane masks, no long-lived scalar registers), so the
+// instrumented kernel keeps the ordinary one's registers and occupancy.  At
+// exit lane k adds its slot to g_probe.
+#if TPMC_PHASE_PROBE
+#define PROBE(...) __VA_ARGS__
+constexpr int kPrTp = 29, kPrTs = 30, kPrTc = 31;
+static_assert(kProbeSlots <= kPrTp, "probe lanes");
+__device__ __forceinline__ uint32_t probe_now() { return (uint32_t)__builtin_amdgcn_s_memtime(); }
+__device__ __forceinline__ uint32_t probe_get(uint32_t v, int k) { return __builtin_amdgcn_readlane(v, k); }
+template <int K>
+__device__ __forceinline__ void probe_set(uint32_t& v, uint32_t x) {
+  // the trailing wait states keep a v_readlane of the written VGPR right after it exact
+  asm("v_writelane_b32 %0, %1, %2\n\ts_nop 1" : "+v"(v) : "s"(x), "i"(K));
+}
+template <int K>
+__device__ __forceinline__ void probe_add(uint32_t& v, uint32_t x) { probe_set<K>(v, probe_get(v, K) + x); }
+template <int K>
+__device__ __forceinline__ void probe_since(uint32_t& v, int t) { probe_add<K>(v, probe_now() - probe_get(v, t)); }
+#else
+#define PROBE(...)
+#endif
+
 // Outcome of a finished segment.  kOutHitLeft: a hit whose outgoing segment
 // cannot hit anything (the mesh lies on the other side of the triangle's
 // plane), so that segment is counted and the particle escapes untraced.
@@ -657,6 +694,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
   Acc A;
   acc_zero(A);
+  PROBE(uint32_t pr = 0u; probe_set<kPrTs>(pr, probe_now()); probe_set<kPrTc>(pr, probe_get(pr, kPrTs));)
   // two-stage seeding, wave-uniform: particles the estimate removed (for the
   // held query), and the estimate's yield so far on it.  A wave that finds
   // more than 60 % of a query's particles surviving the estimate switches it
@@ -708,7 +746,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         for (uint32_t i = threadIdx.x; i < qh.nt * 7u; i += kBlock)
           if (lt[i]) atomic_add_i64(htally + i, (long long)lt[i]);
     }
-    if (j == kNone) break;  // uniform
+    if (j == kNone) break;  // uniform (the last claim's cycles are not in the claim slot)
     const QueryDev& q = a.qs[a.entry_query ? a.entry_query[j] : j];
     const bool use_lds = kMayLds && q.per_tri && q.nt <= (uint32_t)kLdsTallyMaxTris;
     if (j != held) {
@@ -726,6 +764,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     const uint32_t* orig = uniform_ptr(q.orig);
     if (threadIdx.x == 0) next_sh = p_begin;
     __syncthreads();
+    PROBE(probe_since<kPrClaimCyc>(pr, kPrTc); probe_add<kPrClaims>(pr, 1u);)
 
     Lane L;
     Seg s;
@@ -746,14 +785,19 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     for (;;) {
       uint32_t ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
       if (ntrav < a.refill && ballot(L.live && s.p0 >= 0) != 0ull) {
+        PROBE(probe_set<kPrTp>(pr, probe_now()); probe_add<kPrLeafPasses>(pr, 1u);
+              probe_add<kPrLeafLanes>(pr, (uint32_t)lanes(L.live && s.p0 >= 0));)
         uint32_t n1 = 0;
         leaf_phase<false>(tris, orig, r, L.prev, s, n1);
         ntrav = (uint32_t)__popcll(ballot(L.live && seg_traversing(s)));
+        PROBE(probe_since<kPrLeafCyc>(pr, kPrTp);)
       }
       if (ntrav < a.refill) {
         // serve every lane whose segment has ended
         const bool fin = L.live && seg_finished(s);
         if (ballot(fin) != 0ull) {
+          PROBE(probe_set<kPrTp>(pr, probe_now()); probe_add<kPrServes>(pr, 1u);
+                probe_add<kPrServeLanes>(pr, (uint32_t)lanes(fin));)
           Hit h;
           h.valid = false;
           int out = kOutGoOn;
@@ -771,12 +815,14 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               seg_begin(s);
             }
           }
+          PROBE(probe_since<kPrServeCyc>(pr, kPrTp);)
         }
         const uint64_t dead = ballot(!L.live);
         if (kPre && dead != 0ull) {
           while (q_count == 0 && !(exhausted && s_count == 0)) {  // wave-uniform
             if (s_count < 64 && !exhausted) {
               // stage 1: claim 64 particles, keep those the estimate cannot rule out
+              PROBE(probe_set<kPrTp>(pr, probe_now());)
               unsigned long long base = 0;
               if (lane == 0) base = atomicAdd(&next_sh, 64ull);
               base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
@@ -801,12 +847,16 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
                   pc_on = false;
                   pc_off_now = true;
                 }
+                PROBE(probe_add<kPrEstBatches>(pr, 1u); probe_add<kPrEstLanes>(pr, nvalid);
+                      probe_add<kPrEstKept>(pr, nmaybe);)
                 __builtin_amdgcn_wave_barrier();
               }
+              PROBE(probe_since<kPrEstCyc>(pr, kPrTp);)
             } else {
             // stage 2: exact seeding of up to 64 survivors, one per lane; the
             // exact root test as in the one-stage seeding below
             const uint32_t n = s_count < 64u ? s_count : 64u;
+            PROBE(probe_set<kPrTp>(pr, probe_now());)
             bool keep = false;
             float xs[3], ws[3];
             if ((uint32_t)lane < n) {
@@ -835,6 +885,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             s_count -= n;
             q_count = (uint32_t)__popcll(kb);
             q_head = 0;
+            PROBE(probe_since<kPrSeedCyc>(pr, kPrTp); probe_add<kPrSeedBatches>(pr, 1u);
+                  probe_add<kPrSeedLanes>(pr, n); probe_add<kPrSeedKept>(pr, q_count);)
             __builtin_amdgcn_wave_barrier();
             }
           }
@@ -842,6 +894,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         if (!kPre && dead != 0ull) {
           while (q_count == 0 && !exhausted) {  // wave-uniform
             // claim and seed the next (up to) 64 particles, one per lane
+            PROBE(probe_set<kPrTp>(pr, probe_now());)
             unsigned long long base = 0;
             if (lane == 0) base = atomicAdd(&next_sh, 64ull);
             base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
@@ -882,13 +935,17 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
               q_count = (uint32_t)__popcll(kb);
               q_head = 0;
               q_pid0 = base;
+              PROBE(probe_add<kPrSeedBatches>(pr, 1u); probe_add<kPrSeedLanes>(pr, (uint32_t)lanes(pid < p_end));
+                    probe_add<kPrSeedKept>(pr, q_count);)
               __builtin_amdgcn_wave_barrier();
             }
+            PROBE(probe_since<kPrSeedCyc>(pr, kPrTp);)
           }
         }
         if (dead != 0ull) {
           if (q_count > 0) {
             // dead lanes take queue entries in lane order
+            PROBE(probe_set<kPrTp>(pr, probe_now());)
             const uint32_t rank = below(dead);
             if (!L.live && rank < q_count) {
               const uint32_t slot = q_head + rank;
@@ -906,6 +963,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             const uint32_t took = ndead < q_count ? ndead : q_count;
             q_head += took;
             q_count -= took;
+            PROBE(probe_since<kPrAssignCyc>(pr, kPrTp); probe_add<kPrAssigns>(pr, 1u);
+                  probe_add<kPrAssignLanes>(pr, took);)
             __builtin_amdgcn_wave_barrier();
           }
         }
@@ -920,15 +979,21 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
         A.guard += lanes(L.live && s.cur != kDone);
         s.cur = kDone;
       }
+      PROBE(const uint32_t nl = (uint32_t)lanes(L.live && seg_traversing(s)); probe_add<kPrTravLanes>(pr, nl);
+            probe_add<kPrTravSteps>(pr, nl != 0u ? 1u : 0u); probe_set<kPrTp>(pr, probe_now());)
       if (L.live && seg_traversing(s)) {
         uint32_t n0 = 0, n1 = 0;
         trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
       }
+      PROBE(probe_since<kPrTravCyc>(pr, kPrTp);)
     }
+    PROBE(probe_set<kPrTc>(pr, probe_now());)
     if (kPre && pc_off_now && lane == 0)  // published at the tile's end, outside the trace loop
       __hip_atomic_store(a.scal_base + q.scalar_offset + kPrecullOff, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();  // every wave is done with the tile; tile_sh / entry_sh / next_sh may be reused
   }
+  PROBE(probe_set<kPrWaves>(pr, 1u); probe_set<kPrCycles>(pr, probe_now() - probe_get(pr, kPrTs));
+        if (lane < kProbeSlots) atomicAdd(&g_probe[lane], (unsigned long long)pr);)
 }
 
 // ---------------------------------------------------------------------------
@@ -1131,6 +1196,26 @@ void launch_precull_check(const QueryDev* d_q, uint64_t n, unsigned long long* o
   zero_i64_kernel<<<1, kBlock, 0, st>>>(reinterpret_cast<long long*>(out), 2);
   precull_check_kernel<<<grid, kBlock, 0, st>>>(d_q, n, out);
 }
+
+#if TPMC_PHASE_PROBE
+bool probe_built() { return true; }
+
+hipError_t probe_read(unsigned long long* out, bool reset, hipStream_t st) {
+  unsigned long long* d = nullptr;
+  hipError_t e = hipGetSymbolAddress((void**)&d, HIP_SYMBOL(g_probe));
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d, kProbeSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess && reset) {
+    zero_i64_kernel<<<1, kBlock, 0, st>>>(reinterpret_cast<long long*>(d), kProbeSlots);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+#else
+bool probe_built() { return false; }
+
+hipError_t probe_read(unsigned long long*, bool, hipStream_t) { return hipErrorNotSupported; }
+#endif
 
 hipError_t init_seed_tables(hipStream_t st) {
   float* tab = nullptr;

@@ -88,6 +88,11 @@ void launch_batch(const BatchArgs& a, int stack_slots, TallyMode mode, int grid,
 // Check of the two-stage seeding's estimate (precull_check_kernel): out[0] the
 // bits of the largest error / margin, out[1] the particles estimated.
 void launch_precull_check(const QueryDev* d_q, uint64_t n, unsigned long long* out, int grid, hipStream_t st);
+// Phase probe: whether this library was built with it; the readout copies the
+// kProbeSlots sums of the current device into out (after the stream's work)
+// and clears them when reset.
+bool probe_built();
+hipError_t probe_read(unsigned long long* out, bool reset, hipStream_t st);
 // Serving admission: n records (device) -> constants into qs[slot], cleared
 // scalar block and per-triangle tally words; max_words is the largest tally.
 void launch_admit(const AdmitRec* rec, uint32_t n, uint64_t max_words, QueryDev* qs, long long* scal,

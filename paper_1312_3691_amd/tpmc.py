@@ -3,7 +3,9 @@
 Argument marshalling only: every step of the drag computation runs in the
 library's HIP kernels.  PyTorch supplies device memory (the workspaces) and the
 HIP stream.  Importing this module fails loudly when libtpmc.so is missing;
-there is no CPU fallback.
+there is no CPU fallback.  With TPMC_PHASE_PROBE=1 in the environment it loads
+libtpmc_probe.so instead, the same library with the batched kernel's phase
+probe compiled in (Context.phase_probe).
 """
 from __future__ import annotations
 
@@ -15,9 +17,11 @@ import numpy as np
 import torch  # noqa: F401  -- loads PyTorch's HIP runtime, which libtpmc.so is linked against
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtpmc.so")
+PHASE_PROBE = os.environ.get("TPMC_PHASE_PROBE", "0") == "1"
+LIB_PATH = os.path.join(_HERE, "libtpmc_probe.so" if PHASE_PROBE else "libtpmc.so")
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"libtpmc.so not built ({LIB_PATH}); run `python -m paper_1312_3691_amd.build` first")
+    raise ImportError(f"{os.path.basename(LIB_PATH)} not built ({LIB_PATH}); "
+                      "run `python -m paper_1312_3691_amd.build` first")
 _lib = ctypes.CDLL(LIB_PATH)
 
 Q_NO_TRIANGLE_TALLY = 1
@@ -119,16 +123,27 @@ _SIGS = {
     "tpmc_ceiling_atomic": ([_vp, _vp, _u32, _u32, _dp], ctypes.c_int),
     "tpmc_ceiling_lds_atomic": ([_vp, _vp, _u32, _u32, _dp], ctypes.c_int),
     "tpmc_precull_check": ([_vp, _vp, _QP, _vp, _u64, _dp, ctypes.POINTER(_u64)], ctypes.c_int),
+    "tpmc_phase_probe": ([_vp, ctypes.POINTER(_u64), _u32, ctypes.c_int], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
     _f.argtypes = _args
     _f.restype = _res
 
-ABI_VERSION = 8  # the structures below are laid out for this version of include/tpmc.h
+ABI_VERSION = 9  # the structures below are laid out for this version of include/tpmc.h
 if _lib.tpmc_abi_version() != ABI_VERSION:
     raise ImportError(f"libtpmc.so has ABI version {_lib.tpmc_abi_version()}, this binding expects "
                       f"{ABI_VERSION}: rebuild the library (python -c 'import __graft_entry__ as g; g.build()')")
+
+
+# slots of tpmc_phase_probe, in order (include/tpmc.h)
+PROBE_SLOTS = ("waves", "cycles", "claim_cycles", "claims",
+               "trav_cycles", "trav_steps", "trav_lanes",
+               "leaf_cycles", "leaf_passes", "leaf_lanes",
+               "serve_cycles", "serves", "serve_lanes",
+               "est_cycles", "est_batches", "est_particles", "est_kept",
+               "seed_cycles", "seed_batches", "seed_particles", "seed_kept",
+               "assign_cycles", "assigns", "assign_lanes")
 
 
 def _check(status: int):
@@ -282,6 +297,14 @@ class Context:
         out = ctypes.c_double()
         _check(_lib.tpmc_ceiling_lds_atomic(self._h, _vp(sink.data_ptr()), slots, per_thread, ctypes.byref(out)))
         return out.value
+
+    def phase_probe(self, reset: bool = True) -> dict:
+        """Sums of the batched kernel's phase probe since the last reset (after
+        the stream's work), by slot name; raises TpmcError from a library built
+        without the probe (tpmc_phase_probe)."""
+        out = (_u64 * len(PROBE_SLOTS))()
+        _check(_lib.tpmc_phase_probe(self._h, out, len(PROBE_SLOTS), 1 if reset else 0))
+        return {k: int(v) for k, v in zip(PROBE_SLOTS, out)}
 
 
 class Mesh:

@@ -33,7 +33,30 @@ def test_every_declared_symbol_is_exported(T):
     lib = ctypes.CDLL(T.LIB_PATH)
     for n in names:
         assert hasattr(lib, n), n
-    assert lib.tpmc_abi_version() == T.ABI_VERSION == 8
+    assert lib.tpmc_abi_version() == T.ABI_VERSION == 9
+
+
+def test_probe_library_exports_the_same_abi(T):
+    """libtpmc_probe.so (the batched kernel with its phase probe) is the same
+    C ABI; only it answers tpmc_phase_probe, the ordinary library refuses."""
+    probe = ctypes.CDLL(os.path.join(os.path.dirname(T.LIB_PATH), "libtpmc_probe.so"))
+    plain = ctypes.CDLL(os.path.join(os.path.dirname(T.LIB_PATH), "libtpmc.so"))
+    for n in _declared_functions():
+        assert hasattr(probe, n), n
+    assert probe.tpmc_abi_version() == T.ABI_VERSION
+    out = (ctypes.c_uint64 * 24)()
+    plain.tpmc_last_error.restype = ctypes.c_char_p
+    assert plain.tpmc_phase_probe(None, out, 24, 0) == 1  # TPMC_E_INVALID: built without the probe
+    assert b"without the phase probe" in plain.tpmc_last_error()
+    assert probe.tpmc_phase_probe(None, out, 24, 0) == 1  # a probe library: NULL context
+    probe.tpmc_last_error.restype = ctypes.c_char_p
+    assert b"must not be NULL" in probe.tpmc_last_error()
+
+
+def test_probe_slot_names_match_header(T):
+    text = open(os.path.join(ROOT, "include", "tpmc.h")).read()
+    n = int(re.search(r"#define TPMC_PROBE_SLOTS (\d+)", text).group(1))
+    assert len(T.PROBE_SLOTS) == n == len(set(T.PROBE_SLOTS))
 
 
 def _c_layout(struct: str, fields) -> list:
