@@ -957,9 +957,11 @@ def workload_phase_probe(args):
     --particles each with --fixed-n), the concave satellite and the attitude
     sweep, with the autotuned settings (or --tuning).  Prints one JSON line with
     each launch's passes and mean active lanes per phase and the share of wave
-    time each phase takes, and the same as a markdown table on stderr.  The
-    probe's clock reads lengthen a launch by some per cent; the ordinary
-    library has none of this code."""
+    time each phase takes, and the same as a markdown table on stderr; then
+    the plate and cylinder batches at 2e6 particles per case with 1, 2 and 4
+    resident workgroups per CU, whose cycles per pass show which phases are
+    bound by latency rather than by issue.  The probe's clock reads lengthen a
+    launch by some per cent; the ordinary library has none of this code."""
     os.environ["TPMC_PHASE_PROBE"] = "1"
     import torch
 
@@ -1011,8 +1013,37 @@ def workload_phase_probe(args):
                     + " / ".join(f"{100 * sh[k]:.0f}" for k in ("claim", "traversal", "leaf", "service", "estimate",
                                                                  "seeding", "hand-out", "other")) + " % |")
     log("\n".join(rows))
+    # occupancy: the same plate and cylinder batches (2e6 particles per case) at 1, 2 and 4 resident
+    # workgroups per CU (1-4 waves per SIMD); a phase whose cycles per pass stay flat as waves are
+    # added is latency-bound, one whose cycles grow in proportion is issue-bound
+    occ, orows = {}, ["| launch | workgroups per CU | ms | cycles per pass: estimate / seeding / traversal step / "
+                      "leaf phase / service pass |", "|---|---|---|---|"]
+    small = cases(2_000_000)
+    for kind in ("plate", "cylinder"):
+        qs = [c["query"] for c in small if c["kind"] == kind]
+        base = dict(out[kind]["tuning"])
+        for g in (1, 2, 4):
+            ctx.set_tuning(**dict(base, groups_per_cu=g))
+            b = tpmc.Batch(dev_mesh[kind], qs)
+            b.launch().results()
+            torch.cuda.synchronize()
+            ctx.phase_probe(reset=True)
+            ms = launch_ms(ctx, b, ctx.tuning, 1)
+            p = ctx.phase_probe(reset=True)
+            b.close()
+
+            def per(c, n):
+                return p[c] / p[n] if p[n] else None
+            rec = {"ms": ms, "waves": p["waves"], "estimate": per("est_cycles", "est_batches"),
+                   "seeding": per("seed_cycles", "seed_batches"), "traversal": per("trav_cycles", "trav_steps"),
+                   "leaf": per("leaf_cycles", "leaf_passes"), "service": per("serve_cycles", "serves")}
+            occ[f"{kind}@{g}"] = rec
+            orows.append(f"| {kind} | {g} | {ms:.2f} | " + " / ".join(
+                "—" if rec[k] is None else f"{rec[k]:.0f}" for k in ("estimate", "seeding", "traversal", "leaf",
+                                                                     "service")) + " |")
+    log("\n".join(orows))
     print(json.dumps({"probe": "batched kernel phases per 64 particles (libtpmc_probe.so)", "launches": out,
-                      "table_md": rows}), flush=True)
+                      "table_md": rows, "occupancy": occ, "occupancy_md": orows}), flush=True)
 
 
 SERVED_MESHES = {"sat1k": 1_000, "sat20k": 20_000, "sat100k": 100_000, "sat500k": 500_000}
