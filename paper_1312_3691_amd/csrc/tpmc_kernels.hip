@@ -667,11 +667,49 @@ __global__ __launch_bounds__(kBlock) void trace_kernel(TraceArgs a) {
 template <int STACK, int MODE>
 constexpr bool kPrecullInstance = STACK <= 32;
 
+// Work is claimed per wave in units of a quarter tile (a whole tile when the
+// tile is not a multiple of 256 particles): a wave's lanes draw particles
+// from its own unit, and when the unit runs out while lanes are still busy
+// the wave goes on with another unit of the same entry instead of draining
+// (lanes in flight keep their absolute particle ids), so waves drain only
+// when their entry is used up.  Where no tally state is shared by the
+// workgroup's waves (global atomics, per-lane LDS tallies, the waves' own
+// totals) each wave also chooses its entries alone and never waits for the
+// others; with workgroup LDS tallies the workgroup chooses the entry together
+// and its waves meet at a barrier only when they leave it (the tallies are
+// flushed then).
+template <int MODE>
+constexpr bool kWaveEntries = MODE == kTallyGlobal || MODE == kTallyLane || MODE == kTallyTotals;
+
+// Claim the next tile (or quarter tile) of the entry list from `scan` on:
+// the current entry first, then the following ones (bounded scan).  Returns
+// the entry, or kNoEntry when every entry is used up; t gets the unit's index.
+constexpr uint32_t kNoEntry = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t claim_unit(const BatchArgs& a, uint32_t& scan, uint32_t units_per_tile,
+                                               unsigned long long& t) {
+  for (uint32_t k = 0; k < a.n_entries; ++k) {
+    const uint64_t cap = a.entry_tiles[scan] * units_per_tile;
+    if (__hip_atomic_load(&a.entry_next[scan], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cap) {
+      t = atomicAdd(&a.entry_next[scan], 1ull);
+      if (t < cap) return scan;
+    }
+    scan = scan + 1 == a.n_entries ? 0u : scan + 1;
+  }
+  return kNoEntry;
+}
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+  return (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v) |
+         ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32);
+}
+
 template <int STACK, int MODE>
 __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   constexpr bool kMayLds = MODE == kTallyLds || MODE == kTallyAuto;
   constexpr bool kPre = kPrecullInstance<STACK, MODE>;
-  constexpr uint32_t kNone = 0xFFFFFFFFu;
+  constexpr bool kWave = kWaveEntries<MODE>;
+  constexpr uint32_t kNone = kNoEntry;
   constexpr uint32_t kRing = 128;  // survivors of the estimate awaiting exact seeding (< 64 + 64)
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
@@ -683,15 +721,16 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
   // per-wave totals [c][wave]: the start of lt, or after the per-triangle area in the mixed mode
   unsigned long long* const wave_tot = MODE == kTallyAuto ? lt + 7u * a.lds_tris : lt;
-  __shared__ unsigned long long tile_sh, next_sh;
+  __shared__ unsigned long long tile_sh;
+  __shared__ unsigned long long w_next_sh[kWaves];  // each wave's next unclaimed particle
   __shared__ uint32_t entry_sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t scan;  // thread 0's position in the entry list
+  uint32_t scan;  // the claiming thread's position in the entry list (thread 0, or each wave's lane 0)
   {
     const uint32_t x = blockIdx.x & 7u, lo = a.xcd_start[x], hi = a.xcd_start[x + 1];
     scan = a.xcd_start[8] == 0u ? blockIdx.x % a.n_entries : (hi > lo ? lo + (blockIdx.x >> 3) % (hi - lo) : lo);
   }
-  uint32_t held = kNone;                     // entry whose partial sums the workgroup holds
+  uint32_t held = kNone;                     // entry whose partial sums the workgroup (wave tiles: wave) holds
   Acc A;
   acc_zero(A);
   PROBE(uint32_t pr = 0u; probe_set<kPrTs>(pr, probe_now()); probe_set<kPrTc>(pr, probe_get(pr, kPrTs));)
@@ -704,31 +743,34 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   uint32_t pc_seen = 0, pc_kept = 0;
   if (MODE == kTallyLane)
     for (int c = 0; c < 2 * 7; ++c) lt[c * kBlock + threadIdx.x] = 0ull;
-  if ((MODE == kTallyTotals || (MODE == kTallyAuto && a.wave_totals)) && threadIdx.x < 7u * kWaves)
-    wave_tot[threadIdx.x] = 0ull;
+  if (MODE == kTallyTotals || (MODE == kTallyAuto && a.wave_totals)) {
+    if (kWave) {  // each wave its own slots (no barrier before its first tally)
+      if (lane < 7) wave_tot[lane * kWaves + wave] = 0ull;
+    } else if (threadIdx.x < 7u * kWaves) {
+      wave_tot[threadIdx.x] = 0ull;
+    }
+  }
+  // claim units per tile (quarter tiles when they stay multiples of 64 particles)
+  const uint32_t units = (a.tile & 255u) == 0u ? 4u : 1u;
   for (;;) {
-    if (threadIdx.x == 0) {
-      // claim a tile: current entry first, then the following ones (bounded scan)
+    uint32_t j;
+    uint64_t tile;  // claim unit within the entry
+    if (kWave) {
       uint32_t found = kNone;
       unsigned long long t = 0;
-      for (uint32_t k = 0; k < a.n_entries; ++k) {
-        const uint64_t cap = a.entry_tiles[scan];
-        if (__hip_atomic_load(&a.entry_next[scan], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < cap) {
-          t = atomicAdd(&a.entry_next[scan], 1ull);
-          if (t < cap) {
-            found = scan;
-            break;
-          }
-        }
-        scan = scan + 1 == a.n_entries ? 0u : scan + 1;
+      if (lane == 0) found = claim_unit(a, scan, units, t);
+      j = __builtin_amdgcn_readfirstlane(found);  // uniform over the wave
+      tile = uniform_u64(t);
+    } else {
+      if (threadIdx.x == 0) {  // the workgroup's entry, and wave 0's first unit of it
+        unsigned long long t = 0;
+        entry_sh = claim_unit(a, scan, units, t);
+        tile_sh = t;
       }
-      entry_sh = found;
-      tile_sh = t;
+      __syncthreads();
+      j = __builtin_amdgcn_readfirstlane(entry_sh);  // uniform over the workgroup
+      tile = uniform_u64(tile_sh);
     }
-    __syncthreads();
-    const uint32_t j = __builtin_amdgcn_readfirstlane(entry_sh);  // uniform over the workgroup
-    const uint64_t tile = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)tile_sh) |
-                          ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(tile_sh >> 32)) << 32);
     if (j != held && held != kNone) {
       // leaving the held query: flush its partial sums
       const QueryDev& qh = a.qs[a.entry_query ? a.entry_query[held] : held];
@@ -750,21 +792,46 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     const QueryDev& q = a.qs[a.entry_query ? a.entry_query[j] : j];
     const bool use_lds = kMayLds && q.per_tri && q.nt <= (uint32_t)kLdsTallyMaxTris;
     if (j != held) {
-      __syncthreads();  // the flush above has read lt
-      if (use_lds)
+      if (!kWave) __syncthreads();  // the flush above has read lt
+      if (use_lds) {
         for (uint32_t i = threadIdx.x; i < q.nt * 7u; i += kBlock) lt[i] = 0ull;
+        __syncthreads();  // cleared before any wave tallies into it
+      }
       held = j;
     }
-    const uint64_t tile_in_q = (a.entry_tile0 ? a.entry_tile0[j] : 0ull) + tile;
-    const uint64_t p_begin = tile_in_q * a.tile;
-    const uint64_t p_end = p_begin + a.tile < q.N ? p_begin + a.tile : q.N;
+    // particles [p_begin, p_end) of claim unit u of the entry (of its tile u / units);
+    // everything is read again at each claim, so nothing of it stays live across the trace loop
+    auto unit_range = [&](uint64_t u, uint64_t& b, uint64_t& e) {
+      const uint32_t sh = (a.tile & 255u) == 0u ? 2u : 0u;
+      const uint64_t tb = ((a.entry_tile0 ? a.entry_tile0[j] : 0ull) + (u >> sh)) * a.tile;
+      b = tb + (u & ((1u << sh) - 1u)) * (a.tile >> sh);
+      e = b + (a.tile >> sh);
+      if (e > tb + a.tile) e = tb + a.tile;
+      if (e > q.N) e = q.N;
+    };
+    bool have = true;  // the wave holds a unit of entry j
+    // the other waves claim their own first unit of the workgroup's entry (wave number
+    // read into a scalar register, so that the branch and what it sets stay wave-uniform)
+    if (!kWave && __builtin_amdgcn_readfirstlane(wave) != 0) {
+      unsigned long long t = 0;
+      if (lane == 0) t = atomicAdd(&a.entry_next[j], 1ull);
+      tile = uniform_u64(t);
+      have = tile < a.entry_tiles[j] * units;
+    }
+    uint64_t p_begin = 0, p_end = 0;
+    if (have) unit_range(tile, p_begin, p_end);
+    if (lane == 0) w_next_sh[wave] = p_begin;  // the next unclaimed particle of the wave's unit
     long long* qtally = q.per_tri ? a.tally_base + q.tally_offset : nullptr;
     const Node* nodes = uniform_ptr(q.nodes);
     const TriRec* tris = uniform_ptr(q.tris);
     const uint32_t* orig = uniform_ptr(q.orig);
-    if (threadIdx.x == 0) next_sh = p_begin;
-    __syncthreads();
     PROBE(probe_since<kPrClaimCyc>(pr, kPrTc); probe_add<kPrClaims>(pr, 1u);)
+    // next 64 particle ids of the wave's unit
+    auto claim64 = [&]() -> uint64_t {
+      const uint64_t b = uniform_u64(w_next_sh[wave]);
+      if (lane == 0) w_next_sh[wave] = b + 64u;
+      return b;
+    };
 
     Lane L;
     Seg s;
@@ -774,7 +841,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     s.cur = kDone;
     const uint32_t max_steps = __builtin_amdgcn_readfirstlane(2u * q.nt + 64u);
     uint32_t guard = 0;                // steps since the last service pass (wave-uniform)
-    bool exhausted = false;            // wave-uniform: the tile has no particles left to claim
+    bool exhausted = !have;            // wave-uniform: the unit has no particles left to claim
+    bool dry = !have;                  // wave-uniform: the entry has no units left
     uint32_t q_head = 0, q_count = 0;  // wave-uniform queue state
     uint64_t q_pid0 = 0;               // particle id of queue slot 0
     uint32_t s_head = 0, s_count = 0;  // wave-uniform survivor ring state (two-stage seeding)
@@ -818,15 +886,27 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           PROBE(probe_since<kPrServeCyc>(pr, kPrTp);)
         }
         const uint64_t dead = ballot(!L.live);
+        if (dead != 0ull && exhausted && !dry && q_count == 0 && s_count == 0) {
+          // the unit is used up (survivor ring and queue empty, so no offset refers to it):
+          // go on with the entry's next unit while the other lanes are still busy
+          unsigned long long t = 0;
+          if (lane == 0) t = atomicAdd(&a.entry_next[j], 1ull);
+          t = uniform_u64(t);
+          if (t < a.entry_tiles[j] * units) {
+            unit_range(t, p_begin, p_end);
+            if (lane == 0) w_next_sh[wave] = p_begin;
+            exhausted = false;
+            PROBE(probe_add<kPrClaims>(pr, 1u);)
+          } else {
+            dry = true;
+          }
+        }
         if (kPre && dead != 0ull) {
           while (q_count == 0 && !(exhausted && s_count == 0)) {  // wave-uniform
             if (s_count < 64 && !exhausted) {
               // stage 1: claim 64 particles, keep those the estimate cannot rule out
               PROBE(probe_set<kPrTp>(pr, probe_now());)
-              unsigned long long base = 0;
-              if (lane == 0) base = atomicAdd(&next_sh, 64ull);
-              base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
-                     ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
+              const uint64_t base = claim64();
               if (base >= p_end) {
                 exhausted = true;
               } else {
@@ -895,10 +975,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
           while (q_count == 0 && !exhausted) {  // wave-uniform
             // claim and seed the next (up to) 64 particles, one per lane
             PROBE(probe_set<kPrTp>(pr, probe_now());)
-            unsigned long long base = 0;
-            if (lane == 0) base = atomicAdd(&next_sh, 64ull);
-            base = (unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)base) |
-                   ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32);
+            const uint64_t base = claim64();
             if (base >= p_end) {
               exhausted = true;
             } else {
@@ -990,7 +1067,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     PROBE(probe_set<kPrTc>(pr, probe_now());)
     if (kPre && pc_off_now && lane == 0)  // published at the tile's end, outside the trace loop
       __hip_atomic_store(a.scal_base + q.scalar_offset + kPrecullOff, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();  // every wave is done with the tile; tile_sh / entry_sh / next_sh may be reused
+    if (!kWave) __syncthreads();  // every wave is done with the entry; entry_sh / tile_sh may be reused
   }
   PROBE(probe_set<kPrWaves>(pr, 1u); probe_set<kPrCycles>(pr, probe_now() - probe_get(pr, kPrTs));
         if (lane < kProbeSlots) atomicAdd(&g_probe[lane], (unsigned long long)pr);)

@@ -33,9 +33,11 @@ struct TraceArgs {
 // One persistent launch covers n_entries entries; entry j is entry_tiles[j]
 // tiles of query entry_query[j] starting at tile entry_tile0[j] (a whole batch:
 // entry j = query j from tile 0; a serving step: any slots, any ranges).
-// Workgroups claim tiles entry by entry (entry_next[j] counts the claimed
-// tiles), so a workgroup stays on one query and flushes its partial sums only
-// when it moves to another.
+// Waves claim work entry by entry in units of a quarter tile (a whole tile
+// when the tile is not a multiple of 256 particles; entry_next[j] counts the
+// claimed units), so a wave stays on one query and flushes its partial sums
+// only when it moves to another.  With workgroup LDS tallies the workgroup's
+// waves move to another entry together.
 struct BatchArgs {
   const QueryDev* qs;              // query / slot table (meshes referenced per query)
   const uint32_t* entry_query;     // [n_entries] or null (entry j is query j)
