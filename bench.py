@@ -1098,14 +1098,15 @@ def served_measure(args, n_warm, n_meas, load_fracs, fifo_requests):
     meshes = {k: ctx.build_mesh(*I.satellite(v, seed=i), builder=args.bvh) for i, (k, v) in enumerate(sizes.items())}
     max_slots = int(args.slots)
     pool_words = int(args.hbm_budget_gb * 2 ** 30) // 8
-    # tiles of 32768 particles and a refill threshold of 32 lanes: the tuner, timing one batch,
+    # tiles of 16384 particles and a refill threshold of 32 lanes: the tuner, timing one batch,
     # cannot see the per-step costs of claiming tiles (smaller tiles) and of the last tiles of a
     # step (larger ones), nor how a step's mix of meshes shares the waves.  Measured on the
-    # pipelined stream (1000 requests): tiles 16384 / 32768 / 65536 gave 3600 / 3854 / 3669 req/s
-    # (one-stage seeding); refill 16 / 24 / 32 / 40 / 48 lanes gave 4091 / 4135 / 4171 / 4069 /
-    # 3815 req/s, workgroups per CU 4 / 8 / 16 at refill 32 gave 4171 / 4176 / 4163.
+    # pipelined stream at saturation (2000 requests, work claimed per wave in quarter tiles):
+    # tiles 16384 / 32768 / 65536 gave 4505 / 4439 / 3996 req/s; refill 16 / 24 / 32 / 40 / 48
+    # lanes gave 4091 / 4135 / 4171 / 4069 / 3815 req/s and workgroups per CU 4 / 8 / 16 at
+    # refill 32 gave 4171 / 4176 / 4163 (workgroup tiles, 1000 requests).
     tuning = tune_for(args, meshes["sat100k"], [q for m, q in reqs if m == "sat100k"][:64],
-                      hold={"tile_particles": 32768, "refill_lanes": 32})
+                      hold={"tile_particles": 16384, "refill_lanes": 32})
     # the step budget is a particle count, so that the tuned tile size does not change it
     tiles_per_step = max(1, int(args.particles_per_step) // int(tuning["tile_particles"]))
     ex = GpuExecutor(ctx, meshes, max_slots=max_slots, pool_words=pool_words)

@@ -714,10 +714,10 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
   __shared__ int stk[STACK][kBlock];
   __shared__ float qbuf[kBlock / 64][6][64];
   // queue slot -> particle: its offset in its seeding batch, or (two-stage
-  // seeding) in the tile
+  // seeding) in the wave's unit
   __shared__ uint8_t qlane[kPre ? 1 : kBlock / 64][64];
   __shared__ uint16_t qoff[kPre ? kBlock / 64 : 1][64];
-  __shared__ uint16_t ring[kPre ? kBlock / 64 : 1][kPre ? kRing : 1];  // survivor offsets in the tile
+  __shared__ uint16_t ring[kPre ? kBlock / 64 : 1][kPre ? kRing : 1];  // survivor offsets in the unit
   extern __shared__ unsigned long long lt[];  // tallies in LDS, sized at launch (tally_lds_bytes)
   // per-wave totals [c][wave]: the start of lt, or after the per-triangle area in the mixed mode
   unsigned long long* const wave_tot = MODE == kTallyAuto ? lt + 7u * a.lds_tris : lt;
@@ -730,14 +730,14 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
     const uint32_t x = blockIdx.x & 7u, lo = a.xcd_start[x], hi = a.xcd_start[x + 1];
     scan = a.xcd_start[8] == 0u ? blockIdx.x % a.n_entries : (hi > lo ? lo + (blockIdx.x >> 3) % (hi - lo) : lo);
   }
-  uint32_t held = kNone;                     // entry whose partial sums the workgroup (wave tiles: wave) holds
+  uint32_t held = kNone;                     // entry whose partial sums the wave (and workgroup) holds
   Acc A;
   acc_zero(A);
   PROBE(uint32_t pr = 0u; probe_set<kPrTs>(pr, probe_now()); probe_set<kPrTc>(pr, probe_get(pr, kPrTs));)
   // two-stage seeding, wave-uniform: particles the estimate removed (for the
   // held query), and the estimate's yield so far on it.  A wave that finds
   // more than 60 % of a query's particles surviving the estimate switches it
-  // off for the query (its kPrecullOff slot, read at every tile), since the
+  // off for the query (its kPrecullOff slot, read whenever a wave takes up the query), since the
   // estimate then costs more than it saves.
   uint64_t pre = 0;
   uint32_t pc_seen = 0, pc_kept = 0;
@@ -1045,8 +1045,8 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
             __builtin_amdgcn_wave_barrier();
           }
         }
-        // nothing in flight and nothing left: the tile is done (with no lane
-        // live but particles left, the next iteration claims more)
+        // nothing in flight and nothing left: the wave is done with the entry
+        // (with no lane live but particles left, the next iteration claims more)
         if (ballot(L.live) == 0ull && exhausted && q_count == 0 && s_count == 0) break;
         make_ray(r, L.ox, L.oy, L.oz, L.wx, L.wy, L.wz);
         guard = 0;
@@ -1065,7 +1065,7 @@ __global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
       PROBE(probe_since<kPrTravCyc>(pr, kPrTp);)
     }
     PROBE(probe_set<kPrTc>(pr, probe_now());)
-    if (kPre && pc_off_now && lane == 0)  // published at the tile's end, outside the trace loop
+    if (kPre && pc_off_now && lane == 0)  // published when the wave leaves the entry, outside the trace loop
       __hip_atomic_store(a.scal_base + q.scalar_offset + kPrecullOff, 1ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!kWave) __syncthreads();  // every wave is done with the entry; entry_sh / tile_sh may be reused
   }
