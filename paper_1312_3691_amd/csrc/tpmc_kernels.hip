@@ -354,8 +354,11 @@ __device__ __forceinline__ uint32_t below(uint64_t m) {
 // and kPrTp hold the clock at the wave's start, at the current tile claim and
 // at the current phase's start.  Lanes are written with v_writelane and read
 // with v_readlane (no lane masks, no long-lived scalar registers), so the
-// instrumented kernel keeps the ordinary one's registers and occupancy.  At
-// exit lane k adds its slot to g_probe.
+// instrumented kernel needs at most a register or two more than the ordinary
+// one; the instances that run four waves per SIMD are held to that occupancy
+// (amdgpu_waves_per_eu, at the cost of a few spilled dwords), so that the
+// probe measures the kernel at its own occupancy.  At exit lane k adds its
+// slot to g_probe.
 #if TPMC_PHASE_PROBE
 #define PROBE(...) __VA_ARGS__
 constexpr int kPrTp = 29, kPrTs = 30, kPrTc = 31;
@@ -705,7 +708,7 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 }
 
 template <int STACK, int MODE>
-__global__ __launch_bounds__(kBlock) void batch_kernel(BatchArgs a) {
+__global__ __launch_bounds__(kBlock) PROBE(__attribute__((amdgpu_waves_per_eu(STACK <= 32 && MODE != kTallyAuto ? 4 : 1)))) void batch_kernel(BatchArgs a) {
   constexpr bool kMayLds = MODE == kTallyLds || MODE == kTallyAuto;
   constexpr bool kPre = kPrecullInstance<STACK, MODE>;
   constexpr bool kWave = kWaveEntries<MODE>;
