@@ -712,6 +712,7 @@ __global__ __launch_bounds__(kBlock) PROBE(__attribute__((amdgpu_waves_per_eu(ST
   constexpr bool kMayLds = MODE == kTallyLds || MODE == kTallyAuto;
   constexpr bool kPre = kPrecullInstance<STACK, MODE>;
   constexpr bool kWave = kWaveEntries<MODE>;
+  constexpr uint32_t kSteps = STACK >= 32 ? 2u : 1u;  // traversal steps per round of the trace loop
   constexpr uint32_t kNone = kNoEntry;
   constexpr uint32_t kRing = 128;  // survivors of the estimate awaiting exact seeding (< 64 + 64)
   __shared__ int stk[STACK][kBlock];
@@ -1055,13 +1056,25 @@ __global__ __launch_bounds__(kBlock) PROBE(__attribute__((amdgpu_waves_per_eu(ST
         guard = 0;
       }
       // as in the plain path: a bound only against a damaged tree, counted
-      if (++guard > max_steps) {
+      if ((guard += kSteps) > kSteps * max_steps) {
         A.guard += lanes(L.live && s.cur != kDone);
         s.cur = kDone;
       }
       PROBE(const uint32_t nl = (uint32_t)lanes(L.live && seg_traversing(s)); probe_add<kPrTravLanes>(pr, nl);
             probe_add<kPrTravSteps>(pr, nl != 0u ? 1u : 0u); probe_set<kPrTp>(pr, probe_now());)
       if (L.live && seg_traversing(s)) {
+        uint32_t n0 = 0, n1 = 0;
+        trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
+      }
+      // deep trees (32-slot stacks): a second step before the next round of checks
+      // (refill, leaf phase, guard), whose cost there is worth sparing for every
+      // other step (attitude sweep -2.4 %, satellite -1.2 %; neutral on shallow trees)
+      PROBE(if (kSteps == 2) {
+        const uint32_t nl2 = (uint32_t)lanes(L.live && seg_traversing(s));
+        probe_add<kPrTravLanes>(pr, nl2);
+        probe_add<kPrTravSteps>(pr, nl2 != 0u ? 1u : 0u);
+      })
+      if (kSteps == 2 && L.live && seg_traversing(s)) {
         uint32_t n0 = 0, n1 = 0;
         trav_step<STACK, false>(nodes, tris, orig, r, L.prev, s, stk, n0, n1);
       }
