@@ -572,7 +572,10 @@ __device__ __forceinline__ void latitude_G32_est(const QueryDev& q, float t, flo
   d2G = q.Sf * (float)kSqrtPi * cc;
 }
 
-// The estimated ray (o, w); false when the estimate gives up.
+// The estimated ray (o, w); false when the estimate gives up.  The per-particle
+// conditions are gathered into one flag rather than taken as early returns, so
+// that the lanes stay converged (table lookups use clamped indices throughout;
+// what a given-up particle computes is discarded).
 __device__ inline bool precull_estimate(const QueryDev& q, const float* __restrict__ lat_tab,
                                         const float* __restrict__ vn_tab, uint64_t pid, float o[3], float w[3]) {
   if (q.box) return false;
@@ -581,6 +584,7 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
   // latitude mu = sin(phi)
   const float ua = unif32_hi(r0.a), uam = unif32_hi(~r0.a);  // u and 1 - u
   float mu;
+  bool ok = true;
   if (q.s_zero) {
     mu = 2.0f * ua - 1.0f;
   } else {
@@ -595,10 +599,10 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
       latitude_G32_est(q, mu, G, dG, d2G);
       dx = halley_step(mu, G - ua * q.Zf, dG, d2G, lo, hi);
     }
-    if (!(dx <= 1e-5f)) return false;
+    ok = dx <= 1e-5f;
   }
   const float cphi = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
-  if (!(cphi >= 0.05f)) return false;
+  ok = ok && cphi >= 0.05f;
   // inward normal speed at s = S mu
   const float s = q.s_zero ? 0.0f : q.Sf * mu;
   const float es2 = __expf(-s * s);
@@ -606,15 +610,14 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
   const float erfcs = s >= 0.0f ? ta : 2.0f - ta, erfcms = s >= 0.0f ? 2.0f - ta : ta;
   const float erfs = s >= 0.0f ? 1.0f - ta : ta - 1.0f;
   const float chi = es2 + (float)kSqrtPi * s * erfcms;
-  if (!(s > -9.0f)) return false;
   const float uc = unif32_hi(r0.c), ucm = unif32_hi(~r0.c);
   const float hi0 = fmaxf(s, 0.0f) + 7.0f;
   const float fs = (s - kVnS0) * (1.0f / kVnDS);
-  if (!(fs >= 0.0f && fs <= (float)(kVnNS - 1))) return false;  // inside the table's s range only
+  ok = ok && s > -9.0f && fs >= 0.0f && fs <= (float)(kVnNS - 1);  // inside the table's s range only
   const float tv = hw_ln(uc) - hw_ln(ucm);
-  float wn = bilinear_start(vn_tab, kVnNS, kVnNT, fs,
+  float wn = bilinear_start(vn_tab, kVnNS, kVnNT, fminf(fmaxf(fs, 0.0f), (float)(kVnNS - 1)),
                             fminf(fmaxf((tv - kVnT0) * (1.0f / kVnDT), 0.0f), (float)(kVnNT - 1)));
-  if (!(wn > 0.0f && wn < hi0)) return false;
+  ok = ok && wn > 0.0f && wn < hi0;
   {
     float lo = 0.0f, hi = hi0, F, dF, d2F, dx = 0.0f;
 #pragma unroll
@@ -622,7 +625,7 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
       normal_speed_F32(s, es2, erfs, erfcs, erfcms, wn, F, dF, d2F);
       dx = halley_step(wn, F - uc * chi, dF, d2F, lo, hi);
     }
-    if (!(dx <= 1e-5f * wn)) return false;
+    ok = ok && dx <= 1e-5f * wn;
   }
   // tangential Gaussians (Box-Muller) and the angles; v_sin / v_cos take revolutions
   const float rad = sqrtf(-2.0f * hw_ln(unif32_hi(r0.d)));
@@ -640,14 +643,14 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
     o[i] = q.c0f[i] - q.rf * ni;
     w[i] = wn * ni + wt1 * t1i - g2 * di;
   }
-  return true;
+  return ok;
 }
 
 __device__ inline bool precull_may_enter(const QueryDev& q, const float* __restrict__ lat_tab,
                                          const float* __restrict__ vn_tab, const Node* __restrict__ nodes,
                                          uint64_t pid) {
-  float o[3], w[3];
-  if (!precull_estimate(q, lat_tab, vn_tab, pid, o, w)) return true;
+  float o[3] = {0.0f, 0.0f, 0.0f}, w[3] = {0.0f, 0.0f, 0.0f};
+  const bool ok = precull_estimate(q, lat_tab, vn_tab, pid, o, w);
   Ray r;
   r.ox = o[0]; r.oy = o[1]; r.oz = o[2];
   r.idx = __builtin_amdgcn_rcpf(w[0]);
@@ -657,8 +660,9 @@ __device__ inline bool precull_may_enter(const QueryDev& q, const float* __restr
   const Node& nd = nodes[0];
   const float inf = __builtin_inff();
   float tn;
-  return slab(r, nd.lo0x - m, nd.lo0y - m, nd.lo0z - m, nd.hi0x + m, nd.hi0y + m, nd.hi0z + m, inf, tn) ||
-         slab(r, nd.lo1x - m, nd.lo1y - m, nd.lo1z - m, nd.hi1x + m, nd.hi1y + m, nd.hi1z + m, inf, tn);
+  const bool h0 = slab(r, nd.lo0x - m, nd.lo0y - m, nd.lo0z - m, nd.hi0x + m, nd.hi0y + m, nd.hi0z + m, inf, tn);
+  const bool h1 = slab(r, nd.lo1x - m, nd.lo1y - m, nd.lo1z - m, nd.hi1x + m, nd.hi1y + m, nd.hi1z + m, inf, tn);
+  return !ok || h0 || h1;  // a given-up estimate keeps the particle
 }
 
 // ---------------------------------------------------------------------------
