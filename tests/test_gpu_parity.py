@@ -433,17 +433,22 @@ def test_batch_equals_plain_bitwise(ctx, T, flags):
 
 def test_tuning_does_not_change_results(ctx, T):
     """Every launch tuning (refill threshold, tile size, workgroups per CU) gives
-    bit-identical plain and batched results, on a deep and a 2-triangle mesh."""
+    bit-identical plain and batched results, on a deep mesh (global tallies,
+    waves choosing their entries alone), a 256-triangle mesh (workgroup LDS
+    tallies, entries chosen per workgroup) and a 2-triangle mesh (per-lane
+    tallies); tiles of 64 and 320 particles are claimed whole, the others in
+    quarters."""
     import ctypes
     base = ctx.tuning
     try:
-        for V, Tr in (I.satellite(3000), I.plate()):
+        for V, Tr in (I.satellite(3000), I.capped_cylinder(), I.plate()):
             mesh = ctx.build_mesh(V, Tr)
             qs = _batch_queries(4)
             ref = None
             for t in ({"refill_lanes": 1, "tile_particles": 64, "groups_per_cu": 1, "plain_groups_per_cu": 1},
                       {"refill_lanes": 64, "tile_particles": 4096, "groups_per_cu": 32, "plain_groups_per_cu": 32},
-                      {"refill_lanes": 33, "tile_particles": 1 << 16, "groups_per_cu": 3, "plain_groups_per_cu": 3}):
+                      {"refill_lanes": 33, "tile_particles": 1 << 16, "groups_per_cu": 3, "plain_groups_per_cu": 3},
+                      {"refill_lanes": 24, "tile_particles": 320, "groups_per_cu": 8, "plain_groups_per_cu": 4}):
                 ctx.set_tuning(**t)
                 plain, pr = T.run(mesh, qs, A_ref=1.0)
                 b = T.Batch(mesh, qs)
