@@ -49,10 +49,10 @@ OPS_SEED = 950.0   # per particle: 2 Philox blocks + FP64 inverse-CDF seeding + 
 OPS_NODE = 40.0    # per BVH node visit: two slab tests + stack
 OPS_TRI = 45.0     # per watertight triangle test
 OPS_HIT = 225.0    # per hit: Philox block + re-emission + tally
-OPS_PRECULL = 565.0  # per particle the batched path's seeding estimate removes: 2 Philox blocks (250) + two
-                     # FP32 inverse-CDF estimates (210) + frame, Box-Muller and angles (50) + grown two-box test
-                     # (55), in place of OPS_SEED and the one root-node visit such a particle costs on the
-                     # plain path
+OPS_PRECULL = 485.0  # per particle the batched path's seeding estimate removes: 2 Philox blocks (250) + the
+                     # FP32 normal-speed estimate, start and two Halley steps (105) + the latitude from the fine
+                     # table (25) + frame, Box-Muller and angles (50) + grown two-box test (55), in place of
+                     # OPS_SEED and the one root-node visit such a particle costs on the plain path
 KERNEL_SOURCES = ["tpmc_device.hpp", "tpmc_math.hpp", "tpmc_kernels.hip", "tpmc_internal.h"]
 
 

@@ -369,8 +369,9 @@ tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots
 /* ---- Check of the batched path's two-stage seeding ----
  * The persistent kernel (batches and server steps) seeds in two stages: an
  * FP32 estimate of each particle's first ray from its own variates (Sec.
- * III.A.1-3 in FP32, tabulated starts and two Halley steps per inverse-CDF
- * solve) is tested against the BVH root's boxes grown on every side by 2 % of
+ * III.A.1-3 in FP32: the latitude from a fine table without iteration, the
+ * normal speed from a tabulated start and two Halley steps) is tested against
+ * the BVH root's boxes grown on every side by 2 % of
  * the CV radius, and only the particles it does not rule out are seeded
  * exactly (FP64) and traced; the others are misses either way, so no result
  * field other than tpmc_result.preculled depends on it.  The margin rests on
@@ -378,8 +379,9 @@ tpmc_status tpmc_ceiling_lds_atomic(tpmc_ctx ctx, void* dev_sink, uint32_t slots
  * [0, q->n_particles) of the query it returns the largest distance between
  * the estimated and the exact ray (|o_est - o| + 2 r |w_est/|w_est| - w/|w||)
  * as a fraction of the margin, over the particles the estimate covers (it
- * gives up near the poles mu = +-1 and when a solve's start is poor; those
- * particles are always seeded exactly), and their number.  Workspace: the
+ * gives up near the poles mu = +-1, outside its tables' ranges and when the
+ * speed's solve has not converged; those particles are always seeded
+ * exactly), and their number.  Workspace: the
  * caller's device memory, >= TPMC_PRECULL_CHECK_BYTES, 256-byte aligned.
  * Synchronises the context's stream. */
 #define TPMC_PRECULL_CHECK_BYTES 1024

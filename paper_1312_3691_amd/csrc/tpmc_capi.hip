@@ -291,13 +291,23 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
     q->e2f[k] = (float)q->e2[k];
   }
   q->Sf = (float)q->S;
-  q->Zf = (float)q->Z;
-  q->erfSf = (float)q->erfS;
-  q->erfcSf = (float)q->erfcS;
-  q->expmS2f = (float)q->expmS2;
   q->rf = (float)q->r;
-  q->lat_kf = (float)q->lat_k;
-  q->lat_row = q->s_zero ? -1.0f : (float)(std::log(S / 0.05) / 0.05);  // ln(S / S0) / dL of the table
+  // the seeding estimate's fine latitude table: the four rows around ln S and
+  // their cubic Lagrange weights (nodes -1, 0, 1, 2 around the row below ln S)
+  q->lat_f0 = -1;
+  for (int k = 0; k < 4; ++k) q->lat_fw[k] = 0.0f;
+  if (!q->s_zero && S >= kLatFSmin && S <= kLatFSmax) {
+    const double pos = (std::log(S) - kLatFL0) / kLatFDL;
+    const int i = (int)std::floor(pos);
+    const double f = pos - i;
+    if (i - 1 >= 0 && i + 2 <= kLatFNS - 1) {
+      q->lat_f0 = i - 1;
+      q->lat_fw[0] = (float)(-f * (f - 1.0) * (f - 2.0) / 6.0);
+      q->lat_fw[1] = (float)((f + 1.0) * (f - 1.0) * (f - 2.0) / 2.0);
+      q->lat_fw[2] = (float)(-(f + 1.0) * f * (f - 2.0) / 2.0);
+      q->lat_fw[3] = (float)((f + 1.0) * f * (f - 1.0) / 6.0);
+    }
+  }
   const double tau = std::sqrt(in->T_w / in->T_inf);
   q->tau = (float)tau;
   q->alpha = (float)in->alpha;

@@ -156,6 +156,9 @@ __device__ __forceinline__ T halley_step(T& x, T f, T df, T d2f, T& lo, T& hi) {
 constexpr int kLatNS = 107, kLatNT = 257;
 constexpr float kLatS0 = 0.05f, kLatDL = 0.05f, kLatT0 = -24.0f, kLatDT = 0.1875f;
 
+// The seeding estimate takes the same root from a fine table as it is, with
+// no iteration (layout kLatF* in tpmc_internal.h, filled by lat_fine_kernel).
+
 __device__ __forceinline__ float latitude_start(const float* __restrict__ tab, float S, double u) {
   const float fs = logf(S * (1.0f / kLatS0)) * (1.0f / kLatDL);
   const float uf = (float)u;
@@ -523,23 +526,24 @@ __device__ __forceinline__ bool slab(const Ray& r, float lox, float loy, float l
 // root is a miss whatever its exact state, so its exact FP64 seeding (above)
 // is work without effect; on small or flat bodies most particles are such.
 // precull_may_enter estimates the particle's ray from the same variates in
-// FP32 (the tabulated starts and two FP32 Halley steps for each inverse-CDF
-// solve, the hardware exp, log, sine and cosine, the frame in FP32) and tests
-// it against the root's two boxes grown by kPrecullMargin CV radii on every
-// side.  Returns false only if that grown test fails, i.e. only for particles
-// whose exact ray misses the root's boxes:
-//  * by cubic convergence the error left after a Halley step dx is about
-//    C dx^3; the estimate gives up (the particle is seeded exactly) unless
-//    each solve's second step is below 1e-5 (of the speed, for the speed), so
-//    what remains is near the FP32 rounding of the solves; it also gives up
-//    outside the start tables' ranges of S and s;
+// FP32 (the latitude from a fine table without iteration, the normal speed
+// from its tabulated start and two FP32 Halley steps, the hardware exp, log,
+// sine and cosine, the frame in FP32) and tests it against the root's two
+// boxes grown by kPrecullMargin CV radii on every side.  Returns false only if
+// that grown test fails, i.e. only for particles whose exact ray misses the
+// root's boxes:
+//  * the fine latitude table (cubic in ln S, linear in the logit) leaves an
+//    error d in mu of about 1e-5; the speed's Halley steps leave about C dx^3
+//    after a second step dx, and the estimate gives up (the particle is
+//    seeded exactly) unless that step is below 1e-5 of the speed; it also
+//    gives up outside the tables' ranges of S and s;
 //  * a latitude error d moves cos(phi) by d |mu| / cos(phi), so the estimate
 //    gives up for cos(phi) < 0.05 (mu within 1.25e-3 of +-1); elsewhere the
 //    point and the direction move by at most ~20 d, relative to r and to |w|;
 //  * along the at most 2 r of path inside the CV, the estimated ray then stays
-//    within ~60 d r of the exact one, and the margin (0.02 r) exceeds that
-//    bound by orders of magnitude for the ~1e-7 that the solves leave; the
-//    hardware sine, cosine and logarithm add errors of the same order.
+//    within ~60 d r of the exact one: a few hundredths of the margin (0.02 r)
+//    for the table's d, and far less for the rounding of the FP32 solves and
+//    the hardware sine, cosine and logarithm.
 // tpmc_precull_check measures the distance between estimated and exact rays.
 // Box control volumes are not estimated (always true).
 // ---------------------------------------------------------------------------
@@ -547,9 +551,7 @@ constexpr float kPrecullMargin = 0.02f;
 
 __device__ __forceinline__ float unif32_hi(uint32_t k) { return ((float)k + 0.5f) * 0x1p-32f; }  // ~unif64(k)
 
-// Estimate-only forms (FP32, hardware log2 / exp2; the exact path keeps its
-// own): tabulated starts from the precomputed table row of S, and G with its
-// erf-term factor precomputed.
+// Estimate-only forms (FP32, hardware log2; the exact path keeps its own).
 __device__ __forceinline__ float hw_ln(float x) { return 0.69314718f * __builtin_amdgcn_logf(x); }
 
 // fs in [0, ns - 1], ft in [0, nt - 1]
@@ -559,17 +561,6 @@ __device__ __forceinline__ float bilinear_start(const float* __restrict__ tab, i
   const float* r0 = tab + i * nt + j;
   const float* r1 = r0 + nt;
   return (1.0f - a) * ((1.0f - b) * r0[0] + b * r0[1]) + a * ((1.0f - b) * r1[0] + b * r1[1]);
-}
-
-__device__ __forceinline__ void latitude_G32_est(const QueryDev& q, float t, float& G, float& dG, float& d2G) {
-  const float St = q.Sf * t;
-  const float e = __expf(-St * St);
-  const float ey = e * erfcx32(fabsf(St));       // erfc(|S t|)
-  const float cc = St >= 0.0f ? 2.0f - ey : ey;  // erfc(-S t)
-  const float E = St < -1.0f ? cc - q.erfcSf : (cc - 1.0f) + q.erfSf;
-  G = q.lat_kf * E + 0.5f * (float)kSqrtPi * q.Sf * (t * t * cc - q.erfcSf) + 0.5f * (t * e + q.expmS2f);
-  dG = e + (float)kSqrtPi * St * cc;
-  d2G = q.Sf * (float)kSqrtPi * cc;
 }
 
 // The estimated ray (o, w); false when the estimate gives up.  The per-particle
@@ -588,18 +579,17 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
   if (q.s_zero) {
     mu = 2.0f * ua - 1.0f;
   } else {
-    // inside the table's S range only (and not the small-S form of G)
-    if (!(q.lat_row >= 0.0f && q.lat_row <= (float)(kLatNS - 1)) || q.Sf < 0.25f) return false;
+    // from the fine table, inside its S range only (the host sets lat_f0 = -1 outside)
+    if (q.lat_f0 < 0) return false;
     const float t = hw_ln(ua) - hw_ln(uam);
-    const float ft = fminf(fmaxf((t - kLatT0) * (1.0f / kLatDT), 0.0f), (float)(kLatNT - 1));
-    mu = fminf(fmaxf(bilinear_start(lat_tab, kLatNS, kLatNT, q.lat_row, ft), -1.0f), 1.0f);
-    float lo = -1.0f, hi = 1.0f, G, dG, d2G, dx = 0.0f;
+    const float ft = fminf(fmaxf((t - kLatFT0) * (1.0f / kLatFDT), 0.0f), (float)(kLatFNT - 1));
+    const int j = min((int)ft, kLatFNT - 2);
+    const float b = ft - (float)j;
+    const float* r = lat_tab + q.lat_f0 * kLatFNT + j;
+    float m = 0.0f;
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      latitude_G32_est(q, mu, G, dG, d2G);
-      dx = halley_step(mu, G - ua * q.Zf, dG, d2G, lo, hi);
-    }
-    ok = dx <= 1e-5f;
+    for (int k = 0; k < 4; ++k) m += q.lat_fw[k] * ((1.0f - b) * r[k * kLatFNT] + b * r[k * kLatFNT + 1]);
+    mu = fminf(fmaxf(m, -1.0f), 1.0f);
   }
   const float cphi = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
   ok = ok && cphi >= 0.05f;

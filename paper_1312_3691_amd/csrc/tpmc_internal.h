@@ -42,6 +42,21 @@ enum ProbeSlot {
   kProbeSlots = 24
 };
 
+// Fine table of the latitude root mu of G(mu) = u Z(S) for the seeding
+// estimate, which takes it as it is (no iteration): rows ln S = kLatFL0 +
+// i kLatFDL (S from about 0.23 to 10.6), interpolated by the four-point
+// Lagrange cubic in ln S whose rows and weights the host sets per query
+// (QueryDev::lat_f0, lat_fw), columns t = kLatFT0 + j kLatFDT in the logit
+// t = ln(u / (1 - u)), linear.  Filled once per device by FP64 bisection.
+// Where cos(phi) >= 0.05 its error in mu is about 1e-5 (a dense host
+// evaluation of the interpolation against FP64 roots found at most 9e-6,
+// 3.5e-5 of cos(phi)); tpmc_precull_check measures the rays it gives against
+// the exact seeding.
+constexpr int kLatFNS = 192, kLatFNT = 3073;
+constexpr double kLatFL0 = -1.45, kLatFDL = 0.02;
+constexpr float kLatFT0 = -24.0f, kLatFDT = 1.0f / 64.0f;
+constexpr double kLatFSmin = 0.25, kLatFSmax = 10.0;  // the S range the estimate takes from it
+
 struct Node;
 struct TriRec;
 
@@ -83,9 +98,9 @@ struct alignas(16) QueryDev {
   double lat_k;                      // sqrt(pi) / (4 S), the erf term's factor in the latitude CDF
   // FP32 copies for the seeding estimate of the pre-cull (precull_may_enter)
   float e1f[3], e2f[3];
-  float Sf, Zf, erfSf, erfcSf, expmS2f, rf;
-  float lat_kf;   // sqrt(pi) / (4 S)
-  float lat_row;  // row coordinate of S in the latitude start table (may lie outside it)
+  float Sf, rf;
+  int32_t lat_f0;     // first of the four fine-table rows around ln S (-1: the estimate gives up)
+  float lat_fw[4];    // their cubic Lagrange weights at ln S
 };
 
 // Device result of the finalisation kernel (mirrors tpmc_result).

@@ -44,6 +44,7 @@ int grid_for(uint64_t n, int cap) {
 // Starting points of the latitude and normal-speed solves (latitude_start,
 // normal_speed_start); part of the code object, filled once per device.
 __device__ float g_lat_start[kLatNS * kLatNT];
+__device__ float g_lat_fine[kLatFNS * kLatFNT];  // the seeding estimate's latitude table
 __device__ float g_vn_start[kVnNS * kVnNT];
 // sin and cos of 2 pi j / 256, j = 0..255 (sincos_2pi_draw)
 __device__ double g_sc_tab[512];
@@ -77,6 +78,32 @@ __global__ void lat_table_kernel(float* __restrict__ tab, const double* __restri
   q.expmS2 = exp(-q.S * q.S);
   q.lat_k = kSqrtPi / (4.0 * q.S);
   const double t = (double)kLatT0 + (double)(i % kLatNT) * (double)kLatDT;
+  const double u = 1.0 / (1.0 + exp(-t));
+  double Z, G, dG, d2G, e, ta;
+  latitude_G(q, ee, 1.0, Z, dG, d2G, e, ta);
+  const double target = u * Z;
+  double lo = -1.0, hi = 1.0;
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (lo + hi);
+    latitude_G(q, ee, m, G, dG, d2G, e, ta);
+    if (G < target) lo = m;
+    else hi = m;
+  }
+  tab[i] = (float)(0.5 * (lo + hi));
+}
+
+// The seeding estimate's fine latitude table: the same root by the same
+// FP64 bisection, at the fine table's nodes.
+__global__ void lat_fine_kernel(float* __restrict__ tab, const double* __restrict__ ee) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kLatFNS * kLatFNT) return;
+  QueryDev q{};
+  q.S = exp(kLatFL0 + (double)(i / kLatFNT) * kLatFDL);
+  q.erfS = erf(q.S);
+  q.erfcS = erfc(q.S);
+  q.expmS2 = exp(-q.S * q.S);
+  q.lat_k = kSqrtPi / (4.0 * q.S);
+  const double t = (double)kLatFT0 + (double)(i % kLatFNT) * (double)kLatFDT;
   const double u = 1.0 / (1.0 + exp(-t));
   double Z, G, dG, d2G, e, ta;
   latitude_G(q, ee, 1.0, Z, dG, d2G, e, ta);
@@ -917,7 +944,7 @@ __global__ __launch_bounds__(kBlock) PROBE(__attribute__((amdgpu_waves_per_eu(ST
                 const uint64_t pid = base + lane;
                 const bool valid = pid < p_end;
                 bool maybe = valid;
-                if (valid && pc_on) maybe = precull_may_enter(q, g_lat_start, g_vn_start, nodes, pid);
+                if (valid && pc_on) maybe = precull_may_enter(q, g_lat_fine, g_vn_start, nodes, pid);
                 const uint64_t mb = ballot(maybe);
                 if (maybe) ring[wave][(s_head + s_count + below(mb)) & (kRing - 1)] =
                     (uint16_t)(pid - p_begin);
@@ -1265,7 +1292,7 @@ __global__ __launch_bounds__(kBlock) void precull_check_kernel(const QueryDev* _
   unsigned long long cnt = 0;
   for (uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x; pid < n; pid += (uint64_t)gridDim.x * kBlock) {
     float o[3], w[3];
-    if (!precull_estimate(q, g_lat_start, g_vn_start, pid, o, w)) continue;
+    if (!precull_estimate(q, g_lat_fine, g_vn_start, pid, o, w)) continue;
     double x[3], we[3];
     seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, pid, x, we);
     double dp = 0.0, nw = 0.0, ne = 0.0, dd = 0.0;
@@ -1313,10 +1340,12 @@ hipError_t probe_read(unsigned long long*, bool, hipStream_t) { return hipErrorN
 hipError_t init_seed_tables(hipStream_t st) {
   float* tab = nullptr;
   float* lat = nullptr;
+  float* fine = nullptr;
   double* sc = nullptr;
   double* ee = nullptr;
   hipError_t e = hipGetSymbolAddress((void**)&tab, HIP_SYMBOL(g_vn_start));
   if (e == hipSuccess) e = hipGetSymbolAddress((void**)&lat, HIP_SYMBOL(g_lat_start));
+  if (e == hipSuccess) e = hipGetSymbolAddress((void**)&fine, HIP_SYMBOL(g_lat_fine));
   if (e == hipSuccess) e = hipGetSymbolAddress((void**)&sc, HIP_SYMBOL(g_sc_tab));
   if (e == hipSuccess) e = hipGetSymbolAddress((void**)&ee, HIP_SYMBOL(g_ee_tab));
   if (e != hipSuccess) return e;
@@ -1324,6 +1353,7 @@ hipError_t init_seed_tables(hipStream_t st) {
   ee_table_kernel<<<(kExpErfcN + 255) / 256, 256, 0, st>>>(ee);  // before the solves that read it
   vn_table_kernel<<<(kVnNS * kVnNT + 255) / 256, 256, 0, st>>>(tab, ee);
   lat_table_kernel<<<(kLatNS * kLatNT + 255) / 256, 256, 0, st>>>(lat, ee);
+  lat_fine_kernel<<<(kLatFNS * kLatFNT + 255) / 256, 256, 0, st>>>(fine, ee);
   e = hipGetLastError();
   return e != hipSuccess ? e : hipStreamSynchronize(st);
 }

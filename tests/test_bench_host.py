@@ -27,7 +27,7 @@ def test_launch_record_work_model():
     V, T = 9.5, 3.25
     rec = B.launch_record("batch_kernel<16, 1> (test)", 2.0, res, V, T)
     particles, pre, segments, hits = 1500, 300, 2300, 950
-    ops = ((particles - pre) * 950.0 + pre * 565.0 + segments * (V * 40.0 + T * 45.0) - pre * 40.0
+    ops = ((particles - pre) * 950.0 + pre * 485.0 + segments * (V * 40.0 + T * 45.0) - pre * 40.0
            + hits * 225.0)
     assert rec["work"]["alg_lane_ops"] == pytest.approx(ops)
     assert rec["frac"] == pytest.approx(ops / 2e-3 / (256 * 64 * 2.4e9))

@@ -6,8 +6,11 @@ only the particles it does not rule out are seeded exactly and traced).
   case (tpmc_precull_check), the estimated ray stays within a hundredth of
   the margin of the exact one (Sec. III.A.1-3 in FP64) for every mesh, S
   from 0 to 30 and attitude, and the estimate covers nearly every particle
-  at S = 0 and for S inside the start tables (it leaves the others, and
-  0 < S < 0.25, to the exact seeding).
+  at S = 0 and for S inside its tables (it leaves the others, and
+  0 < S < 0.25, to the exact seeding).  Its latitude comes from a fine
+  table without iteration, so S midway between the table's rows is where it
+  errs most: swept across the table, it stays within a twentieth of the
+  margin.
 * The particles it removes are misses either way: batched results equal the
   plain path's bit for bit (every field but the work count), on flat, convex
   and concave bodies at grazing and head-on incidence; the plain path
@@ -53,6 +56,31 @@ def test_estimate_error_far_below_margin(ctx, T, kind):
             assert worst < 1e-2, (kind, S, k, worst)
             if S == 0.0 or 1.0 <= S <= 10.0:  # the estimate's range: S = 0 and S inside the start tables
                 assert covered >= 0.9 * n, (kind, S, k, covered)
+    mesh.close()
+
+
+def test_estimate_error_across_the_latitude_table(ctx, T):
+    """The estimate takes the latitude from a fine table as it is (cubic in
+    ln S between its rows, linear in the logit), so its error peaks where the
+    interpolation is poorest: midway between rows.  Over S at every fourth
+    row of the table and midway between rows (0.25 <= S <= 10), two attitudes
+    each, the estimated rays stay within a twentieth of the margin; the worst
+    over the same S at every row and half row, 2e4 particles each, measured
+    1.3e-2 of the margin."""
+    mesh = ctx.build_mesh(*MESHES["cylinder"]())
+    quats = I.random_quats(2, 5)
+    worst = (0.0, None)
+    k0 = math.ceil((math.log(0.25) + 1.45) / 0.01)
+    k1 = math.floor((math.log(10.0) + 1.45) / 0.01)
+    n = 10_000
+    for k in range(k0, k1 + 1, 4):
+        S = math.exp(-1.45 + 0.01 * k)  # odd k: midway between rows (kLatFDL = 0.02)
+        for a, qq in enumerate(quats):
+            w, covered = mesh.precull_check(I.query(q=tuple(qq), S=S, alpha=0.9, n=n, seed=7 + a))
+            assert covered >= 0.9 * n, (S, a, covered)
+            worst = max(worst, (w, (round(S, 4), a)))
+    print(f"largest error / margin {worst[0]:.3e} at S, attitude {worst[1]}", flush=True)
+    assert worst[0] < 5e-2, worst
     mesh.close()
 
 
