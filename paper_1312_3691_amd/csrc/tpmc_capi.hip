@@ -292,7 +292,7 @@ static void setup_query(const tpmc_query* in, const tpmc_mesh m, QueryDev* q) {
   }
   q->Sf = (float)q->S;
   q->rf = (float)q->r;
-  // the seeding estimate's fine latitude table: the four rows around ln S and
+  // the fine latitude table (seeding estimate, exact solve start): the four rows around ln S and
   // their cubic Lagrange weights (nodes -1, 0, 1, 2 around the row below ln S)
   q->lat_f0 = -1;
   for (int k = 0; k < 4; ++k) q->lat_fw[k] = 0.0f;

@@ -152,12 +152,36 @@ __device__ __forceinline__ T halley_step(T& x, T f, T df, T d2f, T& lo, T& hi) {
 // per device by FP64 bisection (lat_table_kernel); a bilinear start is within
 // 1e-3 of the root, so one FP32 step usually ends the approach.  Outside the
 // table the start is a blend of the S -> 0 law (uniform mu) and the S -> inf
-// law (density 2 mu).  It only chooses where the iteration starts.
+// law (density 2 mu).  It only chooses where the iteration starts, and only
+// where the fine table below does not reach (S < 0.25 or S > 10).
 constexpr int kLatNS = 107, kLatNT = 257;
 constexpr float kLatS0 = 0.05f, kLatDL = 0.05f, kLatT0 = -24.0f, kLatDT = 0.1875f;
 
-// The seeding estimate takes the same root from a fine table as it is, with
-// no iteration (layout kLatF* in tpmc_internal.h, filled by lat_fine_kernel).
+__device__ __forceinline__ float unif32_hi(uint32_t k) { return ((float)k + 0.5f) * 0x1p-32f; }  // ~unif64(k)
+
+// FP32 natural logarithm by the hardware log2 (starting points and the
+// seeding estimate only; the exact solves keep their own logarithm).
+__device__ __forceinline__ float hw_ln(float x) { return 0.69314718f * __builtin_amdgcn_logf(x); }
+
+// The same root from the fine table (layout kLatF* in tpmc_internal.h, filled
+// by lat_fine_kernel) at the draw u = ua, 1 - u = uam: the four rows and
+// cubic weights in ln S that the host set for the query (q.lat_f0 >= 0, i.e.
+// S in [0.25, 10]), linear in the logit.  Within 6e-6 of the root for every u
+// (a dense host evaluation against FP64 roots, poles included), so the exact
+// solve starts from it with no FP32 step, and the seeding estimate takes it as
+// it is.
+__device__ __forceinline__ float latitude_fine(const QueryDev& q, const float* __restrict__ tab, float ua,
+                                               float uam) {
+  const float t = hw_ln(ua) - hw_ln(uam);
+  const float ft = fminf(fmaxf((t - kLatFT0) * (1.0f / kLatFDT), 0.0f), (float)(kLatFNT - 1));
+  const int j = min((int)ft, kLatFNT - 2);
+  const float b = ft - (float)j;
+  const float* r = tab + q.lat_f0 * kLatFNT + j;
+  float m = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) m += q.lat_fw[k] * ((1.0f - b) * r[k * kLatFNT] + b * r[k * kLatFNT + 1]);
+  return fminf(fmaxf(m, -1.0f), 1.0f);
+}
 
 __device__ __forceinline__ float latitude_start(const float* __restrict__ tab, float S, double u) {
   const float fs = logf(S * (1.0f / kLatS0)) * (1.0f / kLatDL);
@@ -182,20 +206,28 @@ struct LatEval {
 };
 
 __device__ inline double sample_latitude(const QueryDev& q, const float* __restrict__ lat_tab,
-                                        const double* __restrict__ ee, double u, LatEval& le) {
+                                        const float* __restrict__ lat_fine, const double* __restrict__ ee,
+                                        uint32_t k, LatEval& le) {
+  const double u = unif64(k);
   le.valid = false;
   if (q.s_zero) return 2.0 * u - 1.0;  // S -> 0: g -> cos(phi)/2, mu uniform
   const double target = u * q.Z;
-  const LatConst32 c{(float)q.S, (float)q.erfS, (float)q.erfcS, (float)q.expmS2, q.S < 0.25};
-  float xf = fminf(fmaxf(latitude_start(lat_tab, c.S, u), -1.0f), 1.0f);
-  float lof = -1.0f, hif = 1.0f;
-  const float tf = (float)target;
+  float xf;
+  if (q.lat_f0 >= 0) {
+    // one FP64 step from here ends the solve (start error ~6e-6 < 1e-5)
+    xf = latitude_fine(q, lat_fine, unif32_hi(k), unif32_hi(~k));
+  } else {
+    const LatConst32 c{(float)q.S, (float)q.erfS, (float)q.erfcS, (float)q.expmS2, q.S < 0.25};
+    xf = fminf(fmaxf(latitude_start(lat_tab, c.S, u), -1.0f), 1.0f);
+    float lof = -1.0f, hif = 1.0f;
+    const float tf = (float)target;
 #pragma unroll 1
-  for (int it = 0; it < 5; ++it) {
-    float G, dG, d2G;
-    latitude_G32(c, xf, G, dG, d2G);
-    const float dx = halley_step(xf, G - tf, dG, d2G, lof, hif);
-    if (dx <= 1e-3f || hif - lof <= 1e-3f) break;
+    for (int it = 0; it < 5; ++it) {
+      float G, dG, d2G;
+      latitude_G32(c, xf, G, dG, d2G);
+      const float dx = halley_step(xf, G - tf, dG, d2G, lof, hif);
+      if (dx <= 1e-3f || hif - lof <= 1e-3f) break;
+    }
   }
   double x = (double)xf;
   double lo = -1.0, hi = 1.0;
@@ -375,7 +407,7 @@ __device__ inline double sample_normal_speed(const float* __restrict__ tab, cons
 // solve (the frame is expanded afterwards), which keeps the persistent kernel
 // inside its register budget.
 __device__ inline void seed_particle(const QueryDev& q, const float* __restrict__ lat_tab,
-                                     const float* __restrict__ vn_tab, const double* __restrict__ sc_tab,
+                                     const float* __restrict__ lat_fine, const float* __restrict__ vn_tab, const double* __restrict__ sc_tab,
                                      const double* __restrict__ ee, uint64_t pid, double x[3], double w[3]) {
   const U4 r0 = stream(q, pid, 0u);
   const U4 r1 = stream(q, pid, 1u);
@@ -394,7 +426,7 @@ __device__ inline void seed_particle(const QueryDev& q, const float* __restrict_
     k = normal_speed_consts(ee, q.face_s[f]);
   } else {
     LatEval le;
-    p0 = sample_latitude(q, lat_tab, ee, unif64(r0.a), le);
+    p0 = sample_latitude(q, lat_tab, lat_fine, ee, r0.a, le);
     p1 = sqrt(fmax(0.0, 1.0 - p0 * p0));
     sincos_2pi_draw(sc_tab, r0.b, p2, p3);  // of 2 pi unif64(r0.b)
     const double s_n = q.S * p0;
@@ -549,10 +581,6 @@ __device__ __forceinline__ bool slab(const Ray& r, float lox, float loy, float l
 // ---------------------------------------------------------------------------
 constexpr float kPrecullMargin = 0.02f;
 
-__device__ __forceinline__ float unif32_hi(uint32_t k) { return ((float)k + 0.5f) * 0x1p-32f; }  // ~unif64(k)
-
-// Estimate-only forms (FP32, hardware log2; the exact path keeps its own).
-__device__ __forceinline__ float hw_ln(float x) { return 0.69314718f * __builtin_amdgcn_logf(x); }
 
 // fs in [0, ns - 1], ft in [0, nt - 1]
 __device__ __forceinline__ float bilinear_start(const float* __restrict__ tab, int ns, int nt, float fs, float ft) {
@@ -581,15 +609,7 @@ __device__ inline bool precull_estimate(const QueryDev& q, const float* __restri
   } else {
     // from the fine table, inside its S range only (the host sets lat_f0 = -1 outside)
     if (q.lat_f0 < 0) return false;
-    const float t = hw_ln(ua) - hw_ln(uam);
-    const float ft = fminf(fmaxf((t - kLatFT0) * (1.0f / kLatFDT), 0.0f), (float)(kLatFNT - 1));
-    const int j = min((int)ft, kLatFNT - 2);
-    const float b = ft - (float)j;
-    const float* r = lat_tab + q.lat_f0 * kLatFNT + j;
-    float m = 0.0f;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) m += q.lat_fw[k] * ((1.0f - b) * r[k * kLatFNT] + b * r[k * kLatFNT + 1]);
-    mu = fminf(fmaxf(m, -1.0f), 1.0f);
+    mu = latitude_fine(q, lat_tab, ua, uam);
   }
   const float cphi = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
   ok = ok && cphi >= 0.05f;

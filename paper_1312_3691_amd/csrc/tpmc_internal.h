@@ -42,16 +42,17 @@ enum ProbeSlot {
   kProbeSlots = 24
 };
 
-// Fine table of the latitude root mu of G(mu) = u Z(S) for the seeding
-// estimate, which takes it as it is (no iteration): rows ln S = kLatFL0 +
+// Fine table of the latitude root mu of G(mu) = u Z(S): the seeding estimate
+// takes it as it is (no iteration), the exact FP64 solve starts from it (one
+// Halley step then ends the solve).  Rows ln S = kLatFL0 +
 // i kLatFDL (S from about 0.23 to 10.6), interpolated by the four-point
 // Lagrange cubic in ln S whose rows and weights the host sets per query
 // (QueryDev::lat_f0, lat_fw), columns t = kLatFT0 + j kLatFDT in the logit
 // t = ln(u / (1 - u)), linear.  Filled once per device by FP64 bisection.
-// Where cos(phi) >= 0.05 its error in mu is about 1e-5 (a dense host
-// evaluation of the interpolation against FP64 roots found at most 9e-6,
-// 3.5e-5 of cos(phi)); tpmc_precull_check measures the rays it gives against
-// the exact seeding.
+// Its error in mu is below 1e-5 (a dense host evaluation of the interpolation
+// against FP64 roots found at most 9e-6 where cos(phi) >= 0.05, 3.5e-5 of
+// cos(phi), and 5.5e-6 over draws from the whole range, poles included);
+// tpmc_precull_check measures the rays it gives against the exact seeding.
 constexpr int kLatFNS = 192, kLatFNT = 3073;
 constexpr double kLatFL0 = -1.45, kLatFDL = 0.02;
 constexpr float kLatFT0 = -24.0f, kLatFDT = 1.0f / 64.0f;
@@ -99,7 +100,7 @@ struct alignas(16) QueryDev {
   // FP32 copies for the seeding estimate of the pre-cull (precull_may_enter)
   float e1f[3], e2f[3];
   float Sf, rf;
-  int32_t lat_f0;     // first of the four fine-table rows around ln S (-1: the estimate gives up)
+  int32_t lat_f0;     // first of the four fine-table rows around ln S (-1: S outside the table)
   float lat_fw[4];    // their cubic Lagrange weights at ln S
 };
 

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void seed_kernel(const QueryDev* __restrict
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
     double x[3], w[3];
-    seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, i, x, w);
+    seed_particle(q, g_lat_start, g_lat_fine, g_vn_start, g_sc_tab, g_ee_tab, i, x, w);
     x0[i] = (float)x[0];
     x1[i] = (float)x[1];
     x2[i] = (float)x[2];
@@ -972,7 +972,7 @@ __global__ __launch_bounds__(kBlock) PROBE(__attribute__((amdgpu_waves_per_eu(ST
             float xs[3], ws[3];
             if ((uint32_t)lane < n) {
               double x[3], w[3];
-              seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab,
+              seed_particle(q, g_lat_start, g_lat_fine, g_vn_start, g_sc_tab, g_ee_tab,
                             p_begin + ring[wave][(s_head + lane) & (kRing - 1)], x, w);
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
@@ -1021,7 +1021,7 @@ __global__ __launch_bounds__(kBlock) PROBE(__attribute__((amdgpu_waves_per_eu(ST
               float xs[3], ws[3];
               if (pid < p_end) {
                 double x[3], w[3];
-                seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, pid, x, w);
+                seed_particle(q, g_lat_start, g_lat_fine, g_vn_start, g_sc_tab, g_ee_tab, pid, x, w);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                   xs[c] = (float)x[c];
@@ -1294,7 +1294,7 @@ __global__ __launch_bounds__(kBlock) void precull_check_kernel(const QueryDev* _
     float o[3], w[3];
     if (!precull_estimate(q, g_lat_fine, g_vn_start, pid, o, w)) continue;
     double x[3], we[3];
-    seed_particle(q, g_lat_start, g_vn_start, g_sc_tab, g_ee_tab, pid, x, we);
+    seed_particle(q, g_lat_start, g_lat_fine, g_vn_start, g_sc_tab, g_ee_tab, pid, x, we);
     double dp = 0.0, nw = 0.0, ne = 0.0, dd = 0.0;
     for (int c = 0; c < 3; ++c) {
       dp += ((double)o[c] - x[c]) * ((double)o[c] - x[c]);
