@@ -64,6 +64,11 @@ SEED_CASES = [
     dict(S=2.0, q=tuple(I.random_quats(1, 5)[0]), cv_radius=0.0, n=10007),
     dict(S=10.0, q=tuple(I.random_quats(1, 6)[0]), cv_radius=1.2, n=10007),
     dict(S=30.0, q=I.quat_for_flow((0, 0, -1.0)), cv_radius=0.0, n=4099),
+    # the latitude solve's starts: S below the fine table (coarse table and an
+    # FP32 approach with erf), where the fine table errs most, and above it
+    dict(S=0.1, q=tuple(I.random_quats(1, 7)[0]), cv_radius=1.1, n=10007),
+    dict(S=0.81, q=tuple(I.random_quats(1, 8)[0]), cv_radius=0.0, n=10007),
+    dict(S=12.0, q=tuple(I.random_quats(1, 9)[0]), cv_radius=0.0, n=10007),
 ]
 
 
